@@ -1,0 +1,190 @@
+/*
+ * mfa.h - C ABI of the MI355X multivariate functional approximation encoder.
+ *
+ * The library fits a tensor-product B-spline (degree p, clamped uniform knots,
+ * all weights W = 1) to data on a regular 1-D, 2-D or 3-D grid with the
+ * overlapping additive-Schwarz domain decomposition of Mahadevan, Lenz,
+ * Grindeanu and Peterka (arXiv 2210.06528): the control grid is split into
+ * axis-aligned subdomains that overlap by `overlap` control points (the
+ * shared spans Delta plus the augmented spans delta of Section 2.2); every
+ * sweep solves each subdomain's local least-squares problem (eq.
+ * minimization-problem) with its neighbours' control points lagged (the
+ * block-Jacobi reading of eq. global-system), and the local solutions are
+ * combined with the uniform weights 1/n_s of Section 2.3.2 (Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grids are C-ordered, last axis contiguous.  Data point i of an axis with
+ *    m points sits at parameter u = i/(m-1).  Control point arrays have shape
+ *    nctrl[0] x ... x nctrl[dim-1].
+ *  - Pointers named *_dev are HIP device pointers on the device that was
+ *    current when mfa_create ran; pointers named *_host are host memory.
+ *  - All work is enqueued on the HIP stream given to mfa_create.  Calls return
+ *    when the work is enqueued unless stated otherwise; mfa_create,
+ *    mfa_encode (to read the convergence metrics) and mfa_schwarz_step (to
+ *    fill its statistics) synchronise the stream before returning.
+ *  - The caller owns every buffer passed in, including the workspace; the
+ *    library never allocates device memory.  It must outlive the handle.
+ *  - Errors: every entry point returns an mfa_status; on failure
+ *    mfa_last_error() returns a message for the calling thread.  No C++
+ *    exception crosses the ABI.  Calls on one handle must not overlap.
+ */
+#ifndef MFA_H
+#define MFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfa_handle mfa_handle;
+
+typedef enum {
+  MFA_OK = 0,
+  MFA_EINVAL = -1,    /* invalid argument or problem (message says which)      */
+  MFA_ENOMEM = -2,    /* workspace smaller than mfa_workspace_size reported    */
+  MFA_EDEVICE = -3,   /* a HIP runtime call failed                             */
+  MFA_ENOTCONV = -4,  /* max_sweeps reached with jumps above jump_tol, or NaN  */
+  MFA_ESINGULAR = -5  /* a local normal matrix is not positive definite:       */
+                      /* some basis function has no data point in its support */
+} mfa_status;
+
+typedef enum { MFA_F32 = 0, MFA_F64 = 1 } mfa_dtype;
+
+/* Arithmetic of the sweep.  FP64: everything in float64.  MIXED_*: the
+ * residual of the normal equations, the control points and the Cholesky
+ * factors stay float64, the Schwarz correction is applied in lower precision
+ * and the sweep acts as iterative refinement on the float64 residual.      */
+typedef enum {
+  MFA_PREC_FP64 = 0,
+  MFA_PREC_MIXED_FP32 = 1,
+  MFA_PREC_MIXED_BF16 = 2
+} mfa_precision;
+
+/* Combine of the local solutions.  AVG: uniform weights 1/n_s over every
+ * subdomain whose free set holds the control point (Section 2.3.2).  RAS:
+ * restricted, each control point takes its owning subdomain's value.       */
+typedef enum { MFA_COMBINE_AVG = 0, MFA_COMBINE_RAS = 1 } mfa_combine;
+
+/* How a sweep forms each subdomain's local right-hand side.
+ * NORMAL: from c = N^T Q (computed once per input) minus N^T N P, which
+ *         equals the local N_F^T (Q - N P) exactly; Q is read once per encode.
+ * DATABOX: decode on every subdomain's data box and form N_F^T (Q - N P)
+ *         from the point residual every sweep, as Algorithm 1 is written.  */
+typedef enum { MFA_RHS_NORMAL = 0, MFA_RHS_DATABOX = 1 } mfa_rhs;
+
+typedef struct {
+  int32_t dim;               /* 1, 2 or 3                                           */
+  int64_t npts[3];           /* data points per axis (>= nctrl on that axis)        */
+  int32_t degree;            /* p >= 1, the same on every axis (Algorithm 1's p)    */
+  int32_t nsub[3];           /* subdomains per axis (the paper's N per axis)        */
+  const int32_t *nctrl[3];   /* host arrays: owned control points of each
+                                subdomain along each axis, length nsub[a]; they
+                                sum to the axis' control count (uneven allowed)   */
+  int32_t overlap;           /* control points added to each interior side of a
+                                subdomain's free set (|Delta| + |delta|);
+                                must be >= max(1, floor(p/2)) when nsub[a] > 1     */
+  int32_t precision;         /* mfa_precision                                      */
+  int32_t combine;           /* mfa_combine                                        */
+  int32_t rhs;               /* mfa_rhs                                            */
+} mfa_problem;
+
+#define MFA_MAX_DEGREE 8
+
+typedef struct {
+  int32_t sweep;                  /* sweeps done since the last mfa_encode start     */
+  int32_t converged;              /* 1 if max_r jump[r] < jump_tol                   */
+  double jump[MFA_MAX_DEGREE];    /* normalised interface jumps J_r, r = 0..p-1
+                                     (eq. nonlinear-residuals; max over axes and
+                                     interfaces of |d^r (L_i - L_j)/du^r| on the
+                                     interface, divided by max(S_r, S_0), S_r the
+                                     largest r-th derivative control coefficient of
+                                     the consensus and S_0 = max |P|)               */
+  double max_dP;                  /* max |P_new - P| of the last sweep               */
+  double nres_max;                /* max |N^T Q - N^T N P| before the last sweep     */
+  double ctrl_max;                /* S_0 = max |P| after the last sweep              */
+} mfa_step_stats;
+
+/* Bytes of device workspace mfa_create needs for this problem.
+ * Validates the problem; MFA_EINVAL names the first violated rule:
+ * dim not in 1..3, p < 1 or > MFA_MAX_DEGREE, an axis with fewer points than
+ * control points, overlap below max(1, floor(p/2)) on a split axis (the
+ * floor(p/2) shared spans needed for partition of unity, Section 2.2), an
+ * owned block smaller than max(p+1, 2*overlap) on a split axis, a null
+ * pointer, or a precision/combine/rhs value out of range.                  */
+mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes);
+
+/* Plan the subdomains (Section 2.2), evaluate the Cox-de Boor basis at every
+ * data point (Section 2.1), assemble the banded per-axis normal matrices
+ * N_a^T N_a with wavefront reductions, factor every subdomain's local normal
+ * matrix with a batched banded Cholesky (Section 2.3.1) and build the
+ * per-axis Schwarz operators; everything runs on `hip_stream` (a hipStream_t,
+ * or NULL for the default stream).  `workspace` is a device buffer of at
+ * least mfa_workspace_size bytes, 256-byte aligned.  Synchronises the stream.
+ * Returns MFA_ESINGULAR when a local normal matrix is not positive definite.
+ * On success *out owns no memory but the small host-side handle.           */
+mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes,
+                      void *hip_stream, mfa_handle **out);
+
+/* Algorithm 1 on the data q_dev (npts[0] x ... float32 or float64 device
+ * array): start from the control points set by mfa_set_ctrl, else from zero
+ * (the first sweep is then the decoupled local fit), and sweep until
+ * max_r J_r < jump_tol, checking every `check_every` sweeps (>= 1), or until
+ * max_sweeps.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
+ * NULL) receives the statistics of the last checked sweep.  Returns
+ * MFA_ENOTCONV if the tolerance was not met (the control points are still
+ * the last iterate) or a non-finite value appeared.                         */
+mfa_status mfa_encode(mfa_handle *h, const void *q_dev, mfa_dtype q_dtype,
+                      int32_t max_sweeps, double jump_tol, int32_t check_every,
+                      mfa_step_stats *last);
+
+/* One sweep of Algorithm 1 from the current control points.  q_dev as in
+ * mfa_encode; q_dev == NULL reuses the data of the previous call on this
+ * handle.  Fills *out (may be NULL) including the jumps.  Synchronises.     */
+mfa_status mfa_schwarz_step(mfa_handle *h, const void *q_dev, mfa_dtype q_dtype,
+                            mfa_step_stats *out);
+
+/* Evaluate the consensus spline (or, with deriv != NULL, the mixed partial
+ * derivative of orders deriv[0..dim-1] with respect to the parameters u_a,
+ * each <= p) at every grid point into out_dev (npts[0] x ... of out_dtype).
+ * This is the decode of Section 2.1 (eq. nurbs-basis).                      */
+mfa_status mfa_decode(mfa_handle *h, void *out_dev, mfa_dtype out_dtype,
+                      const int32_t *deriv);
+
+/* Copy the control points (float64, nctrl[0] x ...) out of / into the handle
+ * ("write MFA to disk" of Algorithm 1; set_ctrl is a warm start or refit).
+ * on_device != 0: the pointer is a device pointer; otherwise host memory
+ * (the copy then completes before the call returns).                       */
+mfa_status mfa_get_ctrl(mfa_handle *h, double *ctrl, int32_t on_device);
+mfa_status mfa_set_ctrl(mfa_handle *h, const double *ctrl, int32_t on_device);
+
+/* Copy an intermediate table into host memory for inspection (tests):
+ *  MFA_T_BASIS   basis values, axis `axis`: npts x (p+1), row i holds
+ *                N_{s-p..s}(u_i) with s the span of u_i (Section 2.1)
+ *  MFA_T_SPAN    spans as float64, npts values
+ *  MFA_T_GRAM    lower band of N_a^T N_a: (p+1) x nctrl, band[t][k] = A[k+t][k]
+ *  MFA_T_CHOL    banded Cholesky factor of subdomain `block` on axis `axis`,
+ *                lower band (p+1) x |F|
+ *  MFA_T_INV     inverse of that local normal matrix, |F| x |F| row-major
+ *  MFA_T_RHS     N^T Q of the last input, float64 control array
+ * `count` is the capacity of host_out in doubles; the needed count is
+ * written to *needed (may be NULL).  Synchronises the stream.              */
+typedef enum {
+  MFA_T_BASIS = 0, MFA_T_SPAN = 1, MFA_T_GRAM = 2, MFA_T_CHOL = 3,
+  MFA_T_INV = 4, MFA_T_RHS = 5
+} mfa_table;
+mfa_status mfa_inspect(mfa_handle *h, int32_t table, int32_t axis, int32_t block,
+                       double *host_out, size_t count, size_t *needed);
+
+/* Release the handle (not the caller-owned workspace).  NULL is ignored.   */
+void mfa_destroy(mfa_handle *h);
+
+/* Message describing the last failure on the calling thread ("" if none).  */
+const char *mfa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFA_H */

@@ -1,0 +1,430 @@
+// C ABI of the MFA encoder: handle lifecycle, Schwarz sweeps, encode loop,
+// decode and inspection.  See include/mfa.h for the contract of each call.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mfa_internal.hpp"
+
+using namespace mfa;
+
+struct mfa_handle {
+  Handle h;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mfa_status fail(mfa_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+mfa_status hip_fail(hipError_t e, const char *where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return MFA_EDEVICE;
+}
+
+#define HIP_CHECK(x, where)                  \
+  do {                                       \
+    hipError_t e_ = (x);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+Dims ctrl_dims(const Handle &h) { return Dims{{h.ax[0].n, h.ax[1].n, h.ax[2].n}}; }
+Dims data_dims(const Handle &h) { return Dims{{h.ax[0].m, h.ax[1].m, h.ax[2].m}}; }
+
+struct Step {
+  int ax;
+  const Ell *op;
+};
+
+// Apply `steps` in order starting from `in` (dims `d`); intermediates
+// alternate between the two scratch buffers; the last step uses `epi` and
+// writes `out` (or only reduces).
+template <typename Tin, typename Tout>
+hipError_t run_chain(Handle &h, const Tin *in, Dims d, const std::vector<Step> &steps, Tout *out,
+                     int epi, const double *sub, int slot_base, const int *gid, int gaxis,
+                     double *bufA, double *bufB) {
+  if (steps.empty()) return hipSuccess;
+  if (steps.size() == 1)
+    return launch_pass<Tin, Tout>(h.stream, in, d, steps[0].ax, *steps[0].op, out, epi, sub, h.slots,
+                                  slot_base, gid, gaxis);
+  double *bufs[2] = {bufA, bufB};
+  int w = 0;
+  hipError_t e = launch_pass<Tin, double>(h.stream, in, d, steps[0].ax, *steps[0].op, bufs[w],
+                                          EPI_STORE, nullptr, h.slots, 0, nullptr, 0);
+  if (e != hipSuccess) return e;
+  d.d[steps[0].ax] = steps[0].op->R;
+  for (size_t s = 1; s + 1 < steps.size(); ++s) {
+    e = launch_pass<double, double>(h.stream, bufs[w], d, steps[s].ax, *steps[s].op, bufs[w ^ 1],
+                                    EPI_STORE, nullptr, h.slots, 0, nullptr, 0);
+    if (e != hipSuccess) return e;
+    d.d[steps[s].ax] = steps[s].op->R;
+    w ^= 1;
+  }
+  return launch_pass<double, Tout>(h.stream, bufs[w], d, steps.back().ax, *steps.back().op, out, epi,
+                                   sub, h.slots, slot_base, gid, gaxis);
+}
+
+// c = N^T Q (every active axis, innermost first)
+template <typename T>
+hipError_t project(Handle &h, const T *q) {
+  std::vector<Step> st;
+  for (int a = 2; a >= 0; --a)
+    if (h.ax[a].active) st.push_back({a, &h.ax[a].NT});
+  return run_chain<T, double>(h, q, data_dims(h), st, h.c, EPI_STORE, nullptr, 0, nullptr, 0, h.s1,
+                              h.s2);
+}
+
+// One sweep (NORMAL right-hand side):
+//   g = c - (A_0 x A_1 x A_2) P      (the local residuals N_F^T (Q - N P) of all
+//                                     subdomains at once)
+//   P += (M_0 x M_1 x M_2) g         (local solves with lagged ghosts and the
+//                                     1/n_s combine, Section 2.3.2)
+hipError_t sweep_normal(Handle &h) {
+  std::vector<Step> st;
+  for (int a = 2; a >= 0; --a)
+    if (h.ax[a].active) st.push_back({a, &h.ax[a].A});
+  hipError_t e = run_chain<double, double>(h, h.P, ctrl_dims(h), st, h.g, EPI_SUBFROM, h.c,
+                                           kSlotNres, nullptr, 0, h.s1, h.s2);
+  if (e != hipSuccess) return e;
+  st.clear();
+  for (int a = 0; a < 3; ++a)
+    if (h.ax[a].active) st.push_back({a, &h.ax[a].M});
+  return run_chain<double, double>(h, h.g, ctrl_dims(h), st, h.P, EPI_ADDTO, nullptr, kSlotMaxDP,
+                                   nullptr, 0, h.s1, h.s2);
+}
+
+// Jump and scale reductions of the sweep just done (g still holds the
+// residual the sweep used; P holds the new consensus).
+hipError_t sweep_metrics(Handle &h) {
+  for (int a = 0; a < 3; ++a) {
+    if (!h.ax[a].active || h.ax[a].B < 2) continue;
+    std::vector<Step> st{{a, &h.ax[a].J}};
+    for (int c = 0; c < 3; ++c)
+      if (c != a && h.ax[c].active) st.push_back({c, &h.ax[c].Om});
+    hipError_t e = run_chain<double, double>(h, h.g, ctrl_dims(h), st, (double *)nullptr, EPI_MAXABS,
+                                             nullptr, kSlotJ + a * kMaxP, h.ax[a].d_gidJ, a, h.s1,
+                                             h.s2);
+    if (e != hipSuccess) return e;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!h.ax[a].active) continue;
+    hipError_t e = launch_pass<double, double>(h.stream, h.P, ctrl_dims(h), a, h.ax[a].D, nullptr,
+                                               EPI_MAXABS, nullptr, h.slots, kSlotS + a * kMaxP,
+                                               h.ax[a].d_gidD, a);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+mfa_status read_stats(Handle &h, mfa_step_stats *out, double jump_tol, bool *finite) {
+  unsigned long long raw[kNumSlots];
+  HIP_CHECK(hipMemcpyAsync(raw, h.slots, sizeof(raw), hipMemcpyDeviceToHost, h.stream), "read stats");
+  HIP_CHECK(hipStreamSynchronize(h.stream), "read stats");
+  auto val = [&](int s) {
+    double d;
+    std::memcpy(&d, &raw[s], sizeof(d));
+    return d;
+  };
+  mfa_step_stats st{};
+  st.sweep = h.sweep;
+  st.max_dP = val(kSlotMaxDP);
+  st.nres_max = val(kSlotNres);
+  double s0 = 0.0;
+  for (int a = 0; a < 3; ++a)
+    if (h.ax[a].active) s0 = std::max(s0, val(kSlotS + a * kMaxP));
+  st.ctrl_max = s0;
+  bool fin = std::isfinite(st.max_dP) && std::isfinite(st.nres_max) && std::isfinite(s0);
+  double jmax = 0.0;
+  for (int r = 0; r < h.p; ++r) {
+    double jr = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      if (!h.ax[a].active || h.ax[a].B < 2) continue;
+      const double raw_j = val(kSlotJ + a * kMaxP + r);
+      const double sr = std::max(val(kSlotS + a * kMaxP + r), s0);
+      if (!std::isfinite(raw_j)) fin = false;
+      jr = std::max(jr, sr > 0.0 ? raw_j / sr : 0.0);
+    }
+    st.jump[r] = jr;
+    jmax = std::max(jmax, jr);
+  }
+  st.converged = (jump_tol > 0.0 && jmax < jump_tol) ? 1 : 0;
+  if (out) *out = st;
+  *finite = fin;
+  return MFA_OK;
+}
+
+bool valid_handle(const mfa_handle *h) { return h != nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+const char *mfa_last_error(void) { return g_last_error.c_str(); }
+
+mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes) {
+  if (!prob || !bytes) return fail(MFA_EINVAL, "null pointer");
+  Handle tmp;
+  std::string msg = plan_problem(*prob, &tmp);
+  if (!msg.empty()) return fail(MFA_EINVAL, msg);
+  *bytes = layout_workspace(&tmp, nullptr);
+  return MFA_OK;
+}
+
+mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, void *hip_stream,
+                      mfa_handle **out) {
+  if (!prob || !out) return fail(MFA_EINVAL, "null pointer");
+  *out = nullptr;
+  if (!workspace) return fail(MFA_EINVAL, "null workspace");
+  if (((uintptr_t)workspace & 255) != 0) return fail(MFA_EINVAL, "workspace not 256-byte aligned");
+  mfa_handle *H = new (std::nothrow) mfa_handle();
+  if (!H) return fail(MFA_ENOMEM, "host allocation failed");
+  Handle &h = H->h;
+  std::string msg = plan_problem(*prob, &h);
+  if (!msg.empty()) {
+    delete H;
+    return fail(MFA_EINVAL, msg);
+  }
+  const size_t need = layout_workspace(&h, nullptr);
+  if (bytes < need) {
+    delete H;
+    return fail(MFA_ENOMEM, "workspace smaller than mfa_workspace_size");
+  }
+  h.ws = (char *)workspace;
+  h.ws_bytes = bytes;
+  layout_workspace(&h, h.ws);
+  h.stream = (hipStream_t)hip_stream;
+  hipError_t e = hipGetDevice(&h.device);
+  if (e != hipSuccess) {
+    delete H;
+    return hip_fail(e, "hipGetDevice");
+  }
+  auto bail = [&](hipError_t err, const char *where) {
+    delete H;
+    return hip_fail(err, where);
+  };
+  if ((e = launch_zero_slots(h.stream, (unsigned long long *)h.flag, 2)) != hipSuccess)
+    return bail(e, "zero flag");
+  if ((e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0)) != hipSuccess) return bail(e, "fill P");
+  for (int a = 0; a < 3; ++a) {
+    if (!h.ax[a].active) continue;
+    if ((e = setup_axis(&h, a)) != hipSuccess) return bail(e, "setup");
+  }
+  int flag = 0;
+  if ((e = hipMemcpyAsync(&flag, h.flag, sizeof(int), hipMemcpyDeviceToHost, h.stream)) != hipSuccess)
+    return bail(e, "read flag");
+  if ((e = hipStreamSynchronize(h.stream)) != hipSuccess) return bail(e, "setup sync");
+  if (flag) {
+    delete H;
+    return fail(MFA_ESINGULAR,
+                "a local normal matrix is not positive definite (a basis function without data)");
+  }
+  *out = H;
+  return MFA_OK;
+}
+
+void mfa_destroy(mfa_handle *h) { delete h; }
+
+static mfa_status load_q(Handle &h, const void *q, mfa_dtype dt) {
+  if (dt != MFA_F32 && dt != MFA_F64) return fail(MFA_EINVAL, "bad dtype");
+  hipError_t e = dt == MFA_F32 ? project<float>(h, (const float *)q) : project<double>(h, (const double *)q);
+  if (e != hipSuccess) return hip_fail(e, "project");
+  h.have_rhs = true;
+  return MFA_OK;
+}
+
+static mfa_status do_sweep(Handle &h, bool metrics) {
+  hipError_t e = launch_zero_slots(h.stream, h.slots, kNumSlots);
+  if (e != hipSuccess) return hip_fail(e, "zero slots");
+  e = sweep_normal(h);
+  if (e != hipSuccess) return hip_fail(e, "sweep");
+  if (metrics) {
+    e = sweep_metrics(h);
+    if (e != hipSuccess) return hip_fail(e, "metrics");
+  }
+  h.sweep++;
+  return MFA_OK;
+}
+
+mfa_status mfa_schwarz_step(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, mfa_step_stats *out) {
+  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  Handle &h = H->h;
+  hipSetDevice(h.device);
+  if (q_dev) {
+    mfa_status s = load_q(h, q_dev, q_dtype);
+    if (s != MFA_OK) return s;
+  } else if (!h.have_rhs) {
+    return fail(MFA_EINVAL, "no data loaded: pass q_dev");
+  }
+  mfa_status s = do_sweep(h, true);
+  if (s != MFA_OK) return s;
+  bool finite = true;
+  s = read_stats(h, out, 0.0, &finite);
+  if (s != MFA_OK) return s;
+  if (!finite) return fail(MFA_ENOTCONV, "non-finite value in the sweep");
+  return MFA_OK;
+}
+
+mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32_t max_sweeps,
+                      double jump_tol, int32_t check_every, mfa_step_stats *last) {
+  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  if (!q_dev) return fail(MFA_EINVAL, "null data pointer");
+  if (max_sweeps < 1) return fail(MFA_EINVAL, "max_sweeps must be >= 1");
+  if (check_every < 1) return fail(MFA_EINVAL, "check_every must be >= 1");
+  Handle &h = H->h;
+  hipSetDevice(h.device);
+  mfa_status s = load_q(h, q_dev, q_dtype);
+  if (s != MFA_OK) return s;
+  h.sweep = 0;
+  if (!h.warm) {
+    hipError_t e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0);
+    if (e != hipSuccess) return hip_fail(e, "fill P");
+  }
+  h.warm = false;
+  mfa_step_stats st{};
+  bool converged = false;
+  for (int k = 1; k <= max_sweeps; ++k) {
+    const bool check = (jump_tol > 0.0 && k % check_every == 0) || k == max_sweeps;
+    s = do_sweep(h, check);
+    if (s != MFA_OK) return s;
+    if (check) {
+      bool finite = true;
+      s = read_stats(h, &st, jump_tol, &finite);
+      if (s != MFA_OK) return s;
+      if (!finite) {
+        if (last) *last = st;
+        return fail(MFA_ENOTCONV, "non-finite value in the sweep");
+      }
+      if (st.converged) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  if (last) *last = st;
+  if (jump_tol > 0.0 && !converged) return fail(MFA_ENOTCONV, "jump tolerance not reached");
+  return MFA_OK;
+}
+
+mfa_status mfa_decode(mfa_handle *H, void *out_dev, mfa_dtype out_dtype, const int32_t *deriv) {
+  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  if (!out_dev) return fail(MFA_EINVAL, "null output pointer");
+  Handle &h = H->h;
+  hipSetDevice(h.device);
+  std::vector<Step> st;
+  for (int a = 2; a >= 0; --a) {
+    if (!h.ax[a].active) continue;
+    int r = 0;
+    if (deriv) r = deriv[a - (3 - h.dim)];
+    if (r < 0 || r > h.p) return fail(MFA_EINVAL, "derivative order out of range");
+    st.push_back({a, &h.ax[a].N[r]});
+  }
+  hipError_t e;
+  if (out_dtype == MFA_F32)
+    e = run_chain<double, float>(h, h.P, ctrl_dims(h), st, (float *)out_dev, EPI_STORE, nullptr, 0,
+                                 nullptr, 0, h.s1, h.s2);
+  else if (out_dtype == MFA_F64)
+    e = run_chain<double, double>(h, h.P, ctrl_dims(h), st, (double *)out_dev, EPI_STORE, nullptr, 0,
+                                  nullptr, 0, h.s1, h.s2);
+  else
+    return fail(MFA_EINVAL, "bad dtype");
+  if (e != hipSuccess) return hip_fail(e, "decode");
+  return MFA_OK;
+}
+
+mfa_status mfa_get_ctrl(mfa_handle *H, double *ctrl, int32_t on_device) {
+  if (!valid_handle(H) || !ctrl) return fail(MFA_EINVAL, "null pointer");
+  Handle &h = H->h;
+  hipSetDevice(h.device);
+  const size_t bytes = sizeof(double) * (size_t)h.nctrl_total;
+  HIP_CHECK(hipMemcpyAsync(ctrl, h.P, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           h.stream),
+            "get_ctrl");
+  if (!on_device) HIP_CHECK(hipStreamSynchronize(h.stream), "get_ctrl");
+  return MFA_OK;
+}
+
+mfa_status mfa_set_ctrl(mfa_handle *H, const double *ctrl, int32_t on_device) {
+  if (!valid_handle(H) || !ctrl) return fail(MFA_EINVAL, "null pointer");
+  Handle &h = H->h;
+  hipSetDevice(h.device);
+  const size_t bytes = sizeof(double) * (size_t)h.nctrl_total;
+  HIP_CHECK(hipMemcpyAsync(h.P, ctrl, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           h.stream),
+            "set_ctrl");
+  if (!on_device) HIP_CHECK(hipStreamSynchronize(h.stream), "set_ctrl");
+  h.warm = true;
+  return MFA_OK;
+}
+
+mfa_status mfa_inspect(mfa_handle *H, int32_t table, int32_t axis, int32_t block, double *host_out,
+                       size_t count, size_t *needed) {
+  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  Handle &h = H->h;
+  hipSetDevice(h.device);
+  if (table != MFA_T_RHS && (axis < 0 || axis >= h.dim)) return fail(MFA_EINVAL, "axis out of range");
+  const Axis &X = h.ax[table == MFA_T_RHS ? 0 : axis + 3 - h.dim];
+  if ((table == MFA_T_CHOL || table == MFA_T_INV) && (block < 0 || block >= X.B))
+    return fail(MFA_EINVAL, "block out of range");
+  const int p = h.p;
+  std::vector<double> buf;
+  switch (table) {
+    case MFA_T_BASIS: {
+      buf.resize((size_t)X.m * (p + 1));
+      HIP_CHECK(hipMemcpyAsync(buf.data(), X.N[0].val, sizeof(double) * buf.size(), hipMemcpyDeviceToHost,
+                               h.stream), "inspect");
+      break;
+    }
+    case MFA_T_SPAN: {
+      std::vector<int> s(X.m);
+      HIP_CHECK(hipMemcpyAsync(s.data(), X.d_span, sizeof(int) * s.size(), hipMemcpyDeviceToHost, h.stream),
+                "inspect");
+      HIP_CHECK(hipStreamSynchronize(h.stream), "inspect");
+      buf.assign(s.begin(), s.end());
+      break;
+    }
+    case MFA_T_GRAM: {
+      buf.resize((size_t)(p + 1) * X.n);
+      HIP_CHECK(hipMemcpyAsync(buf.data(), X.d_gram, sizeof(double) * buf.size(), hipMemcpyDeviceToHost,
+                               h.stream), "inspect");
+      break;
+    }
+    case MFA_T_CHOL: {
+      const int64_t F = X.blk[block].F1 - X.blk[block].F0;
+      buf.resize((size_t)(p + 1) * F);
+      HIP_CHECK(hipMemcpyAsync(buf.data(), X.d_chol + X.chol_off[block], sizeof(double) * buf.size(),
+                               hipMemcpyDeviceToHost, h.stream), "inspect");
+      break;
+    }
+    case MFA_T_INV: {
+      const int64_t F = X.blk[block].F1 - X.blk[block].F0;
+      buf.resize((size_t)F * F);
+      HIP_CHECK(hipMemcpyAsync(buf.data(), X.d_inv + X.inv_off[block], sizeof(double) * buf.size(),
+                               hipMemcpyDeviceToHost, h.stream), "inspect");
+      break;
+    }
+    case MFA_T_RHS: {
+      if (!h.have_rhs) return fail(MFA_EINVAL, "no data loaded");
+      buf.resize((size_t)h.nctrl_total);
+      HIP_CHECK(hipMemcpyAsync(buf.data(), h.c, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, h.stream),
+                "inspect");
+      break;
+    }
+    default:
+      return fail(MFA_EINVAL, "unknown table");
+  }
+  HIP_CHECK(hipStreamSynchronize(h.stream), "inspect");
+  if (needed) *needed = buf.size();
+  if (host_out) {
+    if (count < buf.size()) return fail(MFA_EINVAL, "output buffer too small");
+    std::memcpy(host_out, buf.data(), sizeof(double) * buf.size());
+  }
+  return MFA_OK;
+}
+
+}  // extern "C"

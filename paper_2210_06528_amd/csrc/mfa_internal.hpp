@@ -1,0 +1,145 @@
+// Internal declarations of the MFA library (host planner, device tables,
+// kernel launchers).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mfa.h"
+
+namespace mfa {
+
+constexpr int kMaxP = MFA_MAX_DEGREE;
+
+// Row-sparse operator along one axis in ELL layout: row r has len[r] <= L
+// nonzeros at columns col[r*L + t] with values val[r*L + t].
+struct Ell {
+  int R = 0;        // rows (output length along the axis)
+  int C = 0;        // columns (input length along the axis)
+  int L = 0;        // max nonzeros per row
+  int *len = nullptr;
+  int *col = nullptr;
+  double *val = nullptr;
+  float *valf = nullptr;   // float copy (mixed precision), may be null
+};
+
+// Index ranges of one subdomain along one axis (Section 2.2).
+struct Block {
+  int c0, c1;          // owned control points [c0, c1)
+  int F0, F1;          // free set: owned plus `overlap` on interior sides
+  int E0, E1;          // free set plus the p ghost control points per side
+  int64_t D0, D1;      // data points in the support of the free set
+  int64_t own0, own1;  // owned data points (a partition of the axis)
+};
+
+// Plan and device tables of one axis.  Axes are stored innermost-last as
+// internal axes 0..2; a problem of dimension d uses internal axes 3-d..2 and
+// the others have length 1 and no operators.
+struct Axis {
+  bool active = false;
+  int64_t m = 1;        // data points
+  int n = 1;            // control points
+  int B = 1;            // subdomains
+  std::vector<Block> blk;
+  std::vector<int> ns;            // subdomains whose free set holds each ctrl
+  std::vector<int> blo, bhi;      // first / last block whose free set holds ctrl k
+  std::vector<int> owner;         // block owning ctrl k
+  std::vector<int> pown;          // block owning data point i
+  std::vector<double> ustar;      // interface parameters (B-1)
+  std::vector<int> span_if;       // span of each interface parameter
+  int64_t LNT = 0, LM = 0, LOm = 0, LJ = 0;
+  int64_t Fmax = 0;
+  std::vector<int64_t> chol_off, inv_off;   // per-block offsets (doubles)
+  int64_t chol_total = 0, inv_total = 0;
+  int64_t ND = 0;                            // rows of the derivative-coefficient table
+  // DATABOX segmented layouts
+  int64_t SD = 0, SF = 0;                    // sum of |D_b| and of |F_b|
+  std::vector<int64_t> doff, foff;           // segment offsets per block
+  int64_t LNsT = 0;
+
+  // device pointers (inside the workspace)
+  int *d_span = nullptr;
+  double *d_bas = nullptr;           // m x (p+1), values
+  double *d_gram = nullptr;          // (p+1) x n lower band
+  double *d_chol = nullptr;
+  double *d_inv = nullptr;
+  int *d_blk = nullptr;              // per block: c0 c1 F0 F1 own0 own1 D0 D1 (int)
+  int *d_blo = nullptr, *d_bhi = nullptr, *d_owner = nullptr, *d_pown = nullptr;
+  int *d_ns = nullptr;
+  double *d_ustar = nullptr;
+  int *d_span_if = nullptr;
+  double *d_dbas_if = nullptr;       // (B-1) x p x (p+1)
+  int *d_gidJ = nullptr;             // J row -> r
+  int *d_gidD = nullptr;             // D row -> r
+  Ell N[kMaxP + 1];                  // decode tables, derivative order 0..p
+  Ell NT, A, M, Om, J, D;
+  // DATABOX tables
+  Ell Nseg, NsegT, Zseg, Comb;
+  int *d_qmap = nullptr;             // segmented data row -> data point index
+};
+
+struct Handle {
+  mfa_problem prob{};
+  int dim = 0, p = 0, overlap = 0, precision = 0, combine = 0, rhs = 0;
+  Axis ax[3];
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  int64_t nctrl_total = 1, npts_total = 1;
+  // state
+  double *c = nullptr;      // N^T Q
+  double *P = nullptr;      // consensus control points
+  double *g = nullptr;      // N^T Q - N^T N P
+  double *s1 = nullptr, *s2 = nullptr;   // scratch
+  int64_t s1n = 0, s2n = 0;
+  // DATABOX scratch
+  double *b1 = nullptr, *b2 = nullptr;
+  int64_t b1n = 0, b2n = 0;
+  unsigned long long *slots = nullptr;   // reductions, see kSlot*
+  int *flag = nullptr;                   // setup error flag
+  bool have_rhs = false;
+  bool warm = false;        // P was set by mfa_set_ctrl: the next encode starts there
+  int sweep = 0;
+};
+
+// reduction slots (double bit patterns of non-negative maxima)
+constexpr int kSlotMaxDP = 0;
+constexpr int kSlotNres = 1;
+constexpr int kSlotCtrl = 2;
+constexpr int kSlotJ = 8;                       // + a*kMaxP + r
+constexpr int kSlotS = kSlotJ + 3 * kMaxP;      // + a*kMaxP + r
+constexpr int kNumSlots = kSlotS + 3 * kMaxP;
+
+// ---------------------------------------------------------------- planner
+// Fills h->ax[*] host-side plan; returns an error message or "".
+std::string plan_problem(const mfa_problem &prob, Handle *h);
+// Lays out the workspace; with base == nullptr only counts bytes.
+size_t layout_workspace(Handle *h, char *base);
+
+// ---------------------------------------------------------------- kernels
+enum Epi { EPI_STORE = 0, EPI_SUBFROM = 1, EPI_ADDTO = 2, EPI_MAXABS = 3 };
+
+struct Dims {
+  int64_t d[3];
+  int64_t total() const { return d[0] * d[1] * d[2]; }
+};
+
+// out = op applied along internal axis `ax` of `in` (dims `in_dims`), with
+// the chosen epilogue.  Tin/Tout in {float, double}.
+template <typename Tin, typename Tout>
+hipError_t launch_pass(hipStream_t st, const Tin *in, Dims in_dims, int ax, const Ell &op,
+                       Tout *out, int epi, const double *sub, unsigned long long *slots,
+                       int slot_base, const int *gid, int gaxis);
+
+hipError_t launch_fill(hipStream_t st, double *x, int64_t n, double v);
+hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n);
+hipError_t launch_maxabs(hipStream_t st, const double *x, int64_t n, unsigned long long *slot);
+
+// setup kernels (one axis at a time)
+hipError_t setup_axis(Handle *h, int a);
+
+}  // namespace mfa

@@ -1,0 +1,527 @@
+// Setup kernels: basis evaluation, banded normal matrices, batched banded
+// Cholesky, local inverses and the per-axis operator tables.  All float64.
+#include <algorithm>
+#include <vector>
+
+#include "mfa_internal.hpp"
+
+namespace mfa {
+
+namespace {
+
+// t_j of the clamped uniform knot vector: (j-p)/(n-p) clamped to [0, 1]
+// (Section 2.2: clamped at the global ends, floating in the interior).
+__device__ __forceinline__ double knot(int j, int n, int p) {
+  const int q = j - p;
+  if (q <= 0) return 0.0;
+  if (q >= n - p) return 1.0;
+  return (double)q / (double)(n - p);
+}
+
+__device__ __forceinline__ int64_t dceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__device__ __forceinline__ int64_t d_first_with_span_ge(int s, int64_t m, int n, int p) {
+  if (s <= p) return 0;
+  return dceil_div((int64_t)(s - p) * (m - 1), n - p);
+}
+
+__device__ __forceinline__ int64_t d_last_with_span_le(int s, int64_t m, int n, int p) {
+  if (s >= n - 1) return m - 1;
+  return dceil_div((int64_t)(s - p + 1) * (m - 1), n - p) - 1;
+}
+
+// r-th derivative (r = 0: value) of the p+1 basis functions N_{s-p..s, p}
+// that are nonzero in span s, at parameter u.  Degree is raised with the
+// Cox-de Boor recurrence
+//   N_{j,k} = (u - t_j)/(t_{j+k} - t_j) N_{j,k-1} + (t_{j+k+1} - u)/(t_{j+k+1} - t_{j+1}) N_{j+1,k-1}
+// up to degree p-r, then the last r degrees use the differentiated recurrence
+//   D N_{j,k} = k/(t_{j+k} - t_j) D' N_{j,k-1} - k/(t_{j+k+1} - t_{j+1}) D' N_{j+1,k-1}
+// (empty knot intervals contribute nothing).  v[q] holds the function of index
+// s-k+q at the current degree k.
+__device__ void basis_deriv(double u, int s, int n, int p, int r, double *out) {
+  double v[kMaxP + 1];
+  double w[kMaxP + 1];
+#pragma unroll
+  for (int q = 0; q <= kMaxP; ++q) v[q] = 0.0;
+  v[0] = 1.0;
+  const int kv = p - r;
+  for (int k = 1; k <= p; ++k) {
+    const bool deriv = k > kv;
+#pragma unroll
+    for (int q = 0; q <= kMaxP; ++q) {
+      if (q > k) break;
+      const int j = s - k + q;
+      double a = 0.0, b = 0.0;
+      if (q >= 1) {
+        const double tj = knot(j, n, p), tjk = knot(j + k, n, p);
+        const double d = tjk - tj;
+        if (d > 0.0) a = deriv ? (double)k * v[q - 1] / d : (u - tj) / d * v[q - 1];
+      }
+      if (q <= k - 1) {
+        const double tj1 = knot(j + 1, n, p), tjk1 = knot(j + k + 1, n, p);
+        const double d = tjk1 - tj1;
+        if (d > 0.0) b = deriv ? (double)k * v[q] / d : (tjk1 - u) / d * v[q];
+      }
+      w[q] = deriv ? a - b : a + b;
+    }
+#pragma unroll
+    for (int q = 0; q <= kMaxP; ++q)
+      if (q <= k) v[q] = w[q];
+  }
+  for (int q = 0; q <= p; ++q) out[q] = v[q];
+}
+
+// One thread per data point: span and r-th derivative basis row, written as
+// the ELL decode table (columns span-p..span).
+__global__ void k_basis(int64_t m, int n, int p, int r, int *span_out, Ell tab) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int64_t s = p + (i * (n - p)) / (m - 1);
+  if (s > n - 1) s = n - 1;
+  const double u = (double)i / (double)(m - 1);
+  double vals[kMaxP + 1];
+  basis_deriv(u, (int)s, n, p, r, vals);
+  if (span_out) span_out[i] = (int)s;
+  tab.len[i] = p + 1;
+  for (int q = 0; q <= p; ++q) {
+    tab.col[i * tab.L + q] = (int)s - p + q;
+    tab.val[i * tab.L + q] = vals[q];
+  }
+}
+
+// Derivatives of orders 0..p-1 at each interface parameter u*_b.
+__global__ void k_basis_if(int nif, int n, int p, const double *ustar, const int *span_if,
+                           double *out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nif * p) return;
+  const int b = t / p, r = t % p;
+  basis_deriv(ustar[b], span_if[b], n, p, r, out + (int64_t)t * (p + 1));
+}
+
+// Banded normal matrix A = N^T N of one axis, lower band storage
+// band[t*n + k] = A[k+t][k].  One wavefront per row k: the lanes stride over
+// the data points in the support of N_k and the p+1 partial sums are reduced
+// across the wavefront with shuffles (fixed order, deterministic).
+__global__ void __launch_bounds__(64) k_gram(int64_t m, int n, int p, const int *span,
+                                             Ell basis, double *band) {
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int smin = max(k, p), smax = min(k + p, n - 1);
+  const int64_t lo = d_first_with_span_ge(smin, m, n, p);
+  const int64_t hi = d_last_with_span_le(smax, m, n, p);
+  double acc[kMaxP + 1];
+#pragma unroll
+  for (int t = 0; t <= kMaxP; ++t) acc[t] = 0.0;
+  for (int64_t i = lo + lane; i <= hi; i += 64) {
+    const int s = span[i];
+    const double *b = basis.val + i * basis.L;
+    const double nk = b[k - s + p];
+#pragma unroll
+    for (int t = 0; t <= kMaxP; ++t)
+      if (t <= p && k + t <= s) acc[t] += nk * b[k + t - s + p];
+  }
+#pragma unroll
+  for (int t = 0; t <= kMaxP; ++t) {
+    double v = acc[t];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    acc[t] = v;
+  }
+  if (lane == 0)
+    for (int t = 0; t <= p; ++t) band[(int64_t)t * n + k] = (k + t < n) ? acc[t] : 0.0;
+}
+
+// Batched banded Cholesky of every subdomain's local normal matrix
+// A[F0:F1, F0:F1] (a principal block of the axis' band; Section 2.3.1).
+// One wavefront per matrix: lane 0 forms the pivot of column j, lanes 1..p
+// the subdiagonal entries.  A non-positive pivot sets flag[0].
+__global__ void __launch_bounds__(64) k_chol(int n, int p, const double *band, const int *blk,
+                                             double *chol, int *flag) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  int64_t off = 0;
+  for (int bb = 0; bb < b; ++bb) off += (int64_t)(p + 1) * (blk[8 * bb + 3] - blk[8 * bb + 2]);
+  const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
+  double *L = chol + off;  // L[t*F + j] = L(j+t, j)
+  for (int j = 0; j < F; ++j) {
+    if (lane == 0) {
+      const double ajj = band[F0 + j];
+      double s = ajj;
+      for (int k = max(0, j - p); k < j; ++k) {
+        const double l = L[(j - k) * F + k];
+        s -= l * l;
+      }
+      if (!(s > 1e-13 * ajj) || !(s > 0.0)) {
+        atomicOr(flag, 1);
+        s = 1.0;
+      }
+      L[j] = sqrt(s);
+    }
+    __syncthreads();
+    if (lane >= 1 && lane <= p) {
+      const int i = j + lane;
+      if (i < F) {
+        double s = band[(int64_t)lane * n + F0 + j];
+        for (int k = max(0, i - p); k < j; ++k) s -= L[(i - k) * F + k] * L[(j - k) * F + k];
+        L[lane * F + j] = s / L[j];
+      } else {
+        L[lane * F + j] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Dense inverse of every local normal matrix from its banded Cholesky factor:
+// column `col` solves L L^T z = e_col by forward and backward substitution.
+__global__ void k_inverse(int p, const int *blk, const double *chol, double *inv) {
+  const int b = blockIdx.x;
+  int64_t offc = 0, offi = 0;
+  for (int bb = 0; bb < b; ++bb) {
+    const int Fb = blk[8 * bb + 3] - blk[8 * bb + 2];
+    offc += (int64_t)(p + 1) * Fb;
+    offi += (int64_t)Fb * Fb;
+  }
+  const int F = blk[8 * b + 3] - blk[8 * b + 2];
+  const double *L = chol + offc;
+  double *Z = inv + offi;
+  for (int col = threadIdx.x; col < F; col += blockDim.x) {
+    for (int i = 0; i < F; ++i) {
+      double s = (i == col) ? 1.0 : 0.0;
+      if (i > col)
+        for (int k = max(col, i - p); k < i; ++k) s -= L[(i - k) * F + k] * Z[(int64_t)k * F + col];
+      Z[(int64_t)i * F + col] = (i < col) ? 0.0 : s / L[i];
+    }
+    for (int i = F - 1; i >= 0; --i) {
+      double s = Z[(int64_t)i * F + col];
+      for (int k = i + 1; k <= min(F - 1, i + p); ++k) s -= L[(k - i) * F + i] * Z[(int64_t)k * F + col];
+      Z[(int64_t)i * F + col] = s / L[i];
+    }
+  }
+}
+
+__device__ __forceinline__ int64_t inv_offset(const int *blk, int b) {
+  int64_t off = 0;
+  for (int bb = 0; bb < b; ++bb) {
+    const int Fb = blk[8 * bb + 3] - blk[8 * bb + 2];
+    off += (int64_t)Fb * Fb;
+  }
+  return off;
+}
+
+__device__ __forceinline__ void pad_row(Ell &t, int64_t r, int len) {
+  t.len[r] = len;
+  const int last = len > 0 ? t.col[r * t.L + len - 1] : 0;
+  for (int q = len; q < t.L; ++q) {
+    t.col[r * t.L + q] = last;
+    t.val[r * t.L + q] = 0.0;
+  }
+  if (t.valf)
+    for (int q = 0; q < t.L; ++q) t.valf[r * t.L + q] = (float)t.val[r * t.L + q];
+}
+
+// N^T: row k lists the data points whose span lies in [k, k+p].
+__global__ void k_tab_NT(int64_t m, int n, int p, const int *span, Ell basis, Ell t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t lo = d_first_with_span_ge(max(k, p), m, n, p);
+  const int64_t hi = d_last_with_span_le(min(k + p, n - 1), m, n, p);
+  int len = 0;
+  for (int64_t i = lo; i <= hi; ++i, ++len) {
+    const int s = span[i];
+    t.col[(int64_t)k * t.L + len] = (int)i;
+    t.val[(int64_t)k * t.L + len] = basis.val[i * basis.L + (k - s + p)];
+  }
+  pad_row(t, k, len);
+}
+
+// A = N^T N as rows: columns k-p..k+p from the band.
+__global__ void k_tab_A(int n, int p, const double *band, Ell t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int len = 0;
+  for (int c = max(0, k - p); c <= min(n - 1, k + p); ++c, ++len) {
+    const int lo = min(k, c), d = abs(k - c);
+    t.col[(int64_t)k * t.L + len] = c;
+    t.val[(int64_t)k * t.L + len] = band[(int64_t)d * n + lo];
+  }
+  pad_row(t, k, len);
+}
+
+// Weighted additive-Schwarz operator of one axis:
+// M[k][:] = sum over blocks b whose free set holds k of w_k Z_b[k - F0_b][:],
+// w_k = 1/n_s(k) (combine AVG) or the owner indicator (combine RAS).
+__global__ void k_tab_M(int n, int combine, const int *blk, const int *blo, const int *bhi,
+                        const int *owner, const int *ns, const double *inv, Ell t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int b0 = blo[k], b1 = bhi[k];
+  if (combine == MFA_COMBINE_RAS) b0 = b1 = owner[k];
+  const int cfirst = blk[8 * b0 + 2], clast = blk[8 * b1 + 3];
+  const double w = combine == MFA_COMBINE_RAS ? 1.0 : 1.0 / (double)ns[k];
+  const int len = clast - cfirst;
+  for (int q = 0; q < len; ++q) {
+    t.col[(int64_t)k * t.L + q] = cfirst + q;
+    t.val[(int64_t)k * t.L + q] = 0.0;
+  }
+  for (int b = b0; b <= b1; ++b) {
+    const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
+    const double *Z = inv + inv_offset(blk, b);
+    for (int c = 0; c < F; ++c) t.val[(int64_t)k * t.L + (F0 + c - cfirst)] += w * Z[(int64_t)(k - F0) * F + c];
+  }
+  pad_row(t, k, len);
+}
+
+// Decode of a subdomain's local correction at its owned data points:
+// Om[i][:] = sum_q N_{s-p+q}(u_i) Z_b[s-p+q - F0_b][:] over the free set of the
+// block b that owns point i (basis functions outside F_b carry no correction).
+__global__ void k_tab_Om(int64_t m, int p, const int *blk, const int *pown, const int *span,
+                         Ell basis, const double *inv, Ell t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int b = pown[i];
+  const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
+  const double *Z = inv + inv_offset(blk, b);
+  const int s = span[i];
+  for (int c = 0; c < F; ++c) {
+    double acc = 0.0;
+    for (int q = 0; q <= p; ++q) {
+      const int j = s - p + q - F0;
+      if (j >= 0 && j < F) acc += basis.val[i * basis.L + q] * Z[(int64_t)j * F + c];
+    }
+    t.col[i * t.L + c] = F0 + c;
+    t.val[i * t.L + c] = acc;
+  }
+  pad_row(t, i, F);
+}
+
+// Interface jump functionals: row (b, r) maps a residual line to
+// d^r/du^r (L_b - L_{b+1})(u*_b) = dB_r(u*)^T (E_b Z_b R_b - E_{b+1} Z_{b+1} R_{b+1}).
+__global__ void k_tab_J(int nif, int p, const int *blk, const int *span_if, const double *dbas,
+                        const double *inv, Ell t, int *gid) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nif * p) return;
+  const int b = row / p, r = row % p;
+  const int cfirst = blk[8 * b + 2], clast = blk[8 * (b + 1) + 3];
+  const int len = clast - cfirst;
+  const double *dv = dbas + (int64_t)row * (p + 1);
+  const int s = span_if[b];
+  for (int q = 0; q < len; ++q) {
+    t.col[(int64_t)row * t.L + q] = cfirst + q;
+    t.val[(int64_t)row * t.L + q] = 0.0;
+  }
+  for (int side = 0; side < 2; ++side) {
+    const int bb = b + side;
+    const double sgn = side == 0 ? 1.0 : -1.0;
+    const int F0 = blk[8 * bb + 2], F = blk[8 * bb + 3] - F0;
+    const double *Z = inv + inv_offset(blk, bb);
+    for (int q = 0; q <= p; ++q) {
+      const int j = s - p + q - F0;
+      if (j < 0 || j >= F) continue;
+      for (int c = 0; c < F; ++c)
+        t.val[(int64_t)row * t.L + (F0 + c - cfirst)] += sgn * dv[q] * Z[(int64_t)j * F + c];
+    }
+  }
+  pad_row(t, row, len);
+  gid[row] = r;
+}
+
+// Derivative-coefficient operator: rows of D^r for r = 0..p-1 stacked; row k
+// of D^r gives the r-th derivative control coefficient
+//   D^r_k = (p-r+1)/(t_{k+p+1} - t_{k+r}) (D^{r-1}_{k+1} - D^{r-1}_k),  D^0 = P.
+__global__ void k_tab_D(int n, int p, Ell t, int *gid) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  int r = 0, base = 0;
+  while (r < p && row >= base + (n - r)) {
+    base += n - r;
+    ++r;
+  }
+  if (r >= p) return;
+  const int k = row - base;
+  // c[l][i]: coefficients (over P_{k..k+r}) of D^l_{k+i}
+  double c[kMaxP + 1][kMaxP + 1];
+  for (int i = 0; i <= r; ++i)
+    for (int q = 0; q <= r; ++q) c[i][q] = (i == q) ? 1.0 : 0.0;
+  for (int l = 1; l <= r; ++l) {
+    for (int i = 0; i <= r - l; ++i) {
+      const int kk = k + i;
+      const double den = knot(kk + p + 1, n, p) - knot(kk + l, n, p);
+      const double f = den > 0.0 ? (double)(p - l + 1) / den : 0.0;
+      for (int q = 0; q <= r; ++q) c[i][q] = f * (c[i + 1][q] - c[i][q]);
+    }
+  }
+  for (int q = 0; q <= r; ++q) {
+    t.col[(int64_t)row * t.L + q] = k + q;
+    t.val[(int64_t)row * t.L + q] = c[0][q];
+  }
+  pad_row(t, row, r + 1);
+  gid[row] = r;
+}
+
+// ----------------------------------------------------------------- DATABOX
+// segmented decode: row (b, i) for data point i of D_b (rows of N gathered)
+__global__ void k_tab_Nseg(int p, int B, const int *blk, const int64_t *doff_unused, Ell basis,
+                           Ell t, int *qmap) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= t.R) return;
+  int b = 0;
+  int64_t base = 0;
+  while (b < B) {
+    const int64_t nd = (int64_t)blk[8 * b + 7] - blk[8 * b + 6];
+    if (row < base + nd) break;
+    base += nd;
+    ++b;
+  }
+  const int64_t i = blk[8 * b + 6] + (row - base);
+  qmap[row] = (int)i;
+  for (int q = 0; q <= p; ++q) {
+    t.col[row * t.L + q] = basis.col[i * basis.L + q];
+    t.val[row * t.L + q] = basis.val[i * basis.L + q];
+  }
+  pad_row(t, row, p + 1);
+}
+
+// segmented N_F^T: row (b, k), k in F_b, over the segment of D_b
+__global__ void k_tab_NsegT(int64_t m, int n, int p, int B, const int *blk, const int *span,
+                            Ell basis, Ell t) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= t.R) return;
+  int b = 0;
+  int64_t base = 0, dbase = 0;
+  while (b < B) {
+    const int64_t nf = (int64_t)blk[8 * b + 3] - blk[8 * b + 2];
+    if (row < base + nf) break;
+    base += nf;
+    dbase += (int64_t)blk[8 * b + 7] - blk[8 * b + 6];
+    ++b;
+  }
+  const int k = blk[8 * b + 2] + (int)(row - base);
+  int64_t lo = d_first_with_span_ge(max(k, p), m, n, p);
+  int64_t hi = d_last_with_span_le(min(k + p, n - 1), m, n, p);
+  const int64_t D0 = blk[8 * b + 6], D1 = blk[8 * b + 7];
+  lo = lo > D0 ? lo : D0;
+  hi = hi < D1 - 1 ? hi : D1 - 1;
+  int len = 0;
+  for (int64_t i = lo; i <= hi; ++i, ++len) {
+    const int s = span[i];
+    t.col[row * t.L + len] = (int)(dbase + (i - D0));
+    t.val[row * t.L + len] = basis.val[i * basis.L + (k - s + p)];
+  }
+  pad_row(t, row, len);
+}
+
+// block-diagonal local inverse on the segmented free layout
+__global__ void k_tab_Zseg(int B, const int *blk, const double *inv, Ell t) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= t.R) return;
+  int b = 0;
+  int64_t base = 0;
+  while (b < B) {
+    const int64_t nf = (int64_t)blk[8 * b + 3] - blk[8 * b + 2];
+    if (row < base + nf) break;
+    base += nf;
+    ++b;
+  }
+  const int F = blk[8 * b + 3] - blk[8 * b + 2];
+  const int j = (int)(row - base);
+  const double *Z = inv + inv_offset(blk, b);
+  for (int c = 0; c < F; ++c) {
+    t.col[row * t.L + c] = (int)(base + c);
+    t.val[row * t.L + c] = Z[(int64_t)j * F + c];
+  }
+  pad_row(t, row, F);
+}
+
+// combine from the segmented free layout back to the control grid
+__global__ void k_tab_Comb(int n, int combine, const int *blk, const int *blo, const int *bhi,
+                           const int *owner, const int *ns, Ell t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int b0 = blo[k], b1 = bhi[k];
+  if (combine == MFA_COMBINE_RAS) b0 = b1 = owner[k];
+  const double w = combine == MFA_COMBINE_RAS ? 1.0 : 1.0 / (double)ns[k];
+  int len = 0;
+  for (int b = b0; b <= b1; ++b) {
+    int64_t base = 0;
+    for (int bb = 0; bb < b; ++bb) base += blk[8 * bb + 3] - blk[8 * bb + 2];
+    t.col[(int64_t)k * t.L + len] = (int)(base + (k - blk[8 * b + 2]));
+    t.val[(int64_t)k * t.L + len] = w;
+    ++len;
+  }
+  pad_row(t, k, len);
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+#define MFA_TRY(x)                       \
+  do {                                   \
+    hipError_t e_ = (x);                 \
+    if (e_ != hipSuccess) return e_;     \
+  } while (0)
+
+hipError_t setup_axis(Handle *h, int ia) {
+  Axis &X = h->ax[ia];
+  hipStream_t st = h->stream;
+  const int p = h->p, n = X.n, B = X.B, nif = B - 1;
+  const int64_t m = X.m;
+  // host-planned integer tables
+  std::vector<int> blk(8 * B);
+  for (int b = 0; b < B; ++b) {
+    const Block &Bk = X.blk[b];
+    int *e = &blk[8 * b];
+    e[0] = Bk.c0; e[1] = Bk.c1; e[2] = Bk.F0; e[3] = Bk.F1;
+    e[4] = (int)Bk.own0; e[5] = (int)Bk.own1; e[6] = (int)Bk.D0; e[7] = (int)Bk.D1;
+  }
+  MFA_TRY(hipMemcpyAsync(X.d_blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice, st));
+  MFA_TRY(hipMemcpyAsync(X.d_blo, X.blo.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  MFA_TRY(hipMemcpyAsync(X.d_bhi, X.bhi.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  MFA_TRY(hipMemcpyAsync(X.d_owner, X.owner.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  MFA_TRY(hipMemcpyAsync(X.d_ns, X.ns.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  MFA_TRY(hipMemcpyAsync(X.d_pown, X.pown.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
+  if (nif > 0) {
+    MFA_TRY(hipMemcpyAsync(X.d_ustar, X.ustar.data(), sizeof(double) * nif, hipMemcpyHostToDevice, st));
+    MFA_TRY(hipMemcpyAsync(X.d_span_if, X.span_if.data(), sizeof(int) * nif, hipMemcpyHostToDevice, st));
+  }
+  // pageable host copies above complete before the call returns; the vectors
+  // may go out of scope afterwards.
+  MFA_TRY(hipStreamSynchronize(st));
+
+  // basis values and derivative tables at the data points
+  for (int r = 0; r <= p; ++r) {
+    k_basis<<<nblk(m, 256), 256, 0, st>>>(m, n, p, r, r == 0 ? X.d_span : nullptr, X.N[r]);
+    MFA_TRY(hipGetLastError());
+  }
+  X.d_bas = X.N[0].val;
+  if (nif > 0) {
+    k_basis_if<<<nblk((int64_t)nif * p, 64), 64, 0, st>>>(nif, n, p, X.d_ustar, X.d_span_if, X.d_dbas_if);
+    MFA_TRY(hipGetLastError());
+  }
+  k_gram<<<n, 64, 0, st>>>(m, n, p, X.d_span, X.N[0], X.d_gram);
+  MFA_TRY(hipGetLastError());
+  k_chol<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, h->flag);
+  MFA_TRY(hipGetLastError());
+  k_inverse<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
+  MFA_TRY(hipGetLastError());
+  k_tab_NT<<<nblk(n, 128), 128, 0, st>>>(m, n, p, X.d_span, X.N[0], X.NT);
+  k_tab_A<<<nblk(n, 128), 128, 0, st>>>(n, p, X.d_gram, X.A);
+  k_tab_M<<<nblk(n, 64), 64, 0, st>>>(n, h->combine, X.d_blk, X.d_blo, X.d_bhi, X.d_owner, X.d_ns,
+                                      X.d_inv, X.M);
+  k_tab_Om<<<nblk(m, 64), 64, 0, st>>>(m, p, X.d_blk, X.d_pown, X.d_span, X.N[0], X.d_inv, X.Om);
+  if (nif > 0)
+    k_tab_J<<<nblk((int64_t)nif * p, 64), 64, 0, st>>>(nif, p, X.d_blk, X.d_span_if, X.d_dbas_if,
+                                                       X.d_inv, X.J, X.d_gidJ);
+  k_tab_D<<<nblk(X.ND, 128), 128, 0, st>>>(n, p, X.D, X.d_gidD);
+  MFA_TRY(hipGetLastError());
+  if (h->rhs == MFA_RHS_DATABOX) {
+    k_tab_Nseg<<<nblk(X.SD, 128), 128, 0, st>>>(p, B, X.d_blk, nullptr, X.N[0], X.Nseg, X.d_qmap);
+    k_tab_NsegT<<<nblk(X.SF, 128), 128, 0, st>>>(m, n, p, B, X.d_blk, X.d_span, X.N[0], X.NsegT);
+    k_tab_Zseg<<<nblk(X.SF, 64), 64, 0, st>>>(B, X.d_blk, X.d_inv, X.Zseg);
+    k_tab_Comb<<<nblk(n, 128), 128, 0, st>>>(n, h->combine, X.d_blk, X.d_blo, X.d_bhi, X.d_owner,
+                                             X.d_ns, X.Comb);
+    MFA_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+}  // namespace mfa

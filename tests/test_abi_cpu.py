@@ -1,0 +1,83 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, and the host planner validates problems (no device calls)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2210_06528_amd import _lib
+from paper_2210_06528_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mfa.h")).read()
+    return sorted(set(re.findall(r"\b(mfa_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2210_06528_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_workspace_size_for_named_workloads(lib):
+    for w in [W.cfg_1d(), W.cfg_2d(), W.cfg_3d_batched(), W.cfg_3d_mixed()]:
+        b = _lib.workspace_size(w.npts, w.degree, w.sizes, w.overlap, "fp64")
+        # at least the N^T Q, control point and residual arrays in float64
+        assert b >= 3 * 8 * int(np.prod(w.nctrl))
+
+
+@pytest.mark.parametrize("kwargs,msg", [
+    (dict(npts=(100,), degree=3, sizes=[[10, 10]], overlap=0), "overlap"),
+    (dict(npts=(100,), degree=4, sizes=[[10, 10]], overlap=1), "overlap"),
+    (dict(npts=(100,), degree=3, sizes=[[3, 17]], overlap=1), "owned block"),
+    (dict(npts=(10,), degree=3, sizes=[[8, 8]], overlap=1), "fewer data points"),
+    (dict(npts=(100,), degree=0, sizes=[[10, 10]], overlap=1), "degree"),
+    (dict(npts=(100,), degree=9, sizes=[[10, 10]], overlap=1), "degree"),
+    (dict(npts=(10, 10, 10, 10), degree=2, sizes=[[5]] * 4, overlap=1), "dim"),
+    (dict(npts=(100,), degree=3, sizes=[[2]], overlap=1), "p+1"),
+])
+def test_invalid_problems_are_rejected(lib, kwargs, msg):
+    with pytest.raises(_lib.MfaError) as ei:
+        _lib.workspace_size(**kwargs)
+    assert ei.value.status == _lib.MFA_EINVAL
+    assert msg in str(ei.value)
+
+
+def test_bad_enum_values_rejected(lib):
+    for key in ("precision", "combine", "rhs"):
+        kw = dict(npts=(100,), degree=3, sizes=[[20, 20]], overlap=2)
+        kw[key] = 7
+        with pytest.raises(_lib.MfaError):
+            _lib.workspace_size(**kw)
+
+
+def test_null_pointers_rejected(lib):
+    import ctypes
+    assert lib.mfa_workspace_size(None, None) == _lib.MFA_EINVAL
+    assert b"null" in lib.mfa_last_error()
+    assert lib.mfa_create(None, None, 0, None, None) == _lib.MFA_EINVAL
+    h = ctypes.c_void_p(0)
+    prob, keep = _lib.make_problem((100,), 3, [[20, 20]], 2)
+    assert lib.mfa_create(ctypes.byref(prob), None, 0, None, ctypes.byref(h)) == _lib.MFA_EINVAL
+    assert lib.mfa_encode(None, None, 0, 1, 0.0, 1, None) == _lib.MFA_EINVAL
+    assert lib.mfa_decode(None, None, 0, None) == _lib.MFA_EINVAL
+    lib.mfa_destroy(None)
+
+
+def test_workspace_grows_with_problem(lib):
+    a = _lib.workspace_size((200, 200), 3, [[25, 25]] * 2, 2)
+    b = _lib.workspace_size((400, 400), 3, [[50, 50]] * 2, 2)
+    assert b > 3 * a

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Tolerances: control points in FP64 mode agree to 1e-10 relative (max-norm);
+intermediates (basis rows, normal-matrix bands, Cholesky factors) to 1e-12;
+spans bit-exact.  Inputs come from the seeded generators only.
+"""
+import numpy as np
+import pytest
+
+from oracle import bspline, lsq, schwarz
+from paper_2210_06528_amd import _lib
+from paper_2210_06528_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _oracle(w, combine="avg"):
+    return schwarz.setup(schwarz.make_plan(w.npts, w.degree, w.sizes, w.overlap, combine=combine))
+
+
+def _enc(w, precision="fp64", combine="avg", rhs="normal"):
+    return _lib.Encoder(w.npts, w.degree, w.sizes, w.overlap, precision, combine, rhs)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(1e-300, np.max(np.abs(b))))
+
+
+def _small_2d(p=3, overlap=2, seed=7):
+    sizes = [[9, 10, 9], [8, 9]]
+    sizes = [[max(s, p + 1, 2 * overlap) for s in ax] for ax in sizes]
+    w = W.Workload("2d-small", (97, 71), p, sizes, overlap, jump_tol=1e-8, seed=seed)
+    w.extra["kmax"] = 6
+    return w
+
+
+def _field(w):
+    return W.field_spectral(w.npts, kmax=w.extra.get("kmax", 4), seed=w.seed, dtype=np.float64)
+
+
+SMALL = {
+    "1d": lambda: W.cfg_1d(),
+    "2d": lambda: _small_2d(),
+    "3d": lambda: W.small_3d(),
+    "2d-p1": lambda: _small_2d(p=1, overlap=1),
+    "2d-p5": lambda: _small_2d(p=5, overlap=2),
+    "3d-p4": lambda: W.small_3d(p=4, overlap=2, sizes=((8, 9), (8, 8), (7, 7))),
+}
+
+
+def _data(w):
+    return W.make_field(w) if w.name.startswith("1d") else _field(w)
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "3d", "3d-p4"])
+def test_setup_tables_match_oracle(name):
+    w = SMALL[name]()
+    S = _oracle(w)
+    enc = _enc(w)
+    p = w.degree
+    for a, ax in enumerate(S.plan.axes):
+        span = enc.inspect("span", a)
+        assert np.array_equal(span.astype(np.int64), ax.span)
+        bas = enc.inspect("basis", a).reshape(ax.m, p + 1)
+        C = S.colls[a]
+        rows = np.stack([C[i, ax.span[i] - p:ax.span[i] + 1] for i in range(ax.m)])
+        assert np.max(np.abs(bas - rows)) < 1e-14
+        gram = enc.inspect("gram", a).reshape(p + 1, ax.n)
+        assert _rel(gram, lsq.gram_band(C, p)) < 1e-13
+        for b, bl in enumerate(ax.blocks):
+            F = bl.F1 - bl.F0
+            L = enc.inspect("chol", a, b).reshape(p + 1, F)
+            Lo = S.factors[(a, b)]
+            # only the stored part of the band (entries past the end are padding)
+            for t in range(p + 1):
+                assert _rel(L[t, :F - t], Lo[t, :F - t]) < 1e-12
+            Z = enc.inspect("inv", a, b).reshape(F, F)
+            NF = C[bl.D0:bl.D1, bl.F0:bl.F1]
+            assert _rel(Z, np.linalg.inv(NF.T @ NF)) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "3d"])
+def test_rhs_is_NtQ(name):
+    w = SMALL[name]()
+    S = _oracle(w)
+    Q = _data(w)
+    enc = _enc(w)
+    enc.step(torch.from_numpy(np.ascontiguousarray(Q)).cuda())
+    c = enc.inspect("rhs").reshape(w.nctrl)
+    ref = lsq.tensor_apply([C.T for C in S.colls], Q)
+    assert _rel(c, ref) < 1e-13
+
+
+@pytest.mark.parametrize("combine", ["avg", "ras"])
+@pytest.mark.parametrize("name,nsweeps", [("1d", 10), ("2d", 6), ("3d", 5), ("2d-p1", 5),
+                                          ("2d-p5", 5), ("3d-p4", 4)])
+def test_sweeps_match_oracle(name, nsweeps, combine):
+    w = SMALL[name]()
+    S = _oracle(w, combine)
+    Q = _data(w)
+    enc = _enc(w, combine=combine)
+    q = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    P = np.zeros(w.nctrl)
+    for k in range(nsweeps):
+        P, st = schwarz.sweep(S, Q, P, k + 1)
+        g = enc.step(q if k == 0 else None)
+        Pg = enc.get_ctrl().cpu().numpy()
+        assert _rel(Pg, P) < 1e-10, (k, _rel(Pg, P))
+        assert abs(g["nres_max"] - st.nres_max) <= 1e-9 * max(st.nres_max, 1e-300) + 1e-13
+        assert abs(g["max_dP"] - st.max_dP) <= 1e-8 * st.max_dP + 1e-13
+        for r in range(w.degree):
+            jo, jg = st.jump[r], g["jump"][r]
+            if jo > 1e-9:
+                assert abs(jg - jo) <= 1e-6 * jo, (k, r, jg, jo)
+            else:
+                assert jg < 1e-8
+
+
+def test_cfg2_converges_in_the_oracle_sweep_count():
+    w = W.cfg_2d()
+    S = _oracle(w)
+    Q = W.make_field(w)
+    Po, hist = schwarz.encode(S, Q, 40, jump_tol=w.jump_tol)
+    enc = _enc(w)
+    st = enc.encode(torch.from_numpy(Q).cuda(), 40, w.jump_tol)
+    assert st["converged"] and st["sweep"] == len(hist)
+    assert _rel(enc.get_ctrl().cpu().numpy(), Po) < 1e-10
+    assert max(st["jump"][:3]) < 1e-8
+
+
+def test_decode_and_derivatives_match_oracle():
+    w = SMALL["3d"]()
+    S = _oracle(w)
+    rng = np.random.default_rng(3)
+    P = rng.standard_normal(w.nctrl)
+    enc = _enc(w)
+    enc.set_ctrl(torch.from_numpy(P).cuda())
+    f = enc.decode().cpu().numpy()
+    assert _rel(f, schwarz.decode(S, P)) < 1e-13
+    f32 = enc.decode(dtype=torch.float32).cpu().numpy()
+    assert _rel(f32, schwarz.decode(S, P)) < 1e-6
+    for der in [(1, 0, 0), (0, 2, 1), (3, 3, 3)]:
+        fd = enc.decode(deriv=der).cpu().numpy()
+        assert _rel(fd, schwarz.decode(S, P, der)) < 1e-11
+
+
+def test_single_subdomain_one_sweep_is_direct():
+    w = W.small_3d(sizes=((14,), (12,), (11,)))
+    S = _oracle(w)
+    Q = _field(w)
+    enc = _enc(w)
+    enc.step(torch.from_numpy(Q).cuda())
+    assert _rel(enc.get_ctrl().cpu().numpy(), schwarz.global_direct(S, Q)) < 1e-12
+
+
+def test_exact_fit_is_a_fixed_point_and_warm_start():
+    w = SMALL["2d"]()
+    S = _oracle(w)
+    Q = _field(w)
+    Pstar = schwarz.global_direct(S, Q)
+    enc = _enc(w)
+    enc.set_ctrl(torch.from_numpy(Pstar).cuda())
+    st = enc.encode(torch.from_numpy(Q).cuda(), 1, 0.0)
+    assert _rel(enc.get_ctrl().cpu().numpy(), Pstar) < 1e-12
+    assert max(st["jump"]) < 1e-10
+
+
+def test_encode_is_deterministic():
+    w = SMALL["3d"]()
+    q = torch.from_numpy(_field(w)).cuda()
+    enc = _enc(w)
+    enc.encode(q, 6, 0.0)
+    a = enc.get_ctrl().cpu().numpy()
+    enc.encode(q, 6, 0.0)
+    b = enc.get_ctrl().cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_float32_input():
+    w = SMALL["3d"]()
+    S = _oracle(w)
+    Q = _field(w).astype(np.float32)
+    enc = _enc(w)
+    enc.encode(torch.from_numpy(Q).cuda(), 4, 0.0)
+    Po, _ = schwarz.encode(S, Q.astype(np.float64), 4)
+    assert _rel(enc.get_ctrl().cpu().numpy(), Po) < 1e-10
+
+
+def test_notconv_status_and_data_shape_check():
+    w = SMALL["2d"]()
+    enc = _enc(w)
+    q = torch.from_numpy(_field(w)).cuda()
+    with pytest.raises(_lib.MfaError) as ei:
+        enc.encode(q, 2, 1e-14)
+    assert ei.value.status == _lib.MFA_ENOTCONV
+    with pytest.raises(ValueError):
+        enc.encode(q[:-1].contiguous(), 2, 0.0)
