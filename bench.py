@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Benchmark of the MFA encoder hot path on one MI355X.
+
+One step = the whole hot path over one input resident in HBM: plan and
+setup (basis, normal matrices, banded Cholesky, Schwarz operators), the
+encode (N^T Q, Schwarz sweeps until the interface jumps are below the
+tolerance) and the decode of the fitted spline onto the full grid.
+
+Prints one JSON line (see the design doc for the roofline and CPU-baseline
+definitions).  Only one GPU is supported: --gpus > 1 exits with a message.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "input points encoded/s to 1e-6 rel err (mixed vs FP64); p50/p99 encode latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="3d-mixed",
+                    choices=["1d", "2d", "3d-batched", "3d-mixed"])
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--rhs", default="normal", choices=["normal", "databox"])
+    ap.add_argument("--check-every", type=int, default=0)
+    ap.add_argument("--max-sweeps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--no-validate", action="store_true")
+    return ap.parse_args()
+
+
+def get_workload(name, precision):
+    from paper_2210_06528_amd import workloads as W
+    w = {"1d": W.cfg_1d, "2d": W.cfg_2d, "3d-batched": W.cfg_3d_batched,
+         "3d-mixed": W.cfg_3d_mixed}[name]()
+    if precision:
+        w.precision = precision
+    if w.jump_tol is None:
+        w.jump_tol = 0.0
+    return w
+
+
+def cpu_baseline(w, Q, nsweeps_gpu, nsample):
+    """Oracle timed on the host: `nsample` literal sweeps of the whole workload
+    plus the final decode, extrapolated to the GPU's sweep count."""
+    from threadpoolctl import threadpool_info
+    from oracle import schwarz
+    Q64 = np.asarray(Q, dtype=np.float64)
+    t0 = time.perf_counter()
+    S = schwarz.setup(schwarz.make_plan(w.npts, w.degree, w.sizes, w.overlap))
+    t_setup = time.perf_counter() - t0
+    P = np.zeros(w.nctrl)
+    t0 = time.perf_counter()
+    for k in range(nsample):
+        P, _ = schwarz.sweep(S, Q64, P, k + 1)
+    t_sweep = (time.perf_counter() - t0) / nsample
+    t0 = time.perf_counter()
+    schwarz.decode(S, P)
+    t_dec = time.perf_counter() - t0
+    total = t_setup + t_sweep * nsweeps_gpu + t_dec
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": w.npoints / total, "unit": "points/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"{nsample} literal per-subdomain oracle sweeps of the full {w.name} input "
+                       f"({t_sweep:.2f} s/sweep) + setup + one decode, extrapolated to the "
+                       f"{nsweeps_gpu} sweeps the GPU needed"),
+            "seconds_measured": round(t_setup + t_sweep * nsample + t_dec, 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is a "
+              "design in DESIGN.md, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2210_06528_amd import _lib
+
+    w = get_workload(args.workload, args.precision)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    from paper_2210_06528_amd import workloads as W
+    Q = W.make_field(w)
+    print(f"[bench] input {w.name} {w.npts} {Q.dtype} generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    q = torch.from_numpy(np.ascontiguousarray(Q)).to(dev)
+    out_dtype = torch.float32 if Q.dtype == np.float32 else torch.float64
+    out = torch.empty(w.npts, dtype=out_dtype, device=dev)
+    enc = _lib.Encoder(w.npts, w.degree, w.sizes, w.overlap, w.precision, w.combine, args.rhs,
+                       device=dev)
+    tol = w.jump_tol or 0.0
+    max_sweeps = w.sweeps or args.max_sweeps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def step():
+        ev[0].record()
+        enc.recreate()
+        ev[1].record()
+        st = enc.encode(q, max_sweeps, tol, args.check_every)
+        ev[2].record()
+        enc.decode(out)
+        ev[3].record()
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, phases = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        st = step()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+        phases.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms = wall * 1e3 / args.steps
+    ph = np.mean(np.array(phases), axis=0)
+    print(f"[bench] {args.steps} steps, {ms:.3f} ms/step, sweeps {st['sweep']}, jumps {st['jump']}",
+          file=sys.stderr, flush=True)
+
+    res = {
+        "metric": METRIC, "value": w.npoints / (ms / 1e3), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f64"}[w.precision],
+        "data": "synthetic",
+        "config": {"workload": w.name, "npts": list(w.npts), "degree": w.degree,
+                   "nsub": list(w.nsub), "nctrl": list(w.nctrl), "overlap": w.overlap,
+                   "precision": w.precision, "rhs": args.rhs, "jump_tol": tol,
+                   "input_dtype": str(Q.dtype)},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "phases_ms": {"setup": float(ph[0]), "encode": float(ph[1]), "decode": float(ph[2])},
+        "sweeps": st["sweep"], "jump": st["jump"], "converged": st["converged"],
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(w, Q, st["sweep"], args.cpu_sweeps)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

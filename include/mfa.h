@@ -131,8 +131,11 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes,
 /* Algorithm 1 on the data q_dev (npts[0] x ... float32 or float64 device
  * array): start from the control points set by mfa_set_ctrl, else from zero
  * (the first sweep is then the decoupled local fit), and sweep until
- * max_r J_r < jump_tol, checking every `check_every` sweeps (>= 1), or until
- * max_sweeps.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
+ * max_r J_r < jump_tol or max_sweeps.  The jumps are evaluated every
+ * `check_every` sweeps; check_every <= 0 predicts the next check from the
+ * geometric decay observed between the last two checks (at most 8 sweeps
+ * apart), so the stop may come a few sweeps after the first sweep that met
+ * the tolerance.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
  * NULL) receives the statistics of the last checked sweep.  Returns
  * MFA_ENOTCONV if the tolerance was not met (the control points are still
  * the last iterate) or a non-finite value appeared.                         */

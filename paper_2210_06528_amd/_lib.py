@@ -173,6 +173,15 @@ class Encoder:
                                       ctypes.byref(h)))
         self.handle = h
 
+    def recreate(self):
+        """Destroy and re-create the handle on the same workspace (setup again)."""
+        self.close()
+        h = c_void_p(0)
+        check(self.lib.mfa_create(ctypes.byref(self.prob), c_void_p(self._ws_ptr),
+                                  c_size_t(self.ws_bytes), c_void_p(self.stream.cuda_stream),
+                                  ctypes.byref(h)))
+        self.handle = h
+
     # -- helpers
     def _dt(self, t):
         torch = self.torch

@@ -80,12 +80,58 @@ hipError_t project(Handle &h, const T *q) {
                               h.s2);
 }
 
+bool fast_sweep_ok(const Handle &h, size_t elem) {
+  for (int a = 0; a < 3; ++a)
+    if (h.ax[a].active && bsolve_lds(h.ax[a].Fmax, h.p, elem) > 64 * 1024) return false;
+  return true;
+}
+
+// Schwarz correction along every active axis with the banded-solve kernel;
+// the last axis adds the combined correction into P.
+template <typename T>
+hipError_t correct_bsolve(Handle &h, const T *g) {
+  const int n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
+  int act[3], na = 0;
+  for (int a = 0; a < 3; ++a)
+    if (h.ax[a].active) act[na++] = a;
+  const T *in = g;
+  T *bufs[2] = {reinterpret_cast<T *>(h.s1), reinterpret_cast<T *>(h.s2)};
+  for (int i = 0; i < na; ++i) {
+    const Axis &X = h.ax[act[i]];
+    const bool last = i == na - 1;
+    T *out = last ? nullptr : bufs[i & 1];
+    hipError_t e = launch_bsolve<T, T, T>(h.stream, in, out, last ? h.P : nullptr, act[i], n0, n1, n2,
+                                          h.p, X, h.combine, h.slots);
+    if (e != hipSuccess) return e;
+    in = out;
+  }
+  return hipSuccess;
+}
+
 // One sweep (NORMAL right-hand side):
 //   g = c - (A_0 x A_1 x A_2) P      (the local residuals N_F^T (Q - N P) of all
 //                                     subdomains at once)
 //   P += (M_0 x M_1 x M_2) g         (local solves with lagged ghosts and the
 //                                     1/n_s combine, Section 2.3.2)
 hipError_t sweep_normal(Handle &h) {
+  const bool low = h.precision != MFA_PREC_FP64;
+  const int n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
+  if (fast_sweep_ok(h, low ? sizeof(float) : sizeof(double))) {
+    h.g_float = low;
+    if (low) {
+      float *gf = reinterpret_cast<float *>(h.g);
+      hipError_t e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
+                                         h.ax[2].d_acoef, n0, n1, n2, h.slots);
+      if (e != hipSuccess) return e;
+      return correct_bsolve<float>(h, gf);
+    }
+    hipError_t e = launch_resid<double>(h.stream, h.p, h.P, h.c, h.g, h.ax[0].d_acoef, h.ax[1].d_acoef,
+                                        h.ax[2].d_acoef, n0, n1, n2, h.slots);
+    if (e != hipSuccess) return e;
+    return correct_bsolve<double>(h, h.g);
+  }
+  // general path: row-sparse operator passes (any segment length)
+  h.g_float = false;
   std::vector<Step> st;
   for (int a = 2; a >= 0; --a)
     if (h.ax[a].active) st.push_back({a, &h.ax[a].A});
@@ -104,31 +150,30 @@ hipError_t sweep_normal(Handle &h) {
 hipError_t sweep_metrics(Handle &h) {
   for (int a = 0; a < 3; ++a) {
     if (!h.ax[a].active || h.ax[a].B < 2) continue;
-    std::vector<Step> st{{a, &h.ax[a].J}};
-    for (int c = 0; c < 3; ++c)
-      if (c != a && h.ax[c].active) st.push_back({c, &h.ax[c].Om});
-    hipError_t e = run_chain<double, double>(h, h.g, ctrl_dims(h), st, (double *)nullptr, EPI_MAXABS,
-                                             nullptr, kSlotJ + a * kMaxP, h.ax[a].d_gidJ, a, h.s1,
-                                             h.s2);
+    hipError_t e =
+        h.g_float ? launch_pass<float, double>(h.stream, reinterpret_cast<const float *>(h.g),
+                                               ctrl_dims(h), a, h.ax[a].J, h.s1, EPI_STORE, nullptr,
+                                               h.slots, 0, nullptr, 0)
+                  : launch_pass<double, double>(h.stream, h.g, ctrl_dims(h), a, h.ax[a].J, h.s1,
+                                                EPI_STORE, nullptr, h.slots, 0, nullptr, 0);
+    if (e != hipSuccess) return e;
+    e = launch_jump_expand(h, a, h.s1);
     if (e != hipSuccess) return e;
   }
-  for (int a = 0; a < 3; ++a) {
-    if (!h.ax[a].active) continue;
-    hipError_t e = launch_pass<double, double>(h.stream, h.P, ctrl_dims(h), a, h.ax[a].D, nullptr,
-                                               EPI_MAXABS, nullptr, h.slots, kSlotS + a * kMaxP,
-                                               h.ax[a].d_gidD, a);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return launch_deriv_scale(h);
 }
 
 mfa_status read_stats(Handle &h, mfa_step_stats *out, double jump_tol, bool *finite) {
-  unsigned long long raw[kNumSlots];
-  HIP_CHECK(hipMemcpyAsync(raw, h.slots, sizeof(raw), hipMemcpyDeviceToHost, h.stream), "read stats");
+  std::vector<unsigned long long> raw((size_t)kNumSlots * kSlotCopies);
+  HIP_CHECK(hipMemcpyAsync(raw.data(), h.slots, sizeof(unsigned long long) * raw.size(),
+                           hipMemcpyDeviceToHost, h.stream), "read stats");
   HIP_CHECK(hipStreamSynchronize(h.stream), "read stats");
+  // non-negative doubles order like their bit patterns (NaN sorts above inf)
   auto val = [&](int s) {
+    unsigned long long m = 0;
+    for (int c = 0; c < kSlotCopies; ++c) m = std::max(m, raw[(size_t)s * kSlotCopies + c]);
     double d;
-    std::memcpy(&d, &raw[s], sizeof(d));
+    std::memcpy(&d, &m, sizeof(d));
     return d;
   };
   mfa_step_stats st{};
@@ -212,8 +257,8 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
     return bail(e, "zero flag");
   if ((e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0)) != hipSuccess) return bail(e, "fill P");
   for (int a = 0; a < 3; ++a) {
-    if (!h.ax[a].active) continue;
-    if ((e = setup_axis(&h, a)) != hipSuccess) return bail(e, "setup");
+    if (h.ax[a].active && (e = setup_axis(&h, a)) != hipSuccess) return bail(e, "setup");
+    if ((e = setup_acoef(&h, a)) != hipSuccess) return bail(e, "setup");
   }
   int flag = 0;
   if ((e = hipMemcpyAsync(&flag, h.flag, sizeof(int), hipMemcpyDeviceToHost, h.stream)) != hipSuccess)
@@ -239,7 +284,7 @@ static mfa_status load_q(Handle &h, const void *q, mfa_dtype dt) {
 }
 
 static mfa_status do_sweep(Handle &h, bool metrics) {
-  hipError_t e = launch_zero_slots(h.stream, h.slots, kNumSlots);
+  hipError_t e = launch_zero_slots(h.stream, h.slots, kNumSlots * kSlotCopies);
   if (e != hipSuccess) return hip_fail(e, "zero slots");
   e = sweep_normal(h);
   if (e != hipSuccess) return hip_fail(e, "sweep");
@@ -275,7 +320,6 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
   if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
   if (!q_dev) return fail(MFA_EINVAL, "null data pointer");
   if (max_sweeps < 1) return fail(MFA_EINVAL, "max_sweeps must be >= 1");
-  if (check_every < 1) return fail(MFA_EINVAL, "check_every must be >= 1");
   Handle &h = H->h;
   hipSetDevice(h.device);
   mfa_status s = load_q(h, q_dev, q_dtype);
@@ -288,22 +332,41 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
   h.warm = false;
   mfa_step_stats st{};
   bool converged = false;
+  // check schedule: fixed stride, or (check_every <= 0) predicted from the
+  // observed geometric decay of the jumps between the last two checks
+  int next_check = jump_tol > 0.0 ? (check_every > 0 ? check_every : 1) : max_sweeps;
+  double prev_j = -1.0;
+  int prev_k = 0;
   for (int k = 1; k <= max_sweeps; ++k) {
-    const bool check = (jump_tol > 0.0 && k % check_every == 0) || k == max_sweeps;
+    const bool check = k == next_check || k == max_sweeps;
     s = do_sweep(h, check);
     if (s != MFA_OK) return s;
-    if (check) {
-      bool finite = true;
-      s = read_stats(h, &st, jump_tol, &finite);
-      if (s != MFA_OK) return s;
-      if (!finite) {
-        if (last) *last = st;
-        return fail(MFA_ENOTCONV, "non-finite value in the sweep");
+    if (!check) continue;
+    bool finite = true;
+    s = read_stats(h, &st, jump_tol, &finite);
+    if (s != MFA_OK) return s;
+    if (!finite) {
+      if (last) *last = st;
+      return fail(MFA_ENOTCONV, "non-finite value in the sweep");
+    }
+    if (st.converged) {
+      converged = true;
+      break;
+    }
+    if (check_every > 0) {
+      next_check = k + check_every;
+    } else {
+      double jm = 0.0;
+      for (int r = 0; r < h.p; ++r) jm = std::max(jm, st.jump[r]);
+      int stride = 2;
+      if (prev_j > 0.0 && jm < prev_j && jm > 0.0) {
+        const double rate = std::pow(jm / prev_j, 1.0 / (k - prev_k));
+        const double need = std::log(jump_tol / jm) / std::log(rate);
+        stride = (int)std::min(8.0, std::max(1.0, std::ceil(need)));
       }
-      if (st.converged) {
-        converged = true;
-        break;
-      }
+      prev_j = jm;
+      prev_k = k;
+      next_check = k + stride;
     }
   }
   if (last) *last = st;

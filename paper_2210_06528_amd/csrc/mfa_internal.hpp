@@ -74,6 +74,10 @@ struct Axis {
   double *d_dbas_if = nullptr;       // (B-1) x p x (p+1)
   int *d_gidJ = nullptr;             // J row -> r
   int *d_gidD = nullptr;             // D row -> r
+  double *d_acoef = nullptr;         // (2p+1) x n stencil rows of A (identity if inactive)
+  int *d_choff = nullptr;            // per-block offset of the Cholesky factor
+  int *d_foff = nullptr;             // per-block offset into d_rdiag (sum of earlier |F_b|)
+  double *d_rdiag = nullptr;         // 1 / L_jj of every block's factor
   Ell N[kMaxP + 1];                  // decode tables, derivative order 0..p
   Ell NT, A, M, Om, J, D;
   // DATABOX tables
@@ -102,6 +106,7 @@ struct Handle {
   unsigned long long *slots = nullptr;   // reductions, see kSlot*
   int *flag = nullptr;                   // setup error flag
   bool have_rhs = false;
+  bool g_float = false;     // g holds float32 values (mixed precision)
   bool warm = false;        // P was set by mfa_set_ctrl: the next encode starts there
   int sweep = 0;
 };
@@ -113,6 +118,9 @@ constexpr int kSlotCtrl = 2;
 constexpr int kSlotJ = 8;                       // + a*kMaxP + r
 constexpr int kSlotS = kSlotJ + 3 * kMaxP;      // + a*kMaxP + r
 constexpr int kNumSlots = kSlotS + 3 * kMaxP;
+// each logical slot has kSlotCopies physical copies (atomics spread over them
+// to avoid serialising on one address); readers take the max over copies
+constexpr int kSlotCopies = 64;
 
 // ---------------------------------------------------------------- planner
 // Fills h->ax[*] host-side plan; returns an error message or "".
@@ -141,5 +149,24 @@ hipError_t launch_maxabs(hipStream_t st, const double *x, int64_t n, unsigned lo
 
 // setup kernels (one axis at a time)
 hipError_t setup_axis(Handle *h, int a);
+// stencil rows of A for the residual kernel (identity row for inactive axes)
+hipError_t setup_acoef(Handle *h, int a);
+
+// sweep kernels
+template <typename TG>
+hipError_t launch_resid(hipStream_t st, int p, const double *Pc, const double *c, TG *g,
+                        const double *A0, const double *A1, const double *A2, int n0, int n1, int n2,
+                        unsigned long long *slots);
+template <typename TI, typename TO, typename TC>
+hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int axis, int n0, int n1,
+                         int n2, int p, const Axis &X, int combine, unsigned long long *slots);
+// convergence metrics
+hipError_t launch_deriv_scale(Handle &h);
+hipError_t launch_jump_expand(Handle &h, int a, const double *U);
+
+// LDS bytes the banded-solve kernel needs for segments of length fmax
+inline size_t bsolve_lds(int64_t fmax, int p, size_t elem) {
+  return (size_t)2 * fmax * 64 * elem + sizeof(double) * (size_t)(p + 2) * fmax;
+}
 
 }  // namespace mfa

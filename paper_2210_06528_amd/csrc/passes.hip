@@ -9,49 +9,58 @@ namespace mfa {
 namespace {
 
 __device__ __forceinline__ void slot_max(unsigned long long *slots, int slot, double v) {
-  atomicMax(slots + slot, (unsigned long long)__double_as_longlong(v));
+  const unsigned copy =
+      (blockIdx.x * 7u + blockIdx.y * 131u + blockIdx.z * 1031u + (threadIdx.x >> 6)) % kSlotCopies;
+  atomicMax(slots + (size_t)slot * kSlotCopies + copy, (unsigned long long)__double_as_longlong(v));
 }
 
-// Wavefront max of v (non-negative) into `slot`; lanes with different slots
-// fall back to one atomic each.
+// Wavefront max of v (non-negative) into slots[slot]; lanes may name
+// different slots: one shuffle reduction and one atomic per distinct slot.
 __device__ __forceinline__ void wave_slot_max(unsigned long long *slots, int slot, double v) {
-  const int s0 = __shfl(slot, 0, 64);
-  if (__all(slot == s0)) {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    if ((threadIdx.x & 63) == 0) slot_max(slots, s0, v);
-  } else {
-    slot_max(slots, slot, v);
+  unsigned long long todo = __ballot(1);
+  const int lane = __lane_id();
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int s = __shfl(slot, leader, 64);
+    const bool mine = slot == s;
+    double x = mine ? v : 0.0;
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    if (lane == leader) slot_max(slots, s, x);
+    todo &= ~__ballot(mine);
   }
 }
 
+// One thread per output element; grid (ceil(o2/bs), o1, o0).  When the
+// operator acts on axis 0 or 1 the row is uniform over the workgroup (table
+// loads are scalar); on axis 2 each lane has its own row.
 template <typename Tin, typename Tout, int EPI>
 __global__ void __launch_bounds__(256) k_pass(const Tin *__restrict__ in, Tout *__restrict__ out,
-                                              const double *__restrict__ sub, int64_t o0,
-                                              int64_t o1, int64_t o2, int ax, int64_t rin, Ell op,
-                                              unsigned long long *slots, int slot_base,
-                                              const int *__restrict__ gid, int gaxis) {
-  const int64_t total = o0 * o1 * o2;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = idx < total;
+                                              const double *__restrict__ sub, int o0, int o1, int o2,
+                                              int ax, int rin, Ell op, unsigned long long *slots,
+                                              int slot_base, const int *__restrict__ gid, int gaxis) {
+  const int x2 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int x1 = blockIdx.y, x0 = blockIdx.z;
+  const bool valid = x2 < o2;
   double acc = 0.0;
   int slot = slot_base;
   if (valid) {
-    int64_t x[3];
-    x[2] = idx % o2;
-    const int64_t t = idx / o2;
-    x[1] = t % o1;
-    x[0] = t / o1;
-    const int64_t row = x[ax];
-    if (EPI == EPI_MAXABS && gid != nullptr) slot = slot_base + gid[x[gaxis]];
-    const int64_t i1 = ax == 1 ? rin : o1;
-    const int64_t i2 = ax == 2 ? rin : o2;
-    const int64_t stride = ax == 2 ? 1 : (ax == 1 ? i2 : i1 * i2);
-    x[ax] = 0;
-    const int64_t base = (x[0] * i1 + x[1]) * i2 + x[2];
-    const int *cl = op.col + row * op.L;
-    const double *vl = op.val + row * op.L;
+    const int row = ax == 0 ? x0 : (ax == 1 ? x1 : x2);
+    if (EPI == EPI_MAXABS && gid != nullptr) slot = slot_base + gid[gaxis == 0 ? x0 : (gaxis == 1 ? x1 : x2)];
+    const int *cl = op.col + (int64_t)row * op.L;
+    const double *vl = op.val + (int64_t)row * op.L;
     const int ln = op.len[row];
-    for (int q = 0; q < ln; ++q) acc += vl[q] * (double)in[base + (int64_t)cl[q] * stride];
+    if (ax == 0) {
+      const int64_t plane = (int64_t)o1 * o2;
+      const Tin *src = in + (int64_t)x1 * o2 + x2;
+      for (int q = 0; q < ln; ++q) acc += vl[q] * (double)src[(int64_t)cl[q] * plane];
+    } else if (ax == 1) {
+      const Tin *src = in + (int64_t)x0 * rin * o2 + x2;
+      for (int q = 0; q < ln; ++q) acc += vl[q] * (double)src[(int64_t)cl[q] * o2];
+    } else {
+      const Tin *src = in + ((int64_t)x0 * o1 + x1) * rin;
+      for (int q = 0; q < ln; ++q) acc += vl[q] * (double)src[cl[q]];
+    }
+    const int64_t idx = ((int64_t)x0 * o1 + x1) * o2 + x2;
     if (EPI == EPI_STORE) {
       out[idx] = (Tout)acc;
     } else if (EPI == EPI_SUBFROM) {
@@ -92,26 +101,29 @@ hipError_t launch_pass(hipStream_t st, const Tin *in, Dims in_dims, int ax, cons
                        int slot_base, const int *gid, int gaxis) {
   Dims od = in_dims;
   od.d[ax] = op.R;
-  const int64_t total = od.total();
-  if (total == 0) return hipSuccess;
-  const unsigned grid = nblk(total, 256);
-  const int64_t rin = in_dims.d[ax];
+  if (od.total() == 0) return hipSuccess;
+  if (od.d[0] > 65535 || od.d[1] > 65535 || od.total() >= (1LL << 31) ||
+      in_dims.total() >= (1LL << 31))
+    return hipErrorInvalidValue;
+  const int bs = od.d[2] >= 256 ? 256 : (int)((od.d[2] + 63) / 64) * 64;
+  const dim3 grid(nblk(od.d[2], bs), (unsigned)od.d[1], (unsigned)od.d[0]);
+  const int o0 = (int)od.d[0], o1 = (int)od.d[1], o2 = (int)od.d[2], rin = (int)in_dims.d[ax];
   switch (epi) {
     case EPI_STORE:
-      k_pass<Tin, Tout, EPI_STORE><<<grid, 256, 0, st>>>(in, out, sub, od.d[0], od.d[1], od.d[2], ax,
-                                                         rin, op, slots, slot_base, gid, gaxis);
+      k_pass<Tin, Tout, EPI_STORE><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op, slots,
+                                                         slot_base, gid, gaxis);
       break;
     case EPI_SUBFROM:
-      k_pass<Tin, Tout, EPI_SUBFROM><<<grid, 256, 0, st>>>(in, out, sub, od.d[0], od.d[1], od.d[2],
-                                                           ax, rin, op, slots, slot_base, gid, gaxis);
+      k_pass<Tin, Tout, EPI_SUBFROM><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op,
+                                                           slots, slot_base, gid, gaxis);
       break;
     case EPI_ADDTO:
-      k_pass<Tin, Tout, EPI_ADDTO><<<grid, 256, 0, st>>>(in, out, sub, od.d[0], od.d[1], od.d[2], ax,
-                                                         rin, op, slots, slot_base, gid, gaxis);
+      k_pass<Tin, Tout, EPI_ADDTO><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op, slots,
+                                                         slot_base, gid, gaxis);
       break;
     default:
-      k_pass<Tin, Tout, EPI_MAXABS><<<grid, 256, 0, st>>>(in, out, sub, od.d[0], od.d[1], od.d[2], ax,
-                                                          rin, op, slots, slot_base, gid, gaxis);
+      k_pass<Tin, Tout, EPI_MAXABS><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op, slots,
+                                                          slot_base, gid, gaxis);
       break;
   }
   return hipGetLastError();

@@ -237,7 +237,11 @@ size_t layout_workspace(Handle *h, char *base) {
   const bool mixed = h->precision != MFA_PREC_FP64;
   for (int ia = 0; ia < 3; ++ia) {
     Axis &X = h->ax[ia];
+    X.d_acoef = bp.take<double>((int64_t)(2 * p + 1) * X.n);
     if (!X.active) continue;
+    X.d_choff = bp.take<int>(X.B);
+    X.d_foff = bp.take<int>(X.B);
+    X.d_rdiag = bp.take<double>(X.SF);
     const int n = X.n;
     const int64_t m = X.m;
     const int nif = X.B - 1;
@@ -351,7 +355,7 @@ size_t layout_workspace(Handle *h, char *base) {
     h->b1n = b1;
     h->b2n = b2;
   }
-  h->slots = bp.take<unsigned long long>(kNumSlots);
+  h->slots = bp.take<unsigned long long>((int64_t)kNumSlots * kSlotCopies);
   h->flag = bp.take<int>(4);
   return bp.off + 256;
 }

@@ -135,11 +135,14 @@ __global__ void __launch_bounds__(64) k_gram(int64_t m, int n, int p, const int 
 // One wavefront per matrix: lane 0 forms the pivot of column j, lanes 1..p
 // the subdiagonal entries.  A non-positive pivot sets flag[0].
 __global__ void __launch_bounds__(64) k_chol(int n, int p, const double *band, const int *blk,
-                                             double *chol, int *flag) {
+                                             double *chol, double *rdiag, int *flag) {
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
-  int64_t off = 0;
-  for (int bb = 0; bb < b; ++bb) off += (int64_t)(p + 1) * (blk[8 * bb + 3] - blk[8 * bb + 2]);
+  int64_t off = 0, roff = 0;
+  for (int bb = 0; bb < b; ++bb) {
+    off += (int64_t)(p + 1) * (blk[8 * bb + 3] - blk[8 * bb + 2]);
+    roff += blk[8 * bb + 3] - blk[8 * bb + 2];
+  }
   const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
   double *L = chol + off;  // L[t*F + j] = L(j+t, j)
   for (int j = 0; j < F; ++j) {
@@ -155,6 +158,7 @@ __global__ void __launch_bounds__(64) k_chol(int n, int p, const double *band, c
         s = 1.0;
       }
       L[j] = sqrt(s);
+      rdiag[roff + j] = 1.0 / L[j];
     }
     __syncthreads();
     if (lane >= 1 && lane <= p) {
@@ -450,9 +454,36 @@ __global__ void k_tab_Comb(int n, int combine, const int *blk, const int *blo, c
   pad_row(t, k, len);
 }
 
+// stencil rows: acoef[k*(2p+1) + t] = A[k][k-p+t], zero outside the matrix
+__global__ void k_acoef(int n, int p, const double *band, double *acoef) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  for (int t = 0; t <= 2 * p; ++t) {
+    const int c = k - p + t;
+    double v = 0.0;
+    if (c >= 0 && c < n) v = band[(int64_t)abs(k - c) * n + min(k, c)];
+    acoef[(int64_t)k * (2 * p + 1) + t] = v;
+  }
+}
+
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
+
+hipError_t setup_acoef(Handle *h, int ia) {
+  Axis &X = h->ax[ia];
+  const int p = h->p;
+  if (!X.active) {
+    std::vector<double> id(2 * p + 1, 0.0);
+    id[p] = 1.0;
+    hipError_t e = hipMemcpyAsync(X.d_acoef, id.data(), sizeof(double) * id.size(),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(h->stream);
+  }
+  k_acoef<<<nblk(X.n, 128), 128, 0, h->stream>>>(X.n, p, X.d_gram, X.d_acoef);
+  return hipGetLastError();
+}
 
 #define MFA_TRY(x)                       \
   do {                                   \
@@ -479,6 +510,13 @@ hipError_t setup_axis(Handle *h, int ia) {
   MFA_TRY(hipMemcpyAsync(X.d_owner, X.owner.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
   MFA_TRY(hipMemcpyAsync(X.d_ns, X.ns.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
   MFA_TRY(hipMemcpyAsync(X.d_pown, X.pown.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
+  std::vector<int> choff(B), foff(B);
+  for (int b = 0; b < B; ++b) {
+    choff[b] = (int)X.chol_off[b];
+    foff[b] = (int)X.foff[b];
+  }
+  MFA_TRY(hipMemcpyAsync(X.d_choff, choff.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+  MFA_TRY(hipMemcpyAsync(X.d_foff, foff.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
   if (nif > 0) {
     MFA_TRY(hipMemcpyAsync(X.d_ustar, X.ustar.data(), sizeof(double) * nif, hipMemcpyHostToDevice, st));
     MFA_TRY(hipMemcpyAsync(X.d_span_if, X.span_if.data(), sizeof(int) * nif, hipMemcpyHostToDevice, st));
@@ -499,7 +537,7 @@ hipError_t setup_axis(Handle *h, int ia) {
   }
   k_gram<<<n, 64, 0, st>>>(m, n, p, X.d_span, X.N[0], X.d_gram);
   MFA_TRY(hipGetLastError());
-  k_chol<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, h->flag);
+  k_chol<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
   MFA_TRY(hipGetLastError());
   k_inverse<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
   MFA_TRY(hipGetLastError());

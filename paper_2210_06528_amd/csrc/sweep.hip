@@ -1,0 +1,386 @@
+// Schwarz sweep kernels on the control grid.
+//
+//  k_resid  : g = c - (A_0 x A_1 x A_2) P, the local right-hand sides
+//             N_F^T (Q - N P) of every subdomain at once (A_a = N_a^T N_a is
+//             banded with half-width p).  One fused 3-D stencil: axis 2 and 1
+//             from an LDS tile, axis 0 streamed through a register ring.
+//  k_bsolve : the weighted additive-Schwarz correction along one axis,
+//             out = sum_b w_b R_b^T (L_b L_b^T)^{-1} R_b in, by forward and
+//             backward substitution with every subdomain's banded Cholesky
+//             factor (the batched banded solves), one line per lane, the
+//             1/n_s combine of overlapping segments done in LDS.
+#include <hip/hip_bf16.h>
+
+#include "mfa_internal.hpp"
+
+namespace mfa {
+
+namespace {
+
+__device__ __forceinline__ void slot_max_c(unsigned long long *slots, int slot, double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) {
+    const unsigned copy =
+        (blockIdx.x * 7u + blockIdx.y * 131u + blockIdx.z * 1031u + (threadIdx.x >> 6)) % kSlotCopies;
+    atomicMax(slots + (size_t)slot * kSlotCopies + copy, (unsigned long long)__double_as_longlong(v));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ double to_d(T v) {
+  return (double)v;
+}
+template <>
+__device__ __forceinline__ double to_d<__hip_bfloat16>(__hip_bfloat16 v) {
+  return (double)__bfloat162float(v);
+}
+template <typename T>
+__device__ __forceinline__ T from_d(double v) {
+  return (T)v;
+}
+template <>
+__device__ __forceinline__ __hip_bfloat16 from_d<__hip_bfloat16>(double v) {
+  return __float2bfloat16((float)v);
+}
+
+constexpr int kTZ = 64;   // z outputs per workgroup (one per lane)
+constexpr int kTY = 16;   // y outputs per workgroup
+constexpr int kRY = 4;    // y outputs per thread
+
+// Coefficient tables Aa[k*(2P+1) + t] = A_a[k][k-P+t] (0 outside the matrix);
+// an inactive axis (length 1) has the identity row.
+template <int P, typename TG>
+__global__ void __launch_bounds__(256) k_resid(const double *__restrict__ Pc,
+                                               const double *__restrict__ c, TG *__restrict__ g,
+                                               const double *__restrict__ A0,
+                                               const double *__restrict__ A1,
+                                               const double *__restrict__ A2, int n0, int n1, int n2,
+                                               int xchunk, unsigned long long *slots) {
+  constexpr int W = 2 * P + 1;
+  constexpr int LY = kTY + 2 * P;
+  constexpr int LZ = kTZ + 2 * P;
+  __shared__ double tile[LY][LZ + 1];
+  __shared__ double tz[LY][kTZ + 1];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int z0 = blockIdx.x * kTZ, y0 = blockIdx.y * kTY, x0 = blockIdx.z * xchunk;
+  const int x1 = min(n0, x0 + xchunk);
+  const int gz = z0 + tx;
+  const double *az = A2 + (int64_t)min(gz, n2 - 1) * W;
+  double azr[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) azr[t] = az[t];
+  double ring[W][kRY];
+#pragma unroll
+  for (int t = 0; t < W; ++t)
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) ring[t][r] = 0.0;
+  double nres = 0.0;
+  // the tile of the next plane is loaded into registers while the current
+  // plane is computed (software pipelining of the global loads)
+  constexpr int NE = (LY * LZ + 255) / 256;
+  double pre[NE];
+  auto gload = [&](int xi) {
+    const bool xin = xi >= 0 && xi < n0;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int yy = e / LZ, zz = e - yy * LZ;
+      const int gy = y0 - P + yy, gzz = z0 - P + zz;
+      double v = 0.0;
+      if (e < LY * LZ && xin && gy >= 0 && gy < n1 && gzz >= 0 && gzz < n2)
+        v = Pc[((int64_t)xi * n1 + gy) * n2 + gzz];
+      pre[i] = v;
+    }
+  };
+  gload(x0 - P);
+  for (int xi = x0 - P; xi < x1 + P; ++xi) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < LY * LZ) {
+        const int yy = e / LZ, zz = e - yy * LZ;
+        tile[yy][zz] = pre[i];
+      }
+    }
+    __syncthreads();
+    if (xi + 1 < x1 + P) gload(xi + 1);
+    for (int yy = ty; yy < LY; yy += 4) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < W; ++t) s += azr[t] * tile[yy][tx + t];
+      tz[yy][tx] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) {
+      const int yl = ty * kRY + r;
+      const double *ay = A1 + (int64_t)min(y0 + yl, n1 - 1) * W;
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < W; ++t) s += ay[t] * tz[yl + t][tx];
+#pragma unroll
+      for (int t = 0; t < W - 1; ++t) ring[t][r] = ring[t + 1][r];
+      ring[W - 1][r] = s;
+    }
+    const int xo = xi - P;
+    if (xo >= x0 && xo < x1) {
+      const double *ax = A0 + (int64_t)xo * W;
+#pragma unroll
+      for (int r = 0; r < kRY; ++r) {
+        const int gy = y0 + ty * kRY + r;
+        if (gy < n1 && gz < n2) {
+          double s = 0.0;
+#pragma unroll
+          for (int t = 0; t < W; ++t) s += ax[t] * ring[t][r];
+          const int64_t idx = ((int64_t)xo * n1 + gy) * n2 + gz;
+          const double gv = c[idx] - s;
+          g[idx] = from_d<TG>(gv);
+          nres = fmax(nres, fabs(gv));
+        }
+      }
+    }
+  }
+  slot_max_c(slots, kSlotNres, nres);
+}
+
+// Line geometry of an axis pass on an (n0, n1, n2) array: `nlines` lines of
+// length `len`, element j of line l at base(l) + j*stride.
+struct LineGeom {
+  int axis;   // 0, 1, 2
+  int n0, n1, n2;
+};
+
+__device__ __forceinline__ int64_t line_base(const LineGeom &G, int64_t l) {
+  if (G.axis == 0) return l;                                    // l = y*n2 + z
+  if (G.axis == 1) return (l / G.n2) * (int64_t)G.n1 * G.n2 + (l % G.n2);  // l = x*n2 + z
+  return l * G.n2;                                              // l = x*n1 + y
+}
+
+__device__ __forceinline__ int64_t line_stride(const LineGeom &G) {
+  return G.axis == 0 ? (int64_t)G.n1 * G.n2 : (G.axis == 1 ? G.n2 : 1);
+}
+
+// Weighted additive-Schwarz correction along one axis, 64 lines per
+// workgroup (one per lane).  For every subdomain b of the axis, in order:
+//  1. the factor L_b (band, (P+1) x F) and its reciprocal pivots go to LDS;
+//  2. the segment F_b of each line goes to LDS (coalesced: lanes over lines
+//     for axes 0/1; lanes over the contiguous segment for axis 2);
+//  3. forward then backward substitution, the last P values of the
+//     recurrence kept in registers;
+//  4. positions [F0_b, F0_{b+1}) are final: the part shared with the previous
+//     segment sums the two ping-pong buffers with weight 1/n_s (AVG), or takes
+//     the owner's value (RAS).  Axis 2 stages them in LDS (in the buffer of
+//     the previous segment, compacted in place) and stores them coalesced.
+// MODE 0 stores the correction, MODE 1 adds it to `pc` (the control points)
+// and reduces max |correction|.
+template <typename TI, typename TO, typename TC, int MODE, int P>
+__global__ void __launch_bounds__(64) k_bsolve(const TI *__restrict__ in, TO *__restrict__ out,
+                                               double *__restrict__ pc, LineGeom G, int64_t nlines,
+                                               int B, const int *__restrict__ blk,
+                                               const int *__restrict__ choff,
+                                               const double *__restrict__ chol,
+                                               const int *__restrict__ foff,
+                                               const double *__restrict__ rdiag,
+                                               const int *__restrict__ ns, int combine, int flen,
+                                               unsigned long long *slots) {
+  extern __shared__ double smem_d[];
+  double *fac = smem_d;                             // [(P+1) * flen]
+  double *rdl = smem_d + (P + 1) * flen;            // [flen]
+  TC *buf = reinterpret_cast<TC *>(smem_d + (P + 2) * flen);   // [2][flen][64]
+  const int lane = threadIdx.x;
+  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  const int64_t l = l0 + lane;
+  const bool valid = l < nlines;
+  const int64_t stride = line_stride(G);
+  const int64_t base = valid ? line_base(G, l) : 0;
+  const bool inner = G.axis == 2;
+  const int nin = (int)min<int64_t>(64, nlines - l0);   // lines in this workgroup
+  double dmax = 0.0;
+  int prevF0 = 0, prevF1 = 0;
+  for (int b = 0; b < B; ++b) {
+    TC *cur = buf + (size_t)(b & 1) * flen * 64;
+    TC *prv = buf + (size_t)((b + 1) & 1) * flen * 64;
+    const int F0 = blk[8 * b + 2], F1 = blk[8 * b + 3], F = F1 - F0;
+    const int c0 = blk[8 * b + 0], c1 = blk[8 * b + 1];
+    __syncthreads();   // previous segment's readers of fac/rdl/buffers are done
+    {
+      const double *L = chol + choff[b];
+      for (int e = lane; e < (P + 1) * F; e += 64) fac[e] = L[e];
+      const double *rd = rdiag + foff[b];
+      for (int e = lane; e < F; e += 64) rdl[e] = rd[e];
+    }
+    if (inner) {
+      for (int e = lane; e < nin * F; e += 64) {
+        const int li = e / F, j = e - li * F;
+        cur[j * 64 + li] = (TC)to_d(in[(l0 + li) * G.n2 + F0 + j]);
+      }
+    } else if (valid) {
+      for (int j = 0; j < F; ++j) cur[j * 64 + lane] = (TC)to_d(in[base + (int64_t)(F0 + j) * stride]);
+    }
+    __syncthreads();
+    // forward: L y = s;  w[t] = y_{j-1-t}
+    {
+      TC w[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) w[t] = (TC)0;
+      for (int j = 0; j < F; ++j) {
+        TC s = cur[j * 64 + lane];
+#pragma unroll
+        for (int t = 1; t <= P; ++t) s -= (TC)fac[t * F + (j - t)] * w[t - 1];
+        const TC y = s * (TC)rdl[j];
+#pragma unroll
+        for (int t = P - 1; t > 0; --t) w[t] = w[t - 1];
+        w[0] = y;
+        cur[j * 64 + lane] = y;
+      }
+    }
+    // backward: L^T x = y;  w[t] = x_{j+1+t}
+    {
+      TC w[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) w[t] = (TC)0;
+      for (int j = F - 1; j >= 0; --j) {
+        TC s = cur[j * 64 + lane];
+#pragma unroll
+        for (int t = 1; t <= P; ++t) s -= (TC)fac[t * F + j] * w[t - 1];
+        const TC x = s * (TC)rdl[j];
+#pragma unroll
+        for (int t = P - 1; t > 0; --t) w[t] = w[t - 1];
+        w[0] = x;
+        cur[j * 64 + lane] = x;
+      }
+    }
+    // combine the final positions of this segment
+    const int whi = b + 1 < B ? blk[8 * (b + 1) + 2] : F1;
+    const int pc0 = b > 0 ? blk[8 * (b - 1) + 0] : 0, pc1 = b > 0 ? blk[8 * (b - 1) + 1] : 0;
+    for (int k = F0; k < whi; ++k) {
+      double v;
+      if (combine == MFA_COMBINE_RAS) {
+        if (k >= c0 && k < c1) v = (double)cur[(k - F0) * 64 + lane];
+        else if (b > 0 && k < prevF1 && k >= pc0 && k < pc1) v = (double)prv[(k - prevF0) * 64 + lane];
+        else v = 0.0;
+      } else {
+        v = (double)cur[(k - F0) * 64 + lane];
+        if (b > 0 && k < prevF1) v += (double)prv[(k - prevF0) * 64 + lane];
+        v /= (double)ns[k];
+      }
+      if (MODE == 1) dmax = fmax(dmax, valid ? fabs(v) : 0.0);
+      if (inner) {
+        // in place: slot k-F0 <= k-prevF0, already read for this and earlier k
+        prv[(k - F0) * 64 + lane] = (TC)v;
+      } else if (valid) {
+        const int64_t o = base + (int64_t)k * stride;
+        if (MODE == 0) out[o] = from_d<TO>(v);
+        else pc[o] = pc[o] + v;
+      }
+    }
+    if (inner) {
+      __syncthreads();
+      const int W = whi - F0;
+      for (int e = lane; e < nin * W; e += 64) {
+        const int li = e / W, j = e - li * W;
+        const int64_t o = (l0 + li) * G.n2 + F0 + j;
+        const double v = (double)prv[j * 64 + li];
+        if (MODE == 0) out[o] = from_d<TO>(v);
+        else pc[o] = pc[o] + v;
+      }
+    }
+    prevF0 = F0;
+    prevF1 = F1;
+  }
+  if (MODE == 1) slot_max_c(slots, kSlotMaxDP, dmax);
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <int P, typename TG>
+hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG *g, const double *A0,
+                          const double *A1, const double *A2, int n0, int n1, int n2,
+                          unsigned long long *slots) {
+  const int byz = (int)(nblk(n2, kTZ) * nblk(n1, kTY));
+  // enough workgroups to fill the chip; the x halo (2p planes) is re-read
+  int xchunk = n0;
+  const int target = 1024;
+  if (byz * 1 < target) xchunk = std::max(4, (int)((int64_t)n0 * byz / target));
+  xchunk = std::min(xchunk, n0);
+  const dim3 grid(nblk(n2, kTZ), nblk(n1, kTY), nblk(n0, xchunk));
+  k_resid<P, TG><<<grid, 256, 0, st>>>(Pc, c, g, A0, A1, A2, n0, n1, n2, xchunk, slots);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename TG>
+hipError_t launch_resid(hipStream_t st, int p, const double *Pc, const double *c, TG *g,
+                        const double *A0, const double *A1, const double *A2, int n0, int n1, int n2,
+                        unsigned long long *slots) {
+  switch (p) {
+#define MFA_RESID_CASE(PP) \
+  case PP:                 \
+    return launch_resid_p<PP, TG>(st, Pc, c, g, A0, A1, A2, n0, n1, n2, slots);
+    MFA_RESID_CASE(1)
+    MFA_RESID_CASE(2)
+    MFA_RESID_CASE(3)
+    MFA_RESID_CASE(4)
+    MFA_RESID_CASE(5)
+    MFA_RESID_CASE(6)
+    MFA_RESID_CASE(7)
+    MFA_RESID_CASE(8)
+#undef MFA_RESID_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename TI, typename TO, typename TC>
+hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int axis, int n0, int n1,
+                         int n2, int p, const Axis &X, int combine, unsigned long long *slots) {
+  LineGeom G{axis, n0, n1, n2};
+  const int64_t len = axis == 0 ? n0 : (axis == 1 ? n1 : n2);
+  const int64_t nlines = (int64_t)n0 * n1 * n2 / len;
+  const int flen = (int)X.Fmax;
+  const size_t lds = bsolve_lds(flen, p, sizeof(TC));
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  const unsigned grid = nblk(nlines, 64);
+  switch (p * 2 + (pc ? 1 : 0)) {
+#define MFA_BS_CASE(PP)                                                                              \
+  case 2 * PP:                                                                                       \
+    k_bsolve<TI, TO, TC, 0, PP><<<grid, 64, lds, st>>>(in, out, pc, G, nlines, X.B, X.d_blk,         \
+                                                       X.d_choff, X.d_chol, X.d_foff, X.d_rdiag,     \
+                                                       X.d_ns, combine, flen, slots);                \
+    break;                                                                                           \
+  case 2 * PP + 1:                                                                                   \
+    k_bsolve<TI, TO, TC, 1, PP><<<grid, 64, lds, st>>>(in, out, pc, G, nlines, X.B, X.d_blk,         \
+                                                       X.d_choff, X.d_chol, X.d_foff, X.d_rdiag,     \
+                                                       X.d_ns, combine, flen, slots);                \
+    break;
+    MFA_BS_CASE(1)
+    MFA_BS_CASE(2)
+    MFA_BS_CASE(3)
+    MFA_BS_CASE(4)
+    MFA_BS_CASE(5)
+    MFA_BS_CASE(6)
+    MFA_BS_CASE(7)
+    MFA_BS_CASE(8)
+#undef MFA_BS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_resid<double>(hipStream_t, int, const double *, const double *, double *,
+                                         const double *, const double *, const double *, int, int, int,
+                                         unsigned long long *);
+template hipError_t launch_resid<float>(hipStream_t, int, const double *, const double *, float *,
+                                        const double *, const double *, const double *, int, int, int,
+                                        unsigned long long *);
+template hipError_t launch_bsolve<double, double, double>(hipStream_t, const double *, double *,
+                                                          double *, int, int, int, int, int,
+                                                          const Axis &, int, unsigned long long *);
+template hipError_t launch_bsolve<float, float, float>(hipStream_t, const float *, float *, double *,
+                                                       int, int, int, int, int, const Axis &, int,
+                                                       unsigned long long *);
+
+}  // namespace mfa
