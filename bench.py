@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--check-every", type=int, default=0)
     ap.add_argument("--max-sweeps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-validate", action="store_true")
     return ap.parse_args()
 
@@ -49,6 +49,39 @@ def get_workload(name, precision):
     if w.jump_tol is None:
         w.jump_tol = 0.0
     return w
+
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, datasheet
+
+
+def roofline(w, ktimes, sweeps_total):
+    """Roofline of the dominant single kernel of the sweep (HBM bound).
+
+    Algorithmic bytes per launch: every array element the kernel must touch,
+    once: the residual stencil reads P and N^T Q (float64) and writes g; a
+    correction pass reads its input and writes its output, the last axis also
+    reads and writes P (float64).  Sizes are per control point.
+    """
+    nc = int(np.prod(w.nctrl))
+    gb = 4 if w.precision != "fp64" else 8
+    d = w.dim
+    resid_bytes = nc * (8 + 8 + gb)
+    corr_bytes = nc * ((d - 1) * 2 * gb + (gb + 16)) / d     # mean over the d axis passes
+    cands = {}
+    for k, per in (("resid", resid_bytes), ("correct", corr_bytes)):
+        ms, n = ktimes.get(k, (0.0, 0))
+        if n > 0 and ms > 0:
+            cands[k] = (ms, n, per)
+    if not cands:
+        return None
+    k = max(cands, key=lambda kk: cands[kk][0])
+    ms, n, per = cands[k]
+    avg_s = ms / n / 1e3
+    ach = per / avg_s / 1e9
+    return {"kernel": {"resid": "k_resid", "correct": "k_bsolve"}[k], "bound": "hbm",
+            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "bytes_per_launch": per, "avg_launch_us": avg_s * 1e6,
+            "launches": n}
 
 
 def cpu_baseline(w, Q, nsweeps_gpu, nsample):
@@ -106,6 +139,7 @@ def main():
     def step():
         ev[0].record()
         enc.recreate()
+        enc.set_timing(True)
         ev[1].record()
         st = enc.encode(q, max_sweeps, tol, args.check_every)
         ev[2].record()
@@ -116,7 +150,8 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    lat, phases = [], []
+    lat, phases, ktimes = [], [], {}
+    sweeps_total = 0
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -125,6 +160,11 @@ def main():
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - ts) * 1e3)
         phases.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
+        sweeps_total += st["sweep"]
+        for k in _lib.KERNEL_CLASSES:
+            ms_k, n_k = enc.kernel_time(k)
+            a, b = ktimes.get(k, (0.0, 0))
+            ktimes[k] = (a + ms_k, b + n_k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms = wall * 1e3 / args.steps
@@ -146,6 +186,9 @@ def main():
         "phases_ms": {"setup": float(ph[0]), "encode": float(ph[1]), "decode": float(ph[2])},
         "sweeps": st["sweep"], "jump": st["jump"], "converged": st["converged"],
     }
+    res["kernels_ms"] = {k: {"total_ms": v[0] / args.steps, "launches": v[1] / args.steps}
+                         for k, v in ktimes.items()}
+    res["roofline"] = roofline(w, ktimes, sweeps_total)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, Q, st["sweep"], args.cpu_sweeps)

@@ -132,10 +132,10 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes,
  * array): start from the control points set by mfa_set_ctrl, else from zero
  * (the first sweep is then the decoupled local fit), and sweep until
  * max_r J_r < jump_tol or max_sweeps.  The jumps are evaluated every
- * `check_every` sweeps; check_every <= 0 predicts the next check from the
- * geometric decay observed between the last two checks (at most 8 sweeps
- * apart), so the stop may come a few sweeps after the first sweep that met
- * the tolerance.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
+ * `check_every` sweeps; check_every <= 0 checks at sweeps 4 and 8 and then
+ * at the sweep predicted from the geometric decay observed between the last
+ * two checks (at most 32 sweeps apart), so the stop may come a few sweeps
+ * after the first sweep that met the tolerance.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
  * NULL) receives the statistics of the last checked sweep.  Returns
  * MFA_ENOTCONV if the tolerance was not met (the control points are still
  * the last iterate) or a non-finite value appeared.                         */
@@ -180,6 +180,23 @@ typedef enum {
 } mfa_table;
 mfa_status mfa_inspect(mfa_handle *h, int32_t table, int32_t axis, int32_t block,
                        double *host_out, size_t count, size_t *needed);
+
+/* Per-kernel event timing (measurement support).  With enable != 0 the
+ * library records a HIP event pair on its stream around every launch of each
+ * kernel class below; mfa_kernel_time synchronises the stream and returns the
+ * summed duration in milliseconds and the number of launches of one class
+ * since timing was enabled (or since the class was last read, which resets
+ * it).  Disabled by default; enabling costs two event records per launch.  */
+typedef enum {
+  MFA_K_PROJECT = 0,   /* c = N^T Q passes                                 */
+  MFA_K_RESID = 1,     /* residual stencil g = c - N^T N P                 */
+  MFA_K_CORRECT = 2,   /* Schwarz correction passes (banded solves)        */
+  MFA_K_METRICS = 3,   /* interface jumps and derivative scales            */
+  MFA_K_DECODE = 4,    /* decode passes                                    */
+  MFA_K_COUNT = 5
+} mfa_kernel_class;
+mfa_status mfa_set_timing(mfa_handle *h, int32_t enable);
+mfa_status mfa_kernel_time(mfa_handle *h, int32_t kclass, double *total_ms, int64_t *launches);
 
 /* Release the handle (not the caller-owned workspace).  NULL is ignored.   */
 void mfa_destroy(mfa_handle *h);

@@ -27,7 +27,9 @@ STATUS_NAMES = {0: "MFA_OK", -1: "MFA_EINVAL", -2: "MFA_ENOMEM", -3: "MFA_EDEVIC
 
 # every entry point the header declares
 EXPORTS = ["mfa_workspace_size", "mfa_create", "mfa_encode", "mfa_schwarz_step", "mfa_decode",
-           "mfa_get_ctrl", "mfa_set_ctrl", "mfa_inspect", "mfa_destroy", "mfa_last_error"]
+           "mfa_get_ctrl", "mfa_set_ctrl", "mfa_inspect", "mfa_set_timing", "mfa_kernel_time",
+           "mfa_destroy", "mfa_last_error"]
+KERNEL_CLASSES = {"project": 0, "resid": 1, "correct": 2, "metrics": 3, "decode": 4}
 
 
 class mfa_problem(ctypes.Structure):
@@ -98,6 +100,10 @@ def load(path=LIB_PATH):
     lib.mfa_inspect.argtypes = [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double), c_size_t,
                                 POINTER(c_size_t)]
     lib.mfa_inspect.restype = c_int32
+    lib.mfa_set_timing.argtypes = [c_void_p, c_int32]
+    lib.mfa_set_timing.restype = c_int32
+    lib.mfa_kernel_time.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]
+    lib.mfa_kernel_time.restype = c_int32
     lib.mfa_destroy.argtypes = [c_void_p]
     lib.mfa_destroy.restype = None
     lib.mfa_last_error.argtypes = []
@@ -251,6 +257,16 @@ class Encoder:
             raise ValueError("control points must be float64 of shape %s" % (self.nctrl,))
         ctrl = ctrl.contiguous()
         check(self.lib.mfa_set_ctrl(self.handle, c_void_p(ctrl.data_ptr()), 1))
+
+    def set_timing(self, enable=True):
+        check(self.lib.mfa_set_timing(self.handle, 1 if enable else 0))
+
+    def kernel_time(self, kclass):
+        """(total ms, launches) of one kernel class since the last read."""
+        ms, n = c_double(0.0), c_int64(0)
+        cid = KERNEL_CLASSES[kclass] if isinstance(kclass, str) else int(kclass)
+        check(self.lib.mfa_kernel_time(self.handle, cid, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def inspect(self, table, axis=0, block=0):
         need = c_size_t(0)

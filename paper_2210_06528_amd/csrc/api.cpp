@@ -14,6 +14,43 @@ struct mfa_handle {
   Handle h;
 };
 
+namespace mfa {
+
+Handle::~Handle() {
+  for (auto &v : ev_used)
+    for (auto &pr : v) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+  for (auto e : ev_pool) hipEventDestroy(e);
+}
+
+static hipEvent_t take_event(Handle &h) {
+  if (!h.ev_pool.empty()) {
+    hipEvent_t e = h.ev_pool.back();
+    h.ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+TimeScope::TimeScope(Handle &hh, int c) : h(hh), cls(c) {
+  if (!h.timing) return;
+  e0 = take_event(h);
+  e1 = take_event(h);
+  if (e0) hipEventRecord(e0, h.stream);
+}
+
+TimeScope::~TimeScope() {
+  if (!h.timing || !e0 || !e1) return;
+  hipEventRecord(e1, h.stream);
+  h.ev_used[cls].push_back({e0, e1});
+}
+
+}  // namespace mfa
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -73,6 +110,7 @@ hipError_t run_chain(Handle &h, const Tin *in, Dims d, const std::vector<Step> &
 // c = N^T Q (every active axis, innermost first)
 template <typename T>
 hipError_t project(Handle &h, const T *q) {
+  TimeScope ts(h, MFA_K_PROJECT);
   std::vector<Step> st;
   for (int a = 2; a >= 0; --a)
     if (h.ax[a].active) st.push_back({a, &h.ax[a].NT});
@@ -100,6 +138,7 @@ hipError_t correct_bsolve(Handle &h, const T *g) {
     const Axis &X = h.ax[act[i]];
     const bool last = i == na - 1;
     T *out = last ? nullptr : bufs[i & 1];
+    TimeScope ts(h, MFA_K_CORRECT);
     hipError_t e = launch_bsolve<T, T, T>(h.stream, in, out, last ? h.P : nullptr, act[i], n0, n1, n2,
                                           h.p, X, h.combine, h.slots);
     if (e != hipSuccess) return e;
@@ -120,13 +159,21 @@ hipError_t sweep_normal(Handle &h) {
     h.g_float = low;
     if (low) {
       float *gf = reinterpret_cast<float *>(h.g);
-      hipError_t e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
+      hipError_t e;
+      {
+        TimeScope ts(h, MFA_K_RESID);
+        e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
                                          h.ax[2].d_acoef, n0, n1, n2, h.slots);
+      }
       if (e != hipSuccess) return e;
       return correct_bsolve<float>(h, gf);
     }
-    hipError_t e = launch_resid<double>(h.stream, h.p, h.P, h.c, h.g, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                                        h.ax[2].d_acoef, n0, n1, n2, h.slots);
+    hipError_t e;
+    {
+      TimeScope ts(h, MFA_K_RESID);
+      e = launch_resid<double>(h.stream, h.p, h.P, h.c, h.g, h.ax[0].d_acoef, h.ax[1].d_acoef,
+                               h.ax[2].d_acoef, n0, n1, n2, h.slots);
+    }
     if (e != hipSuccess) return e;
     return correct_bsolve<double>(h, h.g);
   }
@@ -148,6 +195,7 @@ hipError_t sweep_normal(Handle &h) {
 // Jump and scale reductions of the sweep just done (g still holds the
 // residual the sweep used; P holds the new consensus).
 hipError_t sweep_metrics(Handle &h) {
+  TimeScope ts(h, MFA_K_METRICS);
   for (int a = 0; a < 3; ++a) {
     if (!h.ax[a].active || h.ax[a].B < 2) continue;
     hipError_t e =
@@ -275,6 +323,40 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
 
 void mfa_destroy(mfa_handle *h) { delete h; }
 
+mfa_status mfa_set_timing(mfa_handle *H, int32_t enable) {
+  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  Handle &h = H->h;
+  HIP_CHECK(hipStreamSynchronize(h.stream), "set_timing");
+  for (auto &v : h.ev_used) {
+    for (auto &pr : v) {
+      h.ev_pool.push_back(pr.first);
+      h.ev_pool.push_back(pr.second);
+    }
+    v.clear();
+  }
+  h.timing = enable != 0;
+  return MFA_OK;
+}
+
+mfa_status mfa_kernel_time(mfa_handle *H, int32_t kclass, double *total_ms, int64_t *launches) {
+  if (!valid_handle(H) || !total_ms || !launches) return fail(MFA_EINVAL, "null pointer");
+  if (kclass < 0 || kclass >= MFA_K_COUNT) return fail(MFA_EINVAL, "kernel class out of range");
+  Handle &h = H->h;
+  HIP_CHECK(hipStreamSynchronize(h.stream), "kernel_time");
+  double tot = 0.0;
+  for (auto &pr : h.ev_used[kclass]) {
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, pr.first, pr.second), "kernel_time");
+    tot += ms;
+    h.ev_pool.push_back(pr.first);
+    h.ev_pool.push_back(pr.second);
+  }
+  *launches = (int64_t)h.ev_used[kclass].size();
+  h.ev_used[kclass].clear();
+  *total_ms = tot;
+  return MFA_OK;
+}
+
 static mfa_status load_q(Handle &h, const void *q, mfa_dtype dt) {
   if (dt != MFA_F32 && dt != MFA_F64) return fail(MFA_EINVAL, "bad dtype");
   hipError_t e = dt == MFA_F32 ? project<float>(h, (const float *)q) : project<double>(h, (const double *)q);
@@ -334,7 +416,9 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
   bool converged = false;
   // check schedule: fixed stride, or (check_every <= 0) predicted from the
   // observed geometric decay of the jumps between the last two checks
-  int next_check = jump_tol > 0.0 ? (check_every > 0 ? check_every : 1) : max_sweeps;
+  // adaptive: first checks at sweeps 4 and 8 (past the first sweeps'
+  // transient), then at the predicted crossing of the tolerance
+  int next_check = jump_tol > 0.0 ? (check_every > 0 ? check_every : 4) : max_sweeps;
   double prev_j = -1.0;
   int prev_k = 0;
   for (int k = 1; k <= max_sweeps; ++k) {
@@ -358,11 +442,11 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
     } else {
       double jm = 0.0;
       for (int r = 0; r < h.p; ++r) jm = std::max(jm, st.jump[r]);
-      int stride = 2;
+      int stride = 4;
       if (prev_j > 0.0 && jm < prev_j && jm > 0.0) {
         const double rate = std::pow(jm / prev_j, 1.0 / (k - prev_k));
         const double need = std::log(jump_tol / jm) / std::log(rate);
-        stride = (int)std::min(8.0, std::max(1.0, std::ceil(need)));
+        stride = (int)std::min(32.0, std::max(1.0, std::ceil(need)));
       }
       prev_j = jm;
       prev_k = k;
@@ -388,6 +472,7 @@ mfa_status mfa_decode(mfa_handle *H, void *out_dev, mfa_dtype out_dtype, const i
     st.push_back({a, &h.ax[a].N[r]});
   }
   hipError_t e;
+  TimeScope ts(h, MFA_K_DECODE);
   if (out_dtype == MFA_F32)
     e = run_chain<double, float>(h, h.P, ctrl_dims(h), st, (float *)out_dev, EPI_STORE, nullptr, 0,
                                  nullptr, 0, h.s1, h.s2);

@@ -86,38 +86,57 @@ struct OmTab {
 
 // U has shape (R, nb, nc) in the strides given (the row axis is the reduced
 // interface axis; b and c are the other two axes, c may be absent with
-// nc = 1).  Workgroup per (row, data point ib): V[kc] = sum_kb Om_b[ib][kb]
-// U[row, kb, kc] into LDS, then every data point ic of axis c evaluates
-// sum_kc Om_c[ic][kc] V[kc]; max |.| goes to slot (a, row % p).
+// nc = 1).  Workgroup per (row, group of `jb` data points ib):
+// V_i[kc] = sum_kb Om_b[ib_i][kb] U[row, kb, kc] into LDS, then every data
+// point ic of axis c evaluates sum_kc Om_c[ic][kc] V_i[kc] for all i of the
+// group (one read of the Om_c row serves jb outputs); max |.| goes to slot
+// (a, row % p).  Om rows are contiguous column ranges.
+constexpr int kJB = 8;
 __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ U, int R,
                                                      int64_t sr, int64_t sb, int64_t sc, OmTab Ob,
-                                                     OmTab Oc, int has_c, int p, int slot_base,
-                                                     unsigned long long *slots) {
-  extern __shared__ double V[];
-  const int row = blockIdx.x / Ob.m;
-  const int ib = blockIdx.x % Ob.m;
+                                                     OmTab Oc, int has_c, int jb, int p,
+                                                     int slot_base, unsigned long long *slots) {
+  extern __shared__ double V[];   // [jb][nc]
+  const int nbg = (Ob.m + jb - 1) / jb;
+  const int row = blockIdx.x / nbg;
+  const int ib0 = (blockIdx.x % nbg) * jb;
+  const int nib = min(jb, Ob.m - ib0);
   const int nc = has_c ? Oc.n : 1;
-  const int lb = Ob.len[ib];
-  const int *cb = Ob.col + (int64_t)ib * Ob.L;
-  const double *vb = Ob.val + (int64_t)ib * Ob.L;
-  for (int kc = threadIdx.x; kc < nc; kc += blockDim.x) {
+  for (int e = threadIdx.x; e < jb * nc; e += blockDim.x) {
+    const int i = e / nc, kc = e - i * nc;
     double s = 0.0;
-    for (int t = 0; t < lb; ++t) s += vb[t] * U[row * sr + (int64_t)cb[t] * sb + (int64_t)kc * sc];
-    V[kc] = s;
+    if (i < nib) {
+      const int ib = ib0 + i;
+      const int lb = Ob.len[ib];
+      const int cb0 = Ob.col[(int64_t)ib * Ob.L];
+      const double *vb = Ob.val + (int64_t)ib * Ob.L;
+      const double *u = U + row * sr + (int64_t)cb0 * sb + (int64_t)kc * sc;
+      for (int t = 0; t < lb; ++t) s += vb[t] * u[(int64_t)t * sb];
+    }
+    V[e] = s;
   }
   __syncthreads();
   double mx = 0.0;
   if (has_c) {
     for (int ic = threadIdx.x; ic < Oc.m; ic += blockDim.x) {
       const int lc = Oc.len[ic];
-      const int *cc = Oc.col + (int64_t)ic * Oc.L;
+      const int cc0 = Oc.col[(int64_t)ic * Oc.L];
       const double *vc = Oc.val + (int64_t)ic * Oc.L;
-      double s = 0.0;
-      for (int t = 0; t < lc; ++t) s += vc[t] * V[cc[t]];
-      mx = fmax(mx, fabs(s));
+      double acc[kJB];
+#pragma unroll
+      for (int i = 0; i < kJB; ++i) acc[i] = 0.0;
+      for (int t = 0; t < lc; ++t) {
+        const double w = vc[t];
+#pragma unroll
+        for (int i = 0; i < kJB; ++i)
+          if (i < jb) acc[i] += w * V[i * nc + cc0 + t];
+      }
+#pragma unroll
+      for (int i = 0; i < kJB; ++i)
+        if (i < nib) mx = fmax(mx, fabs(acc[i]));
     }
-  } else if (threadIdx.x == 0) {
-    mx = fabs(V[0]);
+  } else {
+    for (int i = threadIdx.x; i < nib; i += blockDim.x) mx = fmax(mx, fabs(V[i]));
   }
   slot_max_w(slots, slot_base + row % p, mx);
 }
@@ -125,12 +144,10 @@ __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ 
 // 1-D: the interface rows themselves
 __global__ void k_jump_rows(const double *__restrict__ U, int R, int p, int slot_base,
                             unsigned long long *slots) {
-  const int r = threadIdx.x;
-  const double v = r < R ? fabs(U[r]) : 0.0;
-  const int slot = r < R ? slot_base + r % p : slot_base;
   // lanes name different slots: plain atomics (R is tiny)
-  if (r < R)
-    atomicMax(slots + (size_t)slot * kSlotCopies, (unsigned long long)__double_as_longlong(v));
+  for (int r = threadIdx.x; r < R; r += blockDim.x)
+    atomicMax(slots + (size_t)(slot_base + r % p) * kSlotCopies,
+              (unsigned long long)__double_as_longlong(fabs(U[r])));
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -175,9 +192,10 @@ hipError_t launch_jump_expand(Handle &h, int a, const double *U) {
     has_c = 1;
     nc = h.ax[oth[1]].n;
   }
-  const unsigned grid = (unsigned)((int64_t)R * Ob.m);
-  k_jump_expand<<<grid, 256, sizeof(double) * nc, h.stream>>>(U, R, st[a], st[oth[0]], sc, Ob, Oc,
-                                                              has_c, h.p, kSlotJ + a * kMaxP, h.slots);
+  const int jb = (int)std::max(1, std::min(kJB, 8192 / nc));
+  const unsigned grid = (unsigned)((int64_t)R * ((Ob.m + jb - 1) / jb));
+  k_jump_expand<<<grid, 256, sizeof(double) * jb * nc, h.stream>>>(
+      U, R, st[a], st[oth[0]], sc, Ob, Oc, has_c, jb, h.p, kSlotJ + a * kMaxP, h.slots);
   return hipGetLastError();
 }
 

@@ -109,6 +109,20 @@ struct Handle {
   bool g_float = false;     // g holds float32 values (mixed precision)
   bool warm = false;        // P was set by mfa_set_ctrl: the next encode starts there
   int sweep = 0;
+  // per-class event timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[MFA_K_COUNT];
+  std::vector<hipEvent_t> ev_pool;
+  ~Handle();
+};
+
+// Records an event pair around the launches in its scope when timing is on.
+struct TimeScope {
+  Handle &h;
+  int cls;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TimeScope(Handle &hh, int c);
+  ~TimeScope();
 };
 
 // reduction slots (double bit patterns of non-negative maxima)
@@ -166,7 +180,7 @@ hipError_t launch_jump_expand(Handle &h, int a, const double *U);
 
 // LDS bytes the banded-solve kernel needs for segments of length fmax
 inline size_t bsolve_lds(int64_t fmax, int p, size_t elem) {
-  return (size_t)2 * fmax * 64 * elem + sizeof(double) * (size_t)(p + 2) * fmax;
+  return (size_t)2 * fmax * 65 * elem + sizeof(double) * (size_t)(p + 2) * fmax;
 }
 
 }  // namespace mfa

@@ -184,10 +184,11 @@ __global__ void __launch_bounds__(64) k_bsolve(const TI *__restrict__ in, TO *__
                                                const double *__restrict__ rdiag,
                                                const int *__restrict__ ns, int combine, int flen,
                                                unsigned long long *slots) {
+  constexpr int LS = 65;   // row stride of the line buffers (odd: no bank conflicts)
   extern __shared__ double smem_d[];
   double *fac = smem_d;                             // [(P+1) * flen]
   double *rdl = smem_d + (P + 1) * flen;            // [flen]
-  TC *buf = reinterpret_cast<TC *>(smem_d + (P + 2) * flen);   // [2][flen][64]
+  TC *buf = reinterpret_cast<TC *>(smem_d + (P + 2) * flen);   // [2][flen][LS]
   const int lane = threadIdx.x;
   const int64_t l0 = (int64_t)blockIdx.x * 64;
   const int64_t l = l0 + lane;
@@ -199,8 +200,8 @@ __global__ void __launch_bounds__(64) k_bsolve(const TI *__restrict__ in, TO *__
   double dmax = 0.0;
   int prevF0 = 0, prevF1 = 0;
   for (int b = 0; b < B; ++b) {
-    TC *cur = buf + (size_t)(b & 1) * flen * 64;
-    TC *prv = buf + (size_t)((b + 1) & 1) * flen * 64;
+    TC *cur = buf + (size_t)(b & 1) * flen * LS;
+    TC *prv = buf + (size_t)((b + 1) & 1) * flen * LS;
     const int F0 = blk[8 * b + 2], F1 = blk[8 * b + 3], F = F1 - F0;
     const int c0 = blk[8 * b + 0], c1 = blk[8 * b + 1];
     __syncthreads();   // previous segment's readers of fac/rdl/buffers are done
@@ -213,26 +214,41 @@ __global__ void __launch_bounds__(64) k_bsolve(const TI *__restrict__ in, TO *__
     if (inner) {
       for (int e = lane; e < nin * F; e += 64) {
         const int li = e / F, j = e - li * F;
-        cur[j * 64 + li] = (TC)to_d(in[(l0 + li) * G.n2 + F0 + j]);
+        cur[j * LS + li] = (TC)to_d(in[(l0 + li) * G.n2 + F0 + j]);
       }
     } else if (valid) {
-      for (int j = 0; j < F; ++j) cur[j * 64 + lane] = (TC)to_d(in[base + (int64_t)(F0 + j) * stride]);
+      for (int j = 0; j < F; ++j) cur[j * LS + lane] = (TC)to_d(in[base + (int64_t)(F0 + j) * stride]);
     }
     __syncthreads();
-    // forward: L y = s;  w[t] = y_{j-1-t}
+    // forward: L y = s;  w[t] = y_{j-1-t}.  The next step's input and
+    // coefficients are read ahead so LDS latency overlaps the FMA chain.
     {
       TC w[P];
 #pragma unroll
       for (int t = 0; t < P; ++t) w[t] = (TC)0;
-      for (int j = 0; j < F; ++j) {
-        TC s = cur[j * 64 + lane];
+      TC sn = cur[lane];
+      TC cn[P];
 #pragma unroll
-        for (int t = 1; t <= P; ++t) s -= (TC)fac[t * F + (j - t)] * w[t - 1];
-        const TC y = s * (TC)rdl[j];
+      for (int t = 1; t <= P; ++t) cn[t - 1] = (TC)fac[t * F - t];
+      TC rn = (TC)rdl[0];
+      for (int j = 0; j < F; ++j) {
+        TC s = sn, r = rn;
+        TC cc[P];
+#pragma unroll
+        for (int t = 0; t < P; ++t) cc[t] = cn[t];
+        if (j + 1 < F) {
+          sn = cur[(j + 1) * LS + lane];
+#pragma unroll
+          for (int t = 1; t <= P; ++t) cn[t - 1] = (TC)fac[t * F + (j + 1 - t)];
+          rn = (TC)rdl[j + 1];
+        }
+#pragma unroll
+        for (int t = 1; t <= P; ++t) s -= cc[t - 1] * w[t - 1];
+        const TC y = s * r;
 #pragma unroll
         for (int t = P - 1; t > 0; --t) w[t] = w[t - 1];
         w[0] = y;
-        cur[j * 64 + lane] = y;
+        cur[j * LS + lane] = y;
       }
     }
     // backward: L^T x = y;  w[t] = x_{j+1+t}
@@ -240,15 +256,29 @@ __global__ void __launch_bounds__(64) k_bsolve(const TI *__restrict__ in, TO *__
       TC w[P];
 #pragma unroll
       for (int t = 0; t < P; ++t) w[t] = (TC)0;
-      for (int j = F - 1; j >= 0; --j) {
-        TC s = cur[j * 64 + lane];
+      TC sn = cur[(F - 1) * LS + lane];
+      TC cn[P];
 #pragma unroll
-        for (int t = 1; t <= P; ++t) s -= (TC)fac[t * F + j] * w[t - 1];
-        const TC x = s * (TC)rdl[j];
+      for (int t = 1; t <= P; ++t) cn[t - 1] = (TC)fac[t * F + F - 1];
+      TC rn = (TC)rdl[F - 1];
+      for (int j = F - 1; j >= 0; --j) {
+        TC s = sn, r = rn;
+        TC cc[P];
+#pragma unroll
+        for (int t = 0; t < P; ++t) cc[t] = cn[t];
+        if (j > 0) {
+          sn = cur[(j - 1) * LS + lane];
+#pragma unroll
+          for (int t = 1; t <= P; ++t) cn[t - 1] = (TC)fac[t * F + j - 1];
+          rn = (TC)rdl[j - 1];
+        }
+#pragma unroll
+        for (int t = 1; t <= P; ++t) s -= cc[t - 1] * w[t - 1];
+        const TC x = s * r;
 #pragma unroll
         for (int t = P - 1; t > 0; --t) w[t] = w[t - 1];
         w[0] = x;
-        cur[j * 64 + lane] = x;
+        cur[j * LS + lane] = x;
       }
     }
     // combine the final positions of this segment
@@ -257,18 +287,18 @@ __global__ void __launch_bounds__(64) k_bsolve(const TI *__restrict__ in, TO *__
     for (int k = F0; k < whi; ++k) {
       double v;
       if (combine == MFA_COMBINE_RAS) {
-        if (k >= c0 && k < c1) v = (double)cur[(k - F0) * 64 + lane];
-        else if (b > 0 && k < prevF1 && k >= pc0 && k < pc1) v = (double)prv[(k - prevF0) * 64 + lane];
+        if (k >= c0 && k < c1) v = (double)cur[(k - F0) * LS + lane];
+        else if (b > 0 && k < prevF1 && k >= pc0 && k < pc1) v = (double)prv[(k - prevF0) * LS + lane];
         else v = 0.0;
       } else {
-        v = (double)cur[(k - F0) * 64 + lane];
-        if (b > 0 && k < prevF1) v += (double)prv[(k - prevF0) * 64 + lane];
+        v = (double)cur[(k - F0) * LS + lane];
+        if (b > 0 && k < prevF1) v += (double)prv[(k - prevF0) * LS + lane];
         v /= (double)ns[k];
       }
       if (MODE == 1) dmax = fmax(dmax, valid ? fabs(v) : 0.0);
       if (inner) {
         // in place: slot k-F0 <= k-prevF0, already read for this and earlier k
-        prv[(k - F0) * 64 + lane] = (TC)v;
+        prv[(k - F0) * LS + lane] = (TC)v;
       } else if (valid) {
         const int64_t o = base + (int64_t)k * stride;
         if (MODE == 0) out[o] = from_d<TO>(v);
@@ -281,13 +311,111 @@ __global__ void __launch_bounds__(64) k_bsolve(const TI *__restrict__ in, TO *__
       for (int e = lane; e < nin * W; e += 64) {
         const int li = e / W, j = e - li * W;
         const int64_t o = (l0 + li) * G.n2 + F0 + j;
-        const double v = (double)prv[j * 64 + li];
+        const double v = (double)prv[j * LS + li];
         if (MODE == 0) out[o] = from_d<TO>(v);
         else pc[o] = pc[o] + v;
       }
     }
     prevF0 = F0;
     prevF1 = F1;
+  }
+  if (MODE == 1) slot_max_c(slots, kSlotMaxDP, dmax);
+}
+
+// Segment-parallel variant: one lane per (line, subdomain segment).  A
+// workgroup holds 64 lines x B segments (B <= 16), lane = b*64 + line, so a
+// wavefront is one segment of 64 consecutive lines (coalesced on axes 0/1).
+// The segment (length F <= MAXF) lives in registers: the substitutions are
+// fully unrolled; the factor entries are wavefront-uniform (scalar loads).
+// Each segment publishes its tail (the positions it shares with the next
+// segment) in LDS; after one barrier every segment writes the positions
+// [F0_b, F0_{b+1}), adding the left neighbour's tail on the shared part with
+// weight 1/n_s (AVG) or taking the owner's value (RAS).
+template <typename TI, typename TO, typename TC, int MODE, int MAXF>
+__global__ void __launch_bounds__(1024) k_bsolve_seg(const TI *__restrict__ in, TO *__restrict__ out,
+                                                     double *__restrict__ pc, LineGeom G,
+                                                     int64_t nlines, int p, int B,
+                                                     const int *__restrict__ blk,
+                                                     const int *__restrict__ choff,
+                                                     const double *__restrict__ chol,
+                                                     const int *__restrict__ foff,
+                                                     const double *__restrict__ rdiag,
+                                                     const int *__restrict__ ns, int combine, int ov,
+                                                     unsigned long long *slots) {
+  extern __shared__ double smem_t[];
+  TC *tails = reinterpret_cast<TC *>(smem_t);   // [B][64][ov]
+  const int li = threadIdx.x & 63;
+  const int b = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t l = (int64_t)blockIdx.x * 64 + li;
+  const bool valid = l < nlines;
+  const int64_t stride = line_stride(G);
+  const int64_t base = valid ? line_base(G, l) : 0;
+  const int F0 = blk[8 * b + 2], F1 = blk[8 * b + 3], F = F1 - F0;
+  const int c0 = blk[8 * b + 0], c1 = blk[8 * b + 1];
+  const int F0n = b + 1 < B ? blk[8 * (b + 1) + 2] : F1;
+  const double *L = chol + choff[b];
+  const double *rd = rdiag + foff[b];
+  TC x[MAXF];
+#pragma unroll
+  for (int j = 0; j < MAXF; ++j)
+    if (j < F) x[j] = valid ? (TC)to_d(in[base + (int64_t)(F0 + j) * stride]) : (TC)0;
+  // forward: L y = s
+#pragma unroll
+  for (int j = 0; j < MAXF; ++j) {
+    if (j < F) {
+      TC s = x[j];
+#pragma unroll
+      for (int t = 1; t <= kMaxP; ++t)
+        if (t <= j && t <= p) s -= (TC)L[t * F + (j - t)] * x[j - t];
+      x[j] = s * (TC)rd[j];
+    }
+  }
+  // backward: L^T x = y
+#pragma unroll
+  for (int j = MAXF - 1; j >= 0; --j) {
+    if (j < F) {
+      TC s = x[j];
+#pragma unroll
+      for (int t = 1; t <= kMaxP; ++t)
+        if (j + t < MAXF && t <= p && j + t < F) s -= (TC)L[t * F + j] * x[j + t];
+      x[j] = s * (TC)rd[j];
+    }
+  }
+  // publish the tail shared with the next segment
+  TC *mytail = tails + ((size_t)b * 64 + li) * ov;
+#pragma unroll
+  for (int j = 0; j < MAXF; ++j)
+    if (j < F && F0 + j >= F0n) mytail[F0 + j - F0n] = x[j];
+  __syncthreads();
+  const TC *lefttail = b > 0 ? tails + ((size_t)(b - 1) * 64 + li) * ov : nullptr;
+  const int F1p = b > 0 ? blk[8 * (b - 1) + 3] : 0;
+  const int c0p = b > 0 ? blk[8 * (b - 1) + 0] : 0, c1p = b > 0 ? blk[8 * (b - 1) + 1] : 0;
+  double dmax = 0.0;
+#pragma unroll
+  for (int j = 0; j < MAXF; ++j) {
+    const int k = F0 + j;
+    if (j < F && k < F0n) {
+      double v;
+      const bool shared_left = b > 0 && k < F1p;
+      if (combine == MFA_COMBINE_RAS) {
+        if (k >= c0 && k < c1) v = (double)x[j];
+        else if (shared_left && k >= c0p && k < c1p) v = (double)lefttail[k - F0];
+        else v = 0.0;
+      } else {
+        v = (double)x[j];
+        if (shared_left) v += (double)lefttail[k - F0];
+        v /= (double)ns[k];
+      }
+      if (valid) {
+        const int64_t o = base + (int64_t)k * stride;
+        if (MODE == 0) {
+          out[o] = from_d<TO>(v);
+        } else {
+          pc[o] = pc[o] + v;
+          dmax = fmax(dmax, fabs(v));
+        }
+      }
+    }
   }
   if (MODE == 1) slot_max_c(slots, kSlotMaxDP, dmax);
 }
@@ -333,12 +461,37 @@ hipError_t launch_resid(hipStream_t st, int p, const double *Pc, const double *c
   }
 }
 
+template <typename TI, typename TO, typename TC, int MAXF>
+hipError_t launch_bsolve_seg(hipStream_t st, const TI *in, TO *out, double *pc, LineGeom G,
+                             int64_t nlines, int p, const Axis &X, int combine, int ov,
+                             unsigned long long *slots) {
+  const unsigned grid = nblk(nlines, 64);
+  const size_t lds = sizeof(TC) * (size_t)X.B * 64 * std::max(ov, 1);
+  if (pc)
+    k_bsolve_seg<TI, TO, TC, 1, MAXF><<<grid, 64 * X.B, lds, st>>>(
+        in, out, pc, G, nlines, p, X.B, X.d_blk, X.d_choff, X.d_chol, X.d_foff, X.d_rdiag, X.d_ns,
+        combine, std::max(ov, 1), slots);
+  else
+    k_bsolve_seg<TI, TO, TC, 0, MAXF><<<grid, 64 * X.B, lds, st>>>(
+        in, out, pc, G, nlines, p, X.B, X.d_blk, X.d_choff, X.d_chol, X.d_foff, X.d_rdiag, X.d_ns,
+        combine, std::max(ov, 1), slots);
+  return hipGetLastError();
+}
+
 template <typename TI, typename TO, typename TC>
 hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int axis, int n0, int n1,
                          int n2, int p, const Axis &X, int combine, unsigned long long *slots) {
   LineGeom G{axis, n0, n1, n2};
   const int64_t len = axis == 0 ? n0 : (axis == 1 ? n1 : n2);
   const int64_t nlines = (int64_t)n0 * n1 * n2 / len;
+  if (X.B <= 16 && X.Fmax <= 64) {
+    int ov = 0;
+    for (int b = 0; b + 1 < X.B; ++b) ov = std::max(ov, X.blk[b].F1 - X.blk[b + 1].F0);
+    if (X.Fmax <= 16) return launch_bsolve_seg<TI, TO, TC, 16>(st, in, out, pc, G, nlines, p, X, combine, ov, slots);
+    if (X.Fmax <= 32) return launch_bsolve_seg<TI, TO, TC, 32>(st, in, out, pc, G, nlines, p, X, combine, ov, slots);
+    if (X.Fmax <= 48) return launch_bsolve_seg<TI, TO, TC, 48>(st, in, out, pc, G, nlines, p, X, combine, ov, slots);
+    return launch_bsolve_seg<TI, TO, TC, 64>(st, in, out, pc, G, nlines, p, X, combine, ov, slots);
+  }
   const int flen = (int)X.Fmax;
   const size_t lds = bsolve_lds(flen, p, sizeof(TC));
   if (lds > 64 * 1024) return hipErrorInvalidValue;

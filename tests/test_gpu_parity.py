@@ -197,3 +197,20 @@ def test_notconv_status_and_data_shape_check():
     assert ei.value.status == _lib.MFA_ENOTCONV
     with pytest.raises(ValueError):
         enc.encode(q[:-1].contiguous(), 2, 0.0)
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32"])
+def test_mixed_precision_converges_to_fp64_fit(precision):
+    """Mixed precision: correction in float32, residual and control points in
+    float64; the converged decode matches the FP64 single-domain fit to 1e-6."""
+    w = W.small_3d(p=4, overlap=2, sizes=((8, 9), (8, 8), (7, 7)))
+    S = _oracle(w)
+    Q = _field(w)
+    Pstar = schwarz.global_direct(S, Q)
+    fstar = schwarz.decode(S, Pstar)
+    enc = _enc(w, precision=precision)
+    st = enc.encode(torch.from_numpy(Q).cuda(), 200, 1e-8, 1)
+    assert st["converged"]
+    f = enc.decode().cpu().numpy()
+    assert _rel(f, fstar) < 1e-6
+    assert _rel(enc.get_ctrl().cpu().numpy(), Pstar) < 1e-6
