@@ -134,8 +134,9 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes,
  * max_r J_r < jump_tol or max_sweeps.  The jumps are evaluated every
  * `check_every` sweeps; check_every <= 0 checks at sweeps 4 and 8 and then
  * at the sweep predicted from the geometric decay observed between the last
- * two checks (at most 32 sweeps apart), so the stop may come a few sweeps
- * after the first sweep that met the tolerance.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
+ * two checks (at most twice the previous interval and 32 sweeps ahead), so
+ * the stop may come a few sweeps after the first sweep that met the
+ * tolerance.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
  * NULL) receives the statistics of the last checked sweep.  Returns
  * MFA_ENOTCONV if the tolerance was not met (the control points are still
  * the last iterate) or a non-finite value appeared.                         */

@@ -129,8 +129,10 @@ bool fast_sweep_ok(const Handle &h, size_t elem) {
 template <typename T>
 hipError_t correct_bsolve(Handle &h, const T *g) {
   const int n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
+  // contiguous axis first: the last pass (which adds into P) then runs on a
+  // strided axis where the lanes of a wavefront touch consecutive addresses
   int act[3], na = 0;
-  for (int a = 0; a < 3; ++a)
+  for (int a = 2; a >= 0; --a)
     if (h.ax[a].active) act[na++] = a;
   const T *in = g;
   T *bufs[2] = {reinterpret_cast<T *>(h.s1), reinterpret_cast<T *>(h.s2)};
@@ -198,12 +200,9 @@ hipError_t sweep_metrics(Handle &h) {
   TimeScope ts(h, MFA_K_METRICS);
   for (int a = 0; a < 3; ++a) {
     if (!h.ax[a].active || h.ax[a].B < 2) continue;
-    hipError_t e =
-        h.g_float ? launch_pass<float, double>(h.stream, reinterpret_cast<const float *>(h.g),
-                                               ctrl_dims(h), a, h.ax[a].J, h.s1, EPI_STORE, nullptr,
-                                               h.slots, 0, nullptr, 0)
-                  : launch_pass<double, double>(h.stream, h.g, ctrl_dims(h), a, h.ax[a].J, h.s1,
-                                                EPI_STORE, nullptr, h.slots, 0, nullptr, 0);
+    hipError_t e = h.g_float
+                       ? launch_jump_project<float>(h, a, reinterpret_cast<const float *>(h.g), h.s1)
+                       : launch_jump_project<double>(h, a, h.g, h.s1);
     if (e != hipSuccess) return e;
     e = launch_jump_expand(h, a, h.s1);
     if (e != hipSuccess) return e;
@@ -446,7 +445,10 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
       if (prev_j > 0.0 && jm < prev_j && jm > 0.0) {
         const double rate = std::pow(jm / prev_j, 1.0 / (k - prev_k));
         const double need = std::log(jump_tol / jm) / std::log(rate);
-        stride = (int)std::min(32.0, std::max(1.0, std::ceil(need)));
+        // never extrapolate past twice the last interval (the jumps of the
+        // highest derivative order plateau for a few sweeps before the
+        // geometric decay sets in)
+        stride = (int)std::min(std::min(32.0, 2.0 * (k - prev_k)), std::max(1.0, std::ceil(need)));
       }
       prev_j = jm;
       prev_k = k;

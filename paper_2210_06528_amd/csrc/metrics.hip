@@ -1,6 +1,8 @@
 // Convergence metrics of a sweep (eq. nonlinear-residuals):
 //  k_deriv_scale : S_r^a = max |r-th derivative control coefficient along a|
 //                  of the consensus, all axes and orders in one pass over P.
+//  k_jump_project: the interface functionals J_a (all orders of an interface
+//                  at once) applied along axis a of the residual.
 //  k_jump_expand : after the interface functional J_a has reduced axis a of the
 //                  residual to (interface, order) rows, evaluate the local
 //                  corrections' difference on the owned data lines of the other
@@ -27,58 +29,11 @@ struct DTab {
   int n;
 };
 
-// One thread per control point (grid-stride): for every active axis a and
-// order r < p, the row (r, k_a) of the derivative-coefficient table applied
-// along a; running maxima kept per (a, r) and reduced per wavefront.
-__global__ void __launch_bounds__(256) k_deriv_scale(const double *__restrict__ P, int n0, int n1,
-                                                     int n2, int p, DTab d0, DTab d1, DTab d2,
-                                                     int act0, int act1, int act2,
-                                                     unsigned long long *slots) {
-  double mx[3][kMaxP];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int r = 0; r < kMaxP; ++r) mx[a][r] = 0.0;
-  const int64_t total = (int64_t)n0 * n1 * n2;
-  const int64_t s1 = n2, s0 = (int64_t)n1 * n2;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int k2 = (int)(i % n2);
-    const int64_t t = i / n2;
-    const int k1 = (int)(t % n1), k0 = (int)(t / n1);
-    const int kk[3] = {k0, k1, k2};
-    const int64_t st[3] = {s0, s1, 1};
-    const DTab *tabs[3] = {&d0, &d1, &d2};
-    const int act[3] = {act0, act1, act2};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (!act[a]) continue;
-      const DTab &D = *tabs[a];
-      int rowoff = 0;
-#pragma unroll
-      for (int r = 0; r < kMaxP; ++r) {
-        if (r >= p) break;
-        if (kk[a] <= D.n - 1 - r) {
-          const int row = rowoff + kk[a];
-          double s = 0.0;
-          for (int q = 0; q <= r; ++q) s += D.val[(int64_t)row * D.L + q] * P[i + (int64_t)q * st[a]];
-          mx[a][r] = fmax(mx[a][r], fabs(s));
-        }
-        rowoff += D.n - r;
-      }
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int r = 0; r < kMaxP; ++r)
-      if (r < p) slot_max_w(slots, kSlotS + a * kMaxP + r, mx[a][r]);
-}
-
 struct OmTab {
   const int *len;
   const int *col;
   const double *val;
+  const double *valT;   // val transposed: valT[t*m + i] = val[i*L + t]
   int L;
   int m;   // rows (data points)
   int n;   // columns (control points)
@@ -121,12 +76,12 @@ __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ 
     for (int ic = threadIdx.x; ic < Oc.m; ic += blockDim.x) {
       const int lc = Oc.len[ic];
       const int cc0 = Oc.col[(int64_t)ic * Oc.L];
-      const double *vc = Oc.val + (int64_t)ic * Oc.L;
+      const double *vc = Oc.valT + ic;
       double acc[kJB];
 #pragma unroll
       for (int i = 0; i < kJB; ++i) acc[i] = 0.0;
       for (int t = 0; t < lc; ++t) {
-        const double w = vc[t];
+        const double w = vc[(int64_t)t * Oc.m];
 #pragma unroll
         for (int i = 0; i < kJB; ++i)
           if (i < jb) acc[i] += w * V[i * nc + cc0 + t];
@@ -150,21 +105,166 @@ __global__ void k_jump_rows(const double *__restrict__ U, int R, int p, int slot
               (unsigned long long)__double_as_longlong(fabs(U[r])));
 }
 
+// U[..., b*p + r, ...] = sum_k J[b*p + r][k] g[..., k, ...] for every
+// interface b of axis a and order r < p (all orders from one read of the
+// interface's support); U has the layout of g with axis a replaced by the
+// (B-1)*p interface rows.  Grid: (ceil(n2'/bs), n1', n0') over U's dims with
+// axis a collapsed to the interface index.
+template <typename TG>
+__global__ void __launch_bounds__(256) k_jump_project(const TG *__restrict__ g, double *__restrict__ U,
+                                                      int a, int n0, int n1, int n2, int nif, int p,
+                                                      const int *__restrict__ Jcol,
+                                                      const int *__restrict__ Jlen,
+                                                      const double *__restrict__ Jval, int LJ) {
+  // output coordinates with axis a replaced by the interface index b
+  int d[3] = {n0, n1, n2};
+  d[a] = nif;
+  const int x2 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x2 >= d[2]) return;
+  int x[3] = {(int)blockIdx.z, (int)blockIdx.y, x2};
+  const int b = x[a];
+  const int64_t gs[3] = {(int64_t)n1 * n2, n2, 1};
+  int R[3] = {n0, n1, n2};
+  R[a] = nif * p;
+  const int64_t us[3] = {(int64_t)R[1] * R[2], R[2], 1};
+  x[a] = 0;
+  const int64_t gbase = x[0] * gs[0] + x[1] * gs[1] + x[2] * gs[2];
+  const int64_t ubase = x[0] * us[0] + x[1] * us[1] + x[2] * us[2];
+  const int row0 = b * p;
+  const int c0 = Jcol[(int64_t)row0 * LJ];
+  const int len = Jlen[row0];
+  double acc[kMaxP];
+#pragma unroll
+  for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
+  for (int t = 0; t < len; ++t) {
+    const double v = (double)g[gbase + (int64_t)(c0 + t) * gs[a]];
+#pragma unroll
+    for (int r = 0; r < kMaxP; ++r)
+      if (r < p) acc[r] += Jval[(int64_t)(row0 + r) * LJ + t] * v;
+  }
+#pragma unroll
+  for (int r = 0; r < kMaxP; ++r)
+    if (r < p) U[ubase + (int64_t)(row0 + r) * us[a]] = acc[r];
+}
+
+// S_r^a for all axes and orders, one workgroup per grid row (x0, x1) with the
+// lanes over axis 2: the coefficient rows of axes 0 and 1 are uniform over the
+// workgroup; those of axis 2 are per lane (a small table, cache resident).
+__global__ void __launch_bounds__(256) k_deriv_scale(const double *__restrict__ P, int n0, int n1,
+                                                     int n2, int p, DTab d0, DTab d1, DTab d2,
+                                                     int act0, int act1, int act2, int rows,
+                                                     unsigned long long *slots) {
+  const int k2 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k0 = blockIdx.z;
+  const bool valid = k2 < n2;
+  const int64_t st[3] = {(int64_t)n1 * n2, n2, 1};
+  const DTab *tabs[3] = {&d0, &d1, &d2};
+  const int act[3] = {act0, act1, act2};
+  double mx[3][kMaxP];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int r = 0; r < kMaxP; ++r) mx[a][r] = 0.0;
+  const int k1lo = blockIdx.y * rows, k1hi = min(n1, k1lo + rows);
+  for (int k1 = k1lo; k1 < k1hi; ++k1) {
+    const int64_t i = ((int64_t)k0 * n1 + k1) * n2 + (valid ? k2 : 0);
+    const int kk[3] = {k0, k1, k2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!act[a]) continue;
+      const DTab &D = *tabs[a];
+      int rowoff = 0;
+#pragma unroll
+      for (int r = 0; r < kMaxP; ++r) {
+        if (r >= p) break;
+        if (valid && kk[a] <= D.n - 1 - r) {
+          const double *dv = D.val + (int64_t)(rowoff + kk[a]) * D.L;
+          double s = 0.0;
+          for (int q = 0; q <= r; ++q) s += dv[q] * P[i + (int64_t)q * st[a]];
+          mx[a][r] = fmax(mx[a][r], fabs(s));
+        }
+        rowoff += D.n - r;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int r = 0; r < kMaxP; ++r)
+      if (act[a] && r < p) slot_max_w(slots, kSlotS + a * kMaxP + r, mx[a][r]);
+}
+
+// Interface projection along the contiguous axis: one lane per grid line
+// (x0, x1), all interfaces and orders.
+template <typename TG>
+__global__ void __launch_bounds__(256) k_jump_project_inner(const TG *__restrict__ g,
+                                                            double *__restrict__ U, int64_t nlines,
+                                                            int n2, int nif, int p,
+                                                            const int *__restrict__ Jcol,
+                                                            const int *__restrict__ Jlen,
+                                                            const double *__restrict__ Jval, int LJ) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nlines) return;
+  const int b = blockIdx.y;
+  const TG *src = g + l * n2;
+  double *dst = U + l * (int64_t)(nif * p);
+  const int row0 = b * p;
+  const int c0 = Jcol[(int64_t)row0 * LJ];
+  const int len = Jlen[row0];
+  double acc[kMaxP];
+#pragma unroll
+  for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
+  for (int t = 0; t < len; ++t) {
+    const double v = (double)src[c0 + t];
+#pragma unroll
+    for (int r = 0; r < kMaxP; ++r)
+      if (r < p) acc[r] += Jval[(int64_t)(row0 + r) * LJ + t] * v;
+  }
+#pragma unroll
+  for (int r = 0; r < kMaxP; ++r)
+    if (r < p) dst[row0 + r] = acc[r];
+}
+
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 DTab dtab(const Axis &X) { return DTab{X.D.len, X.D.col, X.D.val, X.D.L, X.n}; }
-OmTab otab(const Axis &X) { return OmTab{X.Om.len, X.Om.col, X.Om.val, X.Om.L, (int)X.m, X.n}; }
+OmTab otab(const Axis &X) {
+  return OmTab{X.Om.len, X.Om.col, X.Om.val, X.d_omT, X.Om.L, (int)X.m, X.n};
+}
 
 }  // namespace
 
 hipError_t launch_deriv_scale(Handle &h) {
-  const int64_t total = h.nctrl_total;
-  const unsigned grid = (unsigned)std::min<int64_t>(nblk(total, 256), 4096);
-  k_deriv_scale<<<grid, 256, 0, h.stream>>>(h.P, h.ax[0].n, h.ax[1].n, h.ax[2].n, h.p, dtab(h.ax[0]),
-                                            dtab(h.ax[1]), dtab(h.ax[2]), h.ax[0].active,
-                                            h.ax[1].active, h.ax[2].active, h.slots);
+  const int n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
+  const int bs = n2 >= 256 ? 256 : ((n2 + 63) / 64) * 64;
+  const int rows = 32;
+  const dim3 grid(nblk(n2, bs), nblk(n1, rows), n0);
+  k_deriv_scale<<<grid, bs, 0, h.stream>>>(h.P, n0, n1, n2, h.p, dtab(h.ax[0]), dtab(h.ax[1]),
+                                           dtab(h.ax[2]), h.ax[0].active, h.ax[1].active,
+                                           h.ax[2].active, rows, h.slots);
   return hipGetLastError();
 }
+
+template <typename TG>
+hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U) {
+  const Axis &X = h.ax[a];
+  if (a == 2) {
+    const int64_t nlines = (int64_t)h.ax[0].n * h.ax[1].n;
+    const dim3 grid(nblk(nlines, 256), X.B - 1);
+    k_jump_project_inner<TG><<<grid, 256, 0, h.stream>>>(g, U, nlines, h.ax[2].n, X.B - 1, h.p,
+                                                         X.J.col, X.J.len, X.J.val, X.J.L);
+    return hipGetLastError();
+  }
+  int d[3] = {h.ax[0].n, h.ax[1].n, h.ax[2].n};
+  d[a] = X.B - 1;
+  const int bs = d[2] >= 256 ? 256 : ((d[2] + 63) / 64) * 64;
+  const dim3 grid(nblk(d[2], bs), d[1], d[0]);
+  k_jump_project<TG><<<grid, bs, 0, h.stream>>>(g, U, a, h.ax[0].n, h.ax[1].n, h.ax[2].n, X.B - 1,
+                                                h.p, X.J.col, X.J.len, X.J.val, X.J.L);
+  return hipGetLastError();
+}
+template hipError_t launch_jump_project<double>(Handle &, int, const double *, double *);
+template hipError_t launch_jump_project<float>(Handle &, int, const float *, double *);
 
 // U = J_a applied along axis a of the residual (dims with axis a of length R).
 hipError_t launch_jump_expand(Handle &h, int a, const double *U) {

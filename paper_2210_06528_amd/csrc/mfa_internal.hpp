@@ -78,6 +78,7 @@ struct Axis {
   int *d_choff = nullptr;            // per-block offset of the Cholesky factor
   int *d_foff = nullptr;             // per-block offset into d_rdiag (sum of earlier |F_b|)
   double *d_rdiag = nullptr;         // 1 / L_jj of every block's factor
+  double *d_omT = nullptr;           // Om values transposed (L x m)
   Ell N[kMaxP + 1];                  // decode tables, derivative order 0..p
   Ell NT, A, M, Om, J, D;
   // DATABOX tables
@@ -177,6 +178,8 @@ hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int 
 // convergence metrics
 hipError_t launch_deriv_scale(Handle &h);
 hipError_t launch_jump_expand(Handle &h, int a, const double *U);
+template <typename TG>
+hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U);
 
 // LDS bytes the banded-solve kernel needs for segments of length fmax
 inline size_t bsolve_lds(int64_t fmax, int p, size_t elem) {

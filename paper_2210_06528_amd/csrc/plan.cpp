@@ -266,6 +266,7 @@ size_t layout_workspace(Handle *h, char *base) {
     bp.ell(X.A, n, n, 2 * p + 1, false);
     bp.ell(X.M, n, n, X.LM, mixed);
     bp.ell(X.Om, (int)m, n, X.LOm, false);
+    X.d_omT = bp.take<double>((int64_t)X.Om.L * m);
     bp.ell(X.J, nif * p, n, X.LJ, false);
     bp.ell(X.D, (int)X.ND, n, p, false);
     if (h->rhs == MFA_RHS_DATABOX) {

@@ -454,6 +454,13 @@ __global__ void k_tab_Comb(int n, int combine, const int *blk, const int *blo, c
   pad_row(t, k, len);
 }
 
+__global__ void k_transpose_vals(const double *val, int64_t rows, int L, double *valT) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * L) return;
+  const int64_t r = i / L, t = i - r * L;
+  valT[t * rows + r] = val[i];
+}
+
 // stencil rows: acoef[k*(2p+1) + t] = A[k][k-p+t], zero outside the matrix
 __global__ void k_acoef(int n, int p, const double *band, double *acoef) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -546,6 +553,7 @@ hipError_t setup_axis(Handle *h, int ia) {
   k_tab_M<<<nblk(n, 64), 64, 0, st>>>(n, h->combine, X.d_blk, X.d_blo, X.d_bhi, X.d_owner, X.d_ns,
                                       X.d_inv, X.M);
   k_tab_Om<<<nblk(m, 64), 64, 0, st>>>(m, p, X.d_blk, X.d_pown, X.d_span, X.N[0], X.d_inv, X.Om);
+  k_transpose_vals<<<nblk(m * X.Om.L, 256), 256, 0, st>>>(X.Om.val, m, X.Om.L, X.d_omT);
   if (nif > 0)
     k_tab_J<<<nblk((int64_t)nif * p, 64), 64, 0, st>>>(nif, p, X.d_blk, X.d_span_if, X.d_dbas_if,
                                                        X.d_inv, X.J, X.d_gidJ);
