@@ -194,6 +194,78 @@ hipError_t sweep_normal(Handle &h) {
                                    nullptr, 0, h.s1, h.s2);
 }
 
+// One sweep with the DATABOX right-hand side, as Algorithm 1 is written:
+// decode the current spline on every subdomain's data box (segmented layout,
+// one segment per subdomain and axis), residual against Q, contract with the
+// local N_F^T, apply the local inverses, combine into P.  On check sweeps the
+// interface jumps are evaluated from the local right-hand sides.
+hipError_t sweep_databox(Handle &h, bool metrics) {
+  Dims d = ctrl_dims(h);
+  double *buf[2] = {h.b1, h.b2};
+  int w = 0;
+  const double *cur = h.P;
+  hipError_t e;
+  auto pass = [&](int a, const Ell &op, int epi, double *out, int slot) {
+    e = launch_pass<double, double>(h.stream, cur, d, a, op, out, epi, nullptr, h.slots, slot,
+                                    nullptr, 0);
+    d.d[a] = op.R;
+    cur = out;
+  };
+  for (int a = 2; a >= 0; --a) {
+    if (!h.ax[a].active) continue;
+    pass(a, h.ax[a].Nseg, EPI_STORE, buf[w], 0);
+    if (e != hipSuccess) return e;
+    w ^= 1;
+  }
+  // point residual on the boxes
+  double *rbox = const_cast<double *>(cur);
+  e = h.q_dtype == MFA_F32
+          ? launch_box_resid<float>(h.stream, reinterpret_cast<const float *>(h.q), data_dims(h), rbox,
+                                    d, h.ax[0].d_qmap, h.ax[1].d_qmap, h.ax[2].d_qmap)
+          : launch_box_resid<double>(h.stream, reinterpret_cast<const double *>(h.q), data_dims(h),
+                                     rbox, d, h.ax[0].d_qmap, h.ax[1].d_qmap, h.ax[2].d_qmap);
+  if (e != hipSuccess) return e;
+  int last = -1;
+  for (int a = 0; a < 3; ++a)
+    if (h.ax[a].active) last = a;
+  for (int a = 0; a < 3; ++a) {
+    if (!h.ax[a].active) continue;
+    pass(a, h.ax[a].NsegT, a == last ? EPI_STOREMAX : EPI_STORE, buf[w], kSlotNres);
+    if (e != hipSuccess) return e;
+    w ^= 1;
+  }
+  if (metrics) {
+    // jumps from the local right-hand sides (segmented layout)
+    const Dims rd = d;
+    for (int a = 0; a < 3; ++a) {
+      if (!h.ax[a].active || h.ax[a].B < 2) continue;
+      std::vector<Step> st{{a, &h.ax[a].Jseg}};
+      for (int c = 0; c < 3; ++c)
+        if (c != a && h.ax[c].active) st.push_back({c, &h.ax[c].Omseg});
+      e = run_chain<double, double>(h, cur, rd, st, (double *)nullptr, EPI_MAXABS, nullptr,
+                                    kSlotJ + a * kMaxP, h.ax[a].d_gidJ, a, h.s1, h.s2);
+      if (e != hipSuccess) return e;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!h.ax[a].active) continue;
+    pass(a, h.ax[a].Zseg, EPI_STORE, buf[w], 0);
+    if (e != hipSuccess) return e;
+    w ^= 1;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!h.ax[a].active) continue;
+    if (a == last) {
+      pass(a, h.ax[a].Comb, EPI_ADDTO, h.P, kSlotMaxDP);
+    } else {
+      pass(a, h.ax[a].Comb, EPI_STORE, buf[w], 0);
+      w ^= 1;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Jump and scale reductions of the sweep just done (g still holds the
 // residual the sweep used; P holds the new consensus).
 hipError_t sweep_metrics(Handle &h) {
@@ -358,6 +430,12 @@ mfa_status mfa_kernel_time(mfa_handle *H, int32_t kclass, double *total_ms, int6
 
 static mfa_status load_q(Handle &h, const void *q, mfa_dtype dt) {
   if (dt != MFA_F32 && dt != MFA_F64) return fail(MFA_EINVAL, "bad dtype");
+  h.q = q;
+  h.q_dtype = dt;
+  if (h.rhs == MFA_RHS_DATABOX) {   // the data are read on every sweep
+    h.have_rhs = true;
+    return MFA_OK;
+  }
   hipError_t e = dt == MFA_F32 ? project<float>(h, (const float *)q) : project<double>(h, (const double *)q);
   if (e != hipSuccess) return hip_fail(e, "project");
   h.have_rhs = true;
@@ -367,11 +445,21 @@ static mfa_status load_q(Handle &h, const void *q, mfa_dtype dt) {
 static mfa_status do_sweep(Handle &h, bool metrics) {
   hipError_t e = launch_zero_slots(h.stream, h.slots, kNumSlots * kSlotCopies);
   if (e != hipSuccess) return hip_fail(e, "zero slots");
-  e = sweep_normal(h);
-  if (e != hipSuccess) return hip_fail(e, "sweep");
-  if (metrics) {
-    e = sweep_metrics(h);
-    if (e != hipSuccess) return hip_fail(e, "metrics");
+  if (h.rhs == MFA_RHS_DATABOX) {
+    e = sweep_databox(h, metrics);
+    if (e != hipSuccess) return hip_fail(e, "sweep");
+    if (metrics) {
+      TimeScope ts(h, MFA_K_METRICS);
+      e = launch_deriv_scale(h);
+      if (e != hipSuccess) return hip_fail(e, "metrics");
+    }
+  } else {
+    e = sweep_normal(h);
+    if (e != hipSuccess) return hip_fail(e, "sweep");
+    if (metrics) {
+      e = sweep_metrics(h);
+      if (e != hipSuccess) return hip_fail(e, "metrics");
+    }
   }
   h.sweep++;
   return MFA_OK;
@@ -559,7 +647,7 @@ mfa_status mfa_inspect(mfa_handle *H, int32_t table, int32_t axis, int32_t block
       break;
     }
     case MFA_T_RHS: {
-      if (!h.have_rhs) return fail(MFA_EINVAL, "no data loaded");
+      if (!h.have_rhs || h.rhs != MFA_RHS_NORMAL) return fail(MFA_EINVAL, "no N^T Q (NORMAL mode only)");
       buf.resize((size_t)h.nctrl_total);
       HIP_CHECK(hipMemcpyAsync(buf.data(), h.c, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, h.stream),
                 "inspect");

@@ -82,7 +82,7 @@ struct Axis {
   Ell N[kMaxP + 1];                  // decode tables, derivative order 0..p
   Ell NT, A, M, Om, J, D;
   // DATABOX tables
-  Ell Nseg, NsegT, Zseg, Comb;
+  Ell Nseg, NsegT, Zseg, Comb, Jseg, Omseg;
   int *d_qmap = nullptr;             // segmented data row -> data point index
 };
 
@@ -107,6 +107,8 @@ struct Handle {
   unsigned long long *slots = nullptr;   // reductions, see kSlot*
   int *flag = nullptr;                   // setup error flag
   bool have_rhs = false;
+  const void *q = nullptr;  // data of the last encode / step (read every sweep in DATABOX mode)
+  int q_dtype = 0;
   bool g_float = false;     // g holds float32 values (mixed precision)
   bool warm = false;        // P was set by mfa_set_ctrl: the next encode starts there
   int sweep = 0;
@@ -144,7 +146,7 @@ std::string plan_problem(const mfa_problem &prob, Handle *h);
 size_t layout_workspace(Handle *h, char *base);
 
 // ---------------------------------------------------------------- kernels
-enum Epi { EPI_STORE = 0, EPI_SUBFROM = 1, EPI_ADDTO = 2, EPI_MAXABS = 3 };
+enum Epi { EPI_STORE = 0, EPI_SUBFROM = 1, EPI_ADDTO = 2, EPI_MAXABS = 3, EPI_STOREMAX = 4 };
 
 struct Dims {
   int64_t d[3];
@@ -159,6 +161,10 @@ hipError_t launch_pass(hipStream_t st, const Tin *in, Dims in_dims, int ax, cons
                        int slot_base, const int *gid, int gaxis);
 
 hipError_t launch_fill(hipStream_t st, double *x, int64_t n, double v);
+// r = Q[qmap0[x0], qmap1[x1], qmap2[x2]] - r on a segmented data-box array
+template <typename TQ>
+hipError_t launch_box_resid(hipStream_t st, const TQ *q, Dims qd, double *r, Dims rd,
+                            const int *qm0, const int *qm1, const int *qm2);
 hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n);
 hipError_t launch_maxabs(hipStream_t st, const double *x, int64_t n, unsigned long long *slot);
 

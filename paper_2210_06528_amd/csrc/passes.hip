@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(256) k_pass(const Tin *__restrict__ in, Tout *
       for (int q = 0; q < ln; ++q) acc += vl[q] * (double)src[cl[q]];
     }
     const int64_t idx = ((int64_t)x0 * o1 + x1) * o2 + x2;
-    if (EPI == EPI_STORE) {
+    if (EPI == EPI_STORE || EPI == EPI_STOREMAX) {
       out[idx] = (Tout)acc;
     } else if (EPI == EPI_SUBFROM) {
       acc = sub[idx] - acc;
@@ -71,6 +71,21 @@ __global__ void __launch_bounds__(256) k_pass(const Tin *__restrict__ in, Tout *
     }
   }
   if (EPI != EPI_STORE) wave_slot_max(slots, slot, valid ? fabs(acc) : 0.0);
+}
+
+// point residual on the segmented data boxes: r = Q(gathered) - r
+template <typename TQ>
+__global__ void __launch_bounds__(256) k_box_resid(const TQ *__restrict__ q, int q1, int q2,
+                                                   double *__restrict__ r, int r0, int r1, int r2,
+                                                   const int *__restrict__ qm0,
+                                                   const int *__restrict__ qm1,
+                                                   const int *__restrict__ qm2) {
+  const int x2 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x2 >= r2) return;
+  const int x1 = blockIdx.y, x0 = blockIdx.z;
+  const int i0 = qm0 ? qm0[x0] : 0, i1 = qm1 ? qm1[x1] : 0, i2 = qm2 ? qm2[x2] : 0;
+  const int64_t ri = ((int64_t)x0 * r1 + x1) * r2 + x2;
+  r[ri] = (double)q[((int64_t)i0 * q1 + i1) * q2 + i2] - r[ri];
 }
 
 __global__ void k_fill(double *x, int64_t n, double v) {
@@ -117,6 +132,10 @@ hipError_t launch_pass(hipStream_t st, const Tin *in, Dims in_dims, int ax, cons
       k_pass<Tin, Tout, EPI_SUBFROM><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op,
                                                            slots, slot_base, gid, gaxis);
       break;
+    case EPI_STOREMAX:
+      k_pass<Tin, Tout, EPI_STOREMAX><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op,
+                                                           slots, slot_base, gid, gaxis);
+      break;
     case EPI_ADDTO:
       k_pass<Tin, Tout, EPI_ADDTO><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op, slots,
                                                          slot_base, gid, gaxis);
@@ -141,6 +160,21 @@ template hipError_t launch_pass<double, float>(hipStream_t, const double *, Dims
 template hipError_t launch_pass<float, float>(hipStream_t, const float *, Dims, int, const Ell &,
                                               float *, int, const double *, unsigned long long *,
                                               int, const int *, int);
+
+template <typename TQ>
+hipError_t launch_box_resid(hipStream_t st, const TQ *q, Dims qd, double *r, Dims rd,
+                            const int *qm0, const int *qm1, const int *qm2) {
+  if (rd.total() == 0) return hipSuccess;
+  const int bs = rd.d[2] >= 256 ? 256 : (int)((rd.d[2] + 63) / 64) * 64;
+  const dim3 grid(nblk(rd.d[2], bs), (unsigned)rd.d[1], (unsigned)rd.d[0]);
+  k_box_resid<TQ><<<grid, bs, 0, st>>>(q, (int)qd.d[1], (int)qd.d[2], r, (int)rd.d[0], (int)rd.d[1],
+                                       (int)rd.d[2], qm0, qm1, qm2);
+  return hipGetLastError();
+}
+template hipError_t launch_box_resid<float>(hipStream_t, const float *, Dims, double *, Dims,
+                                            const int *, const int *, const int *);
+template hipError_t launch_box_resid<double>(hipStream_t, const double *, Dims, double *, Dims,
+                                             const int *, const int *, const int *);
 
 hipError_t launch_fill(hipStream_t st, double *x, int64_t n, double v) {
   if (n <= 0) return hipSuccess;

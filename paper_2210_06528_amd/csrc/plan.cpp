@@ -274,6 +274,8 @@ size_t layout_workspace(Handle *h, char *base) {
       bp.ell(X.NsegT, (int)X.SF, (int)X.SD, X.LNsT, false);
       bp.ell(X.Zseg, (int)X.SF, (int)X.SF, X.Fmax, false);
       bp.ell(X.Comb, n, (int)X.SF, 2, false);
+      bp.ell(X.Jseg, nif * p, (int)X.SF, 2 * X.Fmax, false);
+      bp.ell(X.Omseg, (int)m, (int)X.SF, X.LOm, false);
       X.d_qmap = bp.take<int>(X.SD);
     }
   }
@@ -308,6 +310,20 @@ size_t layout_workspace(Handle *h, char *base) {
     }
     for (int a = 0; a < 3; ++a) {
       if (!h->ax[a].active || h->ax[a].B < 2) continue;
+      if (h->rhs == MFA_RHS_DATABOX) {
+        Dims j{{h->ax[0].SF, h->ax[1].SF, h->ax[2].SF}};
+        for (int c = 0; c < 3; ++c)
+          if (!h->ax[c].active) j.d[c] = 1;
+        j.d[a] = (int64_t)(h->ax[a].B - 1) * p;
+        int ww = 0;
+        upd(ww, j.total());
+        for (int c = 0; c < 3; ++c) {
+          if (c == a || !h->ax[c].active) continue;
+          ww ^= 1;
+          j.d[c] = h->ax[c].m;
+          upd(ww, j.total());
+        }
+      }
       Dims j{{h->ax[0].n, h->ax[1].n, h->ax[2].n}};
       j.d[a] = (int64_t)(h->ax[a].B - 1) * p;
       w = 0;
@@ -325,36 +341,29 @@ size_t layout_workspace(Handle *h, char *base) {
   h->s1n = s1;
   h->s2n = s2;
   if (h->rhs == MFA_RHS_DATABOX) {
-    // decode onto the data boxes: (n,n,SD) -> (n,SD,SD) -> (SD,SD,SD); the
-    // N_F^T chain back to (SF,SF,SF); the combine back to (n,n,n)
-    int64_t b1 = 1, b2 = 1;
+    // every intermediate of a per-subdomain sweep: decode onto the data boxes
+    // (n -> SD per axis), N_F^T (SD -> SF), local inverses (SF), combine
+    // (SF -> n); both box buffers are sized for the largest one
+    int64_t big = 1;
     Dims d{{h->ax[0].n, h->ax[1].n, h->ax[2].n}};
-    int w = 0;
-    auto upb = [&](int which, int64_t v) {
-      if (which == 0) b1 = std::max(b1, v);
-      else b2 = std::max(b2, v);
-    };
     for (int ia = 2; ia >= 0; --ia) {
       if (!h->ax[ia].active) continue;
       d.d[ia] = h->ax[ia].SD;
-      upb(w, d.total());
-      w ^= 1;
+      big = std::max(big, d.total());
     }
     for (int ia = 0; ia < 3; ++ia) {
       if (!h->ax[ia].active) continue;
       d.d[ia] = h->ax[ia].SF;
-      upb(w, d.total());
-      w ^= 1;
+      big = std::max(big, d.total());
     }
     for (int ia = 0; ia < 3; ++ia) {
       if (!h->ax[ia].active) continue;
-      upb(w, d.total());
-      w ^= 1;
+      d.d[ia] = h->ax[ia].n;
+      big = std::max(big, d.total());
     }
-    h->b1 = bp.take<double>(b1);
-    h->b2 = bp.take<double>(b2);
-    h->b1n = b1;
-    h->b2n = b2;
+    h->b1 = bp.take<double>(big);
+    h->b2 = bp.take<double>(big);
+    h->b1n = h->b2n = big;
   }
   h->slots = bp.take<unsigned long long>((int64_t)kNumSlots * kSlotCopies);
   h->flag = bp.take<int>(4);

@@ -413,6 +413,53 @@ __global__ void k_tab_NsegT(int64_t m, int n, int p, int B, const int *blk, cons
   pad_row(t, row, len);
 }
 
+// interface functional on the segmented free layout: row (b, r) has the
+// Z_b part on segment b and the -Z_{b+1} part on segment b+1
+__global__ void k_tab_Jseg(int nif, int p, const int *blk, const int *span_if, const double *dbas,
+                           const double *inv, Ell t) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nif * p) return;
+  const int b = row / p;
+  const double *dv = dbas + (int64_t)row * (p + 1);
+  const int s = span_if[b];
+  int len = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int bb = b + side;
+    const double sgn = side == 0 ? 1.0 : -1.0;
+    int64_t base = 0;
+    for (int q = 0; q < bb; ++q) base += blk[8 * q + 3] - blk[8 * q + 2];
+    const int F0 = blk[8 * bb + 2], F = blk[8 * bb + 3] - F0;
+    const double *Z = inv + inv_offset(blk, bb);
+    for (int c = 0; c < F; ++c) {
+      double v = 0.0;
+      for (int q = 0; q <= p; ++q) {
+        const int j = s - p + q - F0;
+        if (j >= 0 && j < F) v += dv[q] * Z[(int64_t)j * F + c];
+      }
+      t.col[(int64_t)row * t.L + len] = (int)(base + c);
+      t.val[(int64_t)row * t.L + len] = sgn * v;
+      ++len;
+    }
+  }
+  pad_row(t, row, len);
+}
+
+// owned-data decode of the local correction on the segmented free layout
+__global__ void k_tab_Omseg(int64_t m, const int *blk, const int *pown, Ell om, Ell t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int b = pown[i];
+  int64_t base = 0;
+  for (int q = 0; q < b; ++q) base += blk[8 * q + 3] - blk[8 * q + 2];
+  const int F0 = blk[8 * b + 2];
+  const int len = om.len[i];
+  for (int c = 0; c < len; ++c) {
+    t.col[i * t.L + c] = (int)(base + (om.col[i * om.L + c] - F0));
+    t.val[i * t.L + c] = om.val[i * om.L + c];
+  }
+  pad_row(t, i, len);
+}
+
 // block-diagonal local inverse on the segmented free layout
 __global__ void k_tab_Zseg(int B, const int *blk, const double *inv, Ell t) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -565,6 +612,10 @@ hipError_t setup_axis(Handle *h, int ia) {
     k_tab_Zseg<<<nblk(X.SF, 64), 64, 0, st>>>(B, X.d_blk, X.d_inv, X.Zseg);
     k_tab_Comb<<<nblk(n, 128), 128, 0, st>>>(n, h->combine, X.d_blk, X.d_blo, X.d_bhi, X.d_owner,
                                              X.d_ns, X.Comb);
+    if (nif > 0)
+      k_tab_Jseg<<<nblk((int64_t)nif * p, 64), 64, 0, st>>>(nif, p, X.d_blk, X.d_span_if, X.d_dbas_if,
+                                                            X.d_inv, X.Jseg);
+    k_tab_Omseg<<<nblk(m, 128), 128, 0, st>>>(m, X.d_blk, X.d_pown, X.Om, X.Omseg);
     MFA_TRY(hipGetLastError());
   }
   return hipSuccess;

@@ -93,14 +93,15 @@ def test_rhs_is_NtQ(name):
     assert _rel(c, ref) < 1e-13
 
 
+@pytest.mark.parametrize("rhs", ["normal", "databox"])
 @pytest.mark.parametrize("combine", ["avg", "ras"])
 @pytest.mark.parametrize("name,nsweeps", [("1d", 10), ("2d", 6), ("3d", 5), ("2d-p1", 5),
                                           ("2d-p5", 5), ("3d-p4", 4)])
-def test_sweeps_match_oracle(name, nsweeps, combine):
+def test_sweeps_match_oracle(name, nsweeps, combine, rhs):
     w = SMALL[name]()
     S = _oracle(w, combine)
     Q = _data(w)
-    enc = _enc(w, combine=combine)
+    enc = _enc(w, combine=combine, rhs=rhs)
     q = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
     P = np.zeros(w.nctrl)
     for k in range(nsweeps):
@@ -118,12 +119,13 @@ def test_sweeps_match_oracle(name, nsweeps, combine):
                 assert jg < 1e-8
 
 
-def test_cfg2_converges_in_the_oracle_sweep_count():
+@pytest.mark.parametrize("rhs", ["normal", "databox"])
+def test_cfg2_converges_in_the_oracle_sweep_count(rhs):
     w = W.cfg_2d()
     S = _oracle(w)
     Q = W.make_field(w)
     Po, hist = schwarz.encode(S, Q, 40, jump_tol=w.jump_tol)
-    enc = _enc(w)
+    enc = _enc(w, rhs=rhs)
     st = enc.encode(torch.from_numpy(Q).cuda(), 40, w.jump_tol)
     assert st["converged"] and st["sweep"] == len(hist)
     assert _rel(enc.get_ctrl().cpu().numpy(), Po) < 1e-10
