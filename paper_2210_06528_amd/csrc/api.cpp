@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_bf16.h>
+
 #include "mfa_internal.hpp"
 
 using namespace mfa;
@@ -118,6 +120,12 @@ hipError_t project(Handle &h, const T *q) {
                               h.s2);
 }
 
+bool mfma_ok(const Handle &h) {
+  for (int a = 0; a < 3; ++a)
+    if (h.ax[a].active && !mfma_fits(h.ax[a].npad)) return false;
+  return true;
+}
+
 bool fast_sweep_ok(const Handle &h, size_t elem) {
   for (int a = 0; a < 3; ++a)
     if (h.ax[a].active && bsolve_lds(h.ax[a].Fmax, h.p, elem) > 64 * 1024) return false;
@@ -155,17 +163,43 @@ hipError_t correct_bsolve(Handle &h, const T *g) {
 //   P += (M_0 x M_1 x M_2) g         (local solves with lagged ghosts and the
 //                                     1/n_s combine, Section 2.3.2)
 hipError_t sweep_normal(Handle &h) {
-  const bool low = h.precision != MFA_PREC_FP64;
   const int n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
+  if (h.precision == MFA_PREC_MIXED_BF16 && mfma_ok(h)) {
+    // residual in float64, rounded to FP32; correction on the matrix cores
+    h.g_type = 1;
+    float *gf = reinterpret_cast<float *>(h.g);
+    hipError_t e;
+    {
+      TimeScope ts(h, MFA_K_RESID);
+      e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
+                              h.ax[2].d_acoef, n0, n1, n2, h.slots);
+    }
+    if (e != hipSuccess) return e;
+    int act[3], na = 0;
+    for (int a = 2; a >= 0; --a)
+      if (h.ax[a].active) act[na++] = a;
+    const float *in = gf;
+    float *bufs[2] = {reinterpret_cast<float *>(h.s1), reinterpret_cast<float *>(h.s2)};
+    for (int i = 0; i < na; ++i) {
+      const bool last = i == na - 1;
+      float *out = last ? nullptr : bufs[i & 1];
+      TimeScope ts(h, MFA_K_CORRECT);
+      e = launch_mfma_correct(h, act[i], in, out, last);
+      if (e != hipSuccess) return e;
+      in = out;
+    }
+    return hipSuccess;
+  }
+  const bool low = h.precision != MFA_PREC_FP64;
   if (fast_sweep_ok(h, low ? sizeof(float) : sizeof(double))) {
-    h.g_float = low;
+    h.g_type = low ? 1 : 0;
     if (low) {
       float *gf = reinterpret_cast<float *>(h.g);
       hipError_t e;
       {
         TimeScope ts(h, MFA_K_RESID);
         e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                                         h.ax[2].d_acoef, n0, n1, n2, h.slots);
+                                h.ax[2].d_acoef, n0, n1, n2, h.slots);
       }
       if (e != hipSuccess) return e;
       return correct_bsolve<float>(h, gf);
@@ -180,7 +214,7 @@ hipError_t sweep_normal(Handle &h) {
     return correct_bsolve<double>(h, h.g);
   }
   // general path: row-sparse operator passes (any segment length)
-  h.g_float = false;
+  h.g_type = 0;
   std::vector<Step> st;
   for (int a = 2; a >= 0; --a)
     if (h.ax[a].active) st.push_back({a, &h.ax[a].A});
@@ -272,9 +306,11 @@ hipError_t sweep_metrics(Handle &h) {
   TimeScope ts(h, MFA_K_METRICS);
   for (int a = 0; a < 3; ++a) {
     if (!h.ax[a].active || h.ax[a].B < 2) continue;
-    hipError_t e = h.g_float
-                       ? launch_jump_project<float>(h, a, reinterpret_cast<const float *>(h.g), h.s1)
-                       : launch_jump_project<double>(h, a, h.g, h.s1);
+    hipError_t e =
+        h.g_type == 1   ? launch_jump_project<float>(h, a, reinterpret_cast<const float *>(h.g), h.s1)
+        : h.g_type == 2 ? launch_jump_project<__hip_bfloat16>(
+                              h, a, reinterpret_cast<const __hip_bfloat16 *>(h.g), h.s1)
+                        : launch_jump_project<double>(h, a, h.g, h.s1);
     if (e != hipSuccess) return e;
     e = launch_jump_expand(h, a, h.s1);
     if (e != hipSuccess) return e;
@@ -378,6 +414,8 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
   for (int a = 0; a < 3; ++a) {
     if (h.ax[a].active && (e = setup_axis(&h, a)) != hipSuccess) return bail(e, "setup");
     if ((e = setup_acoef(&h, a)) != hipSuccess) return bail(e, "setup");
+    if (h.ax[a].active && h.precision == MFA_PREC_MIXED_BF16 && (e = setup_mfma(&h, a)) != hipSuccess)
+      return bail(e, "setup");
   }
   int flag = 0;
   if ((e = hipMemcpyAsync(&flag, h.flag, sizeof(int), hipMemcpyDeviceToHost, h.stream)) != hipSuccess)

@@ -7,6 +7,8 @@
 //                  residual to (interface, order) rows, evaluate the local
 //                  corrections' difference on the owned data lines of the other
 //                  axes (Omega_b, Omega_c) and reduce max |.| per order.
+#include <hip/hip_bf16.h>
+
 #include "mfa_internal.hpp"
 
 namespace mfa {
@@ -20,6 +22,10 @@ __device__ __forceinline__ void slot_max_w(unsigned long long *slots, int slot, 
     atomicMax(slots + (size_t)slot * kSlotCopies + copy, (unsigned long long)__double_as_longlong(v));
   }
 }
+
+__device__ __forceinline__ double tod(double v) { return v; }
+__device__ __forceinline__ double tod(float v) { return (double)v; }
+__device__ __forceinline__ double tod(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
 
 struct DTab {
   const int *len;
@@ -137,7 +143,7 @@ __global__ void __launch_bounds__(256) k_jump_project(const TG *__restrict__ g, 
 #pragma unroll
   for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
   for (int t = 0; t < len; ++t) {
-    const double v = (double)g[gbase + (int64_t)(c0 + t) * gs[a]];
+    const double v = tod(g[gbase + (int64_t)(c0 + t) * gs[a]]);
 #pragma unroll
     for (int r = 0; r < kMaxP; ++r)
       if (r < p) acc[r] += Jval[(int64_t)(row0 + r) * LJ + t] * v;
@@ -215,7 +221,7 @@ __global__ void __launch_bounds__(256) k_jump_project_inner(const TG *__restrict
 #pragma unroll
   for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
   for (int t = 0; t < len; ++t) {
-    const double v = (double)src[c0 + t];
+    const double v = tod(src[c0 + t]);
 #pragma unroll
     for (int r = 0; r < kMaxP; ++r)
       if (r < p) acc[r] += Jval[(int64_t)(row0 + r) * LJ + t] * v;
@@ -265,6 +271,7 @@ hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U) {
 }
 template hipError_t launch_jump_project<double>(Handle &, int, const double *, double *);
 template hipError_t launch_jump_project<float>(Handle &, int, const float *, double *);
+template hipError_t launch_jump_project<__hip_bfloat16>(Handle &, int, const __hip_bfloat16 *, double *);
 
 // U = J_a applied along axis a of the residual (dims with axis a of length R).
 hipError_t launch_jump_expand(Handle &h, int a, const double *U) {

@@ -79,6 +79,11 @@ struct Axis {
   int *d_foff = nullptr;             // per-block offset into d_rdiag (sum of earlier |F_b|)
   double *d_rdiag = nullptr;         // 1 / L_jj of every block's factor
   double *d_omT = nullptr;           // Om values transposed (L x m)
+  // mixed BF16: dense split-BF16 copy of M (hi then lo; rows padded to 16,
+  // npad columns) and the K range of every 16-row tile
+  int npad = 0;
+  void *d_Mb = nullptr;
+  int *d_klo = nullptr, *d_knc = nullptr;
   Ell N[kMaxP + 1];                  // decode tables, derivative order 0..p
   Ell NT, A, M, Om, J, D;
   // DATABOX tables
@@ -109,7 +114,7 @@ struct Handle {
   bool have_rhs = false;
   const void *q = nullptr;  // data of the last encode / step (read every sweep in DATABOX mode)
   int q_dtype = 0;
-  bool g_float = false;     // g holds float32 values (mixed precision)
+  int g_type = 0;           // element type of g: 0 float64, 1 float32, 2 bfloat16
   bool warm = false;        // P was set by mfa_set_ctrl: the next encode starts there
   int sweep = 0;
   // per-class event timing
@@ -186,6 +191,12 @@ hipError_t launch_deriv_scale(Handle &h);
 hipError_t launch_jump_expand(Handle &h, int a, const double *U);
 template <typename TG>
 hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U);
+
+// mixed BF16 correction on the matrix cores
+size_t mfma_lds(int npad);
+bool mfma_fits(int npad);
+hipError_t setup_mfma(Handle *h, int a);
+hipError_t launch_mfma_correct(Handle &h, int axis, const float *in, float *out, bool add);
 
 // LDS bytes the banded-solve kernel needs for segments of length fmax
 inline size_t bsolve_lds(int64_t fmax, int p, size_t elem) {

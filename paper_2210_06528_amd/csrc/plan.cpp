@@ -265,6 +265,12 @@ size_t layout_workspace(Handle *h, char *base) {
     bp.ell(X.NT, n, (int)m, X.LNT, false);
     bp.ell(X.A, n, n, 2 * p + 1, false);
     bp.ell(X.M, n, n, X.LM, mixed);
+    if (h->precision == MFA_PREC_MIXED_BF16) {
+      X.npad = (n + 31) / 32 * 32 + 32;
+      X.d_Mb = bp.take<uint16_t>(2 * (int64_t)((n + 15) / 16 * 16) * X.npad);
+      X.d_klo = bp.take<int>((n + 15) / 16);
+      X.d_knc = bp.take<int>((n + 15) / 16);
+    }
     bp.ell(X.Om, (int)m, n, X.LOm, false);
     X.d_omT = bp.take<double>((int64_t)X.Om.L * m);
     bp.ell(X.J, nif * p, n, X.LJ, false);

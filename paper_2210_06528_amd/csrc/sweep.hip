@@ -529,6 +529,9 @@ template hipError_t launch_resid<double>(hipStream_t, int, const double *, const
 template hipError_t launch_resid<float>(hipStream_t, int, const double *, const double *, float *,
                                         const double *, const double *, const double *, int, int, int,
                                         unsigned long long *);
+template hipError_t launch_resid<__hip_bfloat16>(hipStream_t, int, const double *, const double *,
+                                                 __hip_bfloat16 *, const double *, const double *,
+                                                 const double *, int, int, int, unsigned long long *);
 template hipError_t launch_bsolve<double, double, double>(hipStream_t, const double *, double *,
                                                           double *, int, int, int, int, int,
                                                           const Axis &, int, unsigned long long *);

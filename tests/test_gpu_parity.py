@@ -201,18 +201,32 @@ def test_notconv_status_and_data_shape_check():
         enc.encode(q[:-1].contiguous(), 2, 0.0)
 
 
-@pytest.mark.parametrize("precision", ["mixed_fp32"])
-def test_mixed_precision_converges_to_fp64_fit(precision):
-    """Mixed precision: correction in float32, residual and control points in
-    float64; the converged decode matches the FP64 single-domain fit to 1e-6."""
-    w = W.small_3d(p=4, overlap=2, sizes=((8, 9), (8, 8), (7, 7)))
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+@pytest.mark.parametrize("name", ["1d", "2d", "3d-p4"])
+def test_mixed_precision_converges_to_fp64_fit(precision, name):
+    """Mixed precision: correction in float32 or BF16 (matrix cores), residual
+    and control points in float64; the converged control points and decode
+    match the FP64 single-domain fit to 1e-6 relative."""
+    w = SMALL[name]()
     S = _oracle(w)
-    Q = _field(w)
+    Q = _data(w)
     Pstar = schwarz.global_direct(S, Q)
     fstar = schwarz.decode(S, Pstar)
     enc = _enc(w, precision=precision)
-    st = enc.encode(torch.from_numpy(Q).cuda(), 200, 1e-8, 1)
+    st = enc.encode(torch.from_numpy(np.ascontiguousarray(Q)).cuda(), 300, 1e-8, 1)
     assert st["converged"]
     f = enc.decode().cpu().numpy()
     assert _rel(f, fstar) < 1e-6
     assert _rel(enc.get_ctrl().cpu().numpy(), Pstar) < 1e-6
+
+
+def test_bf16_sweep_is_a_perturbed_fp64_sweep():
+    """One BF16 sweep from the same state differs from the FP64 sweep by the
+    BF16 rounding of the correction only (a few parts in 1e3 of its size)."""
+    w = SMALL["3d-p4"]()
+    Q = torch.from_numpy(_data(w)).cuda()
+    a, b = _enc(w, precision="fp64"), _enc(w, precision="mixed_bf16")
+    a.step(Q)
+    b.step(Q)
+    pa, pb = a.get_ctrl().cpu().numpy(), b.get_ctrl().cpu().numpy()
+    assert 0 < _rel(pb, pa) < 1e-2
