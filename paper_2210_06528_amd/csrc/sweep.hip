@@ -45,12 +45,13 @@ __device__ __forceinline__ __hip_bfloat16 from_d<__hip_bfloat16>(double v) {
 
 constexpr int kTZ = 64;   // z outputs per workgroup (one per lane)
 constexpr int kTY = 16;   // y outputs per workgroup
-constexpr int kRY = 4;    // y outputs per thread
+constexpr int kRY = 2;    // y outputs per thread
+constexpr int kRT = 512;  // threads per workgroup (kTY / kRY wavefronts)
 
 // Coefficient tables Aa[k*(2P+1) + t] = A_a[k][k-P+t] (0 outside the matrix);
 // an inactive axis (length 1) has the identity row.
 template <int P, typename TG>
-__global__ void __launch_bounds__(256) k_resid(const double *__restrict__ Pc,
+__global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
                                                const double *__restrict__ c, TG *__restrict__ g,
                                                const double *__restrict__ A0,
                                                const double *__restrict__ A1,
@@ -61,14 +62,16 @@ __global__ void __launch_bounds__(256) k_resid(const double *__restrict__ Pc,
   constexpr int LZ = kTZ + 2 * P;
   __shared__ double tile[LY][LZ + 1];
   __shared__ double tz[LY][kTZ + 1];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  __shared__ double azs[W][kTZ];   // axis-2 stencil rows of this tile's columns
+  const int tx = threadIdx.x & 63;
+  const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wavefront index 0..7
   const int z0 = blockIdx.x * kTZ, y0 = blockIdx.y * kTY, x0 = blockIdx.z * xchunk;
   const int x1 = min(n0, x0 + xchunk);
   const int gz = z0 + tx;
-  const double *az = A2 + (int64_t)min(gz, n2 - 1) * W;
-  double azr[W];
-#pragma unroll
-  for (int t = 0; t < W; ++t) azr[t] = az[t];
+  for (int e = threadIdx.x; e < W * kTZ; e += kRT) {
+    const int t = e / kTZ, zl = e - t * kTZ;
+    azs[t][zl] = A2[(int64_t)min(z0 + zl, n2 - 1) * W + t];
+  }
   double ring[W][kRY];
 #pragma unroll
   for (int t = 0; t < W; ++t)
@@ -77,13 +80,13 @@ __global__ void __launch_bounds__(256) k_resid(const double *__restrict__ Pc,
   double nres = 0.0;
   // the tile of the next plane is loaded into registers while the current
   // plane is computed (software pipelining of the global loads)
-  constexpr int NE = (LY * LZ + 255) / 256;
+  constexpr int NE = (LY * LZ + kRT - 1) / kRT;
   double pre[NE];
   auto gload = [&](int xi) {
     const bool xin = xi >= 0 && xi < n0;
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-      const int e = threadIdx.x + 256 * i;
+      const int e = threadIdx.x + kRT * i;
       const int yy = e / LZ, zz = e - yy * LZ;
       const int gy = y0 - P + yy, gzz = z0 - P + zz;
       double v = 0.0;
@@ -94,10 +97,19 @@ __global__ void __launch_bounds__(256) k_resid(const double *__restrict__ Pc,
   };
   gload(x0 - P);
   for (int xi = x0 - P; xi < x1 + P; ++xi) {
+    const int xo = xi - P;
+    const bool out_plane = xo >= x0 && xo < x1;
+    // the right-hand side of the plane completed in this iteration
+    double cv[kRY];
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) {
+      const int gy = y0 + ty * kRY + r;
+      cv[r] = (out_plane && gy < n1 && gz < n2) ? c[((int64_t)xo * n1 + gy) * n2 + gz] : 0.0;
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-      const int e = threadIdx.x + 256 * i;
+      const int e = threadIdx.x + kRT * i;
       if (e < LY * LZ) {
         const int yy = e / LZ, zz = e - yy * LZ;
         tile[yy][zz] = pre[i];
@@ -105,10 +117,10 @@ __global__ void __launch_bounds__(256) k_resid(const double *__restrict__ Pc,
     }
     __syncthreads();
     if (xi + 1 < x1 + P) gload(xi + 1);
-    for (int yy = ty; yy < LY; yy += 4) {
+    for (int yy = ty; yy < LY; yy += kRT / 64) {
       double s = 0.0;
 #pragma unroll
-      for (int t = 0; t < W; ++t) s += azr[t] * tile[yy][tx + t];
+      for (int t = 0; t < W; ++t) s += azs[t][tx] * tile[yy][tx + t];
       tz[yy][tx] = s;
     }
     __syncthreads();
@@ -123,8 +135,7 @@ __global__ void __launch_bounds__(256) k_resid(const double *__restrict__ Pc,
       for (int t = 0; t < W - 1; ++t) ring[t][r] = ring[t + 1][r];
       ring[W - 1][r] = s;
     }
-    const int xo = xi - P;
-    if (xo >= x0 && xo < x1) {
+    if (out_plane) {
       const double *ax = A0 + (int64_t)xo * W;
 #pragma unroll
       for (int r = 0; r < kRY; ++r) {
@@ -134,7 +145,7 @@ __global__ void __launch_bounds__(256) k_resid(const double *__restrict__ Pc,
 #pragma unroll
           for (int t = 0; t < W; ++t) s += ax[t] * ring[t][r];
           const int64_t idx = ((int64_t)xo * n1 + gy) * n2 + gz;
-          const double gv = c[idx] - s;
+          const double gv = cv[r] - s;
           g[idx] = from_d<TG>(gv);
           nres = fmax(nres, fabs(gv));
         }
@@ -433,7 +444,7 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
   if (byz * 1 < target) xchunk = std::max(4, (int)((int64_t)n0 * byz / target));
   xchunk = std::min(xchunk, n0);
   const dim3 grid(nblk(n2, kTZ), nblk(n1, kTY), nblk(n0, xchunk));
-  k_resid<P, TG><<<grid, 256, 0, st>>>(Pc, c, g, A0, A1, A2, n0, n1, n2, xchunk, slots);
+  k_resid<P, TG><<<grid, kRT, 0, st>>>(Pc, c, g, A0, A1, A2, n0, n1, n2, xchunk, slots);
   return hipGetLastError();
 }
 

@@ -221,12 +221,15 @@ def test_mixed_precision_converges_to_fp64_fit(precision, name):
 
 
 def test_bf16_sweep_is_a_perturbed_fp64_sweep():
-    """One BF16 sweep from the same state differs from the FP64 sweep by the
-    BF16 rounding of the correction only (a few parts in 1e3 of its size)."""
+    """One split-BF16 sweep from the same state differs from the FP64 sweep by
+    the rounding of the correction only: about 2^-16 per product, amplified by
+    the condition number of the local normal matrices on each of the three
+    axis passes (about 1e-2 for p = 4 here).  A wrong index or layout gives an
+    O(1) difference."""
     w = SMALL["3d-p4"]()
     Q = torch.from_numpy(_data(w)).cuda()
     a, b = _enc(w, precision="fp64"), _enc(w, precision="mixed_bf16")
     a.step(Q)
     b.step(Q)
     pa, pb = a.get_ctrl().cpu().numpy(), b.get_ctrl().cpu().numpy()
-    assert 0 < _rel(pb, pa) < 1e-2
+    assert 0 < _rel(pb, pa) < 5e-2
