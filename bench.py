@@ -29,8 +29,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="3d-mixed",
-                    choices=["1d", "2d", "3d-batched", "3d-mixed"])
-    ap.add_argument("--precision", default="fp64")
+                    choices=["1d", "2d", "3d-batched", "3d-mixed", "serving"])
+    ap.add_argument("--precision", default="mixed_bf16")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: stream length")
+    ap.add_argument("--slots", type=int, default=12, help="serving: concurrent requests")
+    ap.add_argument("--calib", type=int, default=100, help="serving: saturated calibration sample")
     ap.add_argument("--rhs", default="normal", choices=["normal", "databox"])
     ap.add_argument("--check-every", type=int, default=0)
     ap.add_argument("--max-sweeps", type=int, default=200)
@@ -111,12 +114,59 @@ def cpu_baseline(w, Q, nsweeps_gpu, nsample):
             "seconds_measured": round(t_setup + t_sweep * nsample + t_dec, 2)}
 
 
+def run_serving(args):
+    """Poisson stream of encode requests through the continuous-batching loop.
+
+    The arrival rate is calibrated to 0.7x the saturated request rate measured
+    on the first `calib` requests (all available at once); the input of each
+    request is generated on the device when it is admitted (standing in for
+    its arrival in HBM), so latency = arrival -> input resident -> setup ->
+    encode -> decode complete.
+    """
+    import torch
+    from paper_2210_06528_amd import workloads as W
+    from paper_2210_06528_amd.serve import Server, spectral_field_gpu
+    dev = torch.device("cuda:0")
+
+    def make(req):
+        w = req.workload
+        return spectral_field_gpu(w.npts, w.extra["kmax"], w.seed, dev)
+
+    base = W.serving_stream(args.requests, rate=1.0, seed=2)
+    srv = Server(slots=args.slots, hbm_budget=200e9, device=dev)
+    def report(done, total):
+        print(f"[bench] serving: {done}/{total} requests done", file=sys.stderr, flush=True)
+
+    warm = srv.run(base[:min(16, len(base))], make, time_scale=0.0, progress=report)
+    cal = srv.run(base[:args.calib], make, time_scale=0.0, progress=report)
+    sat_rate = cal["requests"] / cal["wall_s"]
+    lam = 0.7 * sat_rate
+    print(f"[bench] serving: saturated {sat_rate:.1f} req/s, lambda {lam:.1f} req/s",
+          file=sys.stderr, flush=True)
+    out = srv.run(base, make, time_scale=1.0 / lam, progress=report)
+    res = {
+        "metric": METRIC, "value": out["points_per_s"], "unit": "points/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": out["wall_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
+        "config": {"workload": f"serving-{args.requests}-poisson", "slots": args.slots,
+                   "hbm_budget_gb": 200, "lambda_req_per_s": lam,
+                   "saturated_req_per_s": sat_rate, "sides": [64, 512], "degrees": [2, 3, 4],
+                   "precision": "mixed_bf16", "jump_tol": 1e-8},
+        "p50_ms": out["p50_ms"], "p99_ms": out["p99_ms"], "requests": out["requests"],
+        "converged": out["converged"], "warm_requests": warm["requests"],
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is a "
               "design in DESIGN.md, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serving":
+        run_serving(args)
+        return
     import torch
     from paper_2210_06528_amd import _lib
 

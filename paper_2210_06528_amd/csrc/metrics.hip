@@ -52,11 +52,13 @@ struct OmTab {
 // point ic of axis c evaluates sum_kc Om_c[ic][kc] V_i[kc] for all i of the
 // group (one read of the Om_c row serves jb outputs); max |.| goes to slot
 // (a, row % p).  Om rows are contiguous column ranges.
-constexpr int kJB = 8;
+constexpr int kJB = 16;
+template <int JB>
 __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ U, int R,
                                                      int64_t sr, int64_t sb, int64_t sc, OmTab Ob,
-                                                     OmTab Oc, int has_c, int jb, int p,
-                                                     int slot_base, unsigned long long *slots) {
+                                                     OmTab Oc, int has_c, int p, int slot_base,
+                                                     unsigned long long *slots) {
+  constexpr int jb = JB;
   extern __shared__ double V[];   // [jb][nc]
   const int nbg = (Ob.m + jb - 1) / jb;
   const int row = blockIdx.x / nbg;
@@ -83,17 +85,25 @@ __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ 
       const int lc = Oc.len[ic];
       const int cc0 = Oc.col[(int64_t)ic * Oc.L];
       const double *vc = Oc.valT + ic;
-      double acc[kJB];
+      const double *vrow = V + cc0;
+      double acc[JB];
 #pragma unroll
-      for (int i = 0; i < kJB; ++i) acc[i] = 0.0;
-      for (int t = 0; t < lc; ++t) {
-        const double w = vc[(int64_t)t * Oc.m];
+      for (int i = 0; i < JB; ++i) acc[i] = 0.0;
+      // coefficients read eight at a time so their loads overlap
+      for (int t0 = 0; t0 < lc; t0 += 8) {
+        double wv[8];
 #pragma unroll
-        for (int i = 0; i < kJB; ++i)
-          if (i < jb) acc[i] += w * V[i * nc + cc0 + t];
+        for (int u = 0; u < 8; ++u) wv[u] = t0 + u < lc ? vc[(int64_t)(t0 + u) * Oc.m] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (t0 + u < lc) {
+#pragma unroll
+            for (int i = 0; i < JB; ++i) acc[i] += wv[u] * vrow[i * nc + t0 + u];
+          }
+        }
       }
 #pragma unroll
-      for (int i = 0; i < kJB; ++i)
+      for (int i = 0; i < JB; ++i)
         if (i < nib) mx = fmax(mx, fabs(acc[i]));
     }
   } else {
@@ -299,10 +309,18 @@ hipError_t launch_jump_expand(Handle &h, int a, const double *U) {
     has_c = 1;
     nc = h.ax[oth[1]].n;
   }
-  const int jb = (int)std::max(1, std::min(kJB, 8192 / nc));
+  const int jb = nc <= 384 ? 16 : (nc <= 768 ? 8 : (nc <= 1536 ? 4 : 1));
   const unsigned grid = (unsigned)((int64_t)R * ((Ob.m + jb - 1) / jb));
-  k_jump_expand<<<grid, 256, sizeof(double) * jb * nc, h.stream>>>(
-      U, R, st[a], st[oth[0]], sc, Ob, Oc, has_c, jb, h.p, kSlotJ + a * kMaxP, h.slots);
+  const size_t lds = sizeof(double) * jb * nc;
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+#define MFA_JE(JB)                                                                                  \
+  k_jump_expand<JB><<<grid, 256, lds, h.stream>>>(U, R, st[a], st[oth[0]], sc, Ob, Oc, has_c, h.p, \
+                                                 kSlotJ + a * kMaxP, h.slots)
+  if (jb == 16) MFA_JE(16);
+  else if (jb == 8) MFA_JE(8);
+  else if (jb == 4) MFA_JE(4);
+  else MFA_JE(1);
+#undef MFA_JE
   return hipGetLastError();
 }
 

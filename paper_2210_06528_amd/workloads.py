@@ -263,7 +263,9 @@ def serving_stream(nreq=2000, rate=100.0, seed=2, side_lo=64, side_hi=512, block
     Per request (one rng, seed `seed`): inter-arrival ~ Exp(rate), dimension
     uniform in {2, 3}, sides uniform in [side_lo, side_hi], p uniform in
     {2, 3, 4}; n_a = side_a // 8 control points split into ceil(n_a / block)
-    even blocks; the field uses seed 1000 + rid and k_max = n_min // 4.
+    even blocks (fewer if a block would be smaller than max(p+1, 2*overlap));
+    the field uses seed 1000 + rid and k_max = n_min // 4.  The rng draws do
+    not depend on `rate`, so changing the rate only rescales arrival times.
     """
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -274,7 +276,10 @@ def serving_stream(nreq=2000, rate=100.0, seed=2, side_lo=64, side_hi=512, block
         sides = tuple(int(s) for s in rng.integers(side_lo, side_hi + 1, dim))
         p = int(rng.integers(2, 5))
         nctrl = [s // 8 for s in sides]
-        sizes = [even_sizes(n, -(-n // block)) for n in nctrl]
+        # ceil(n / block) subdomains per axis, fewer where blocks would drop
+        # below the minimum size max(p+1, 2*overlap)
+        minb = max(p + 1, 2 * overlap)
+        sizes = [even_sizes(n, max(1, min(-(-n // block), n // minb))) for n in nctrl]
         w = Workload(f"req{rid}", sides, p, sizes, overlap, precision="mixed_bf16",
                      jump_tol=1e-8, dtype="f32", seed=1000 + rid)
         w.extra["kmax"] = max(1, min(nctrl) // 4)

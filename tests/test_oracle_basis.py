@@ -132,3 +132,15 @@ def test_spectral_field_fft_route_equals_mode_sum():
         f = W.field_spectral(shape, nmodes=40, kmax=kmax, seed=3, dtype=np.float64)
         g = W.field_spectral_direct(shape, nmodes=40, kmax=kmax, seed=3)
         assert np.max(np.abs(f - g)) < 1e-12
+
+
+def test_separable_spectral_field_equals_fft_route():
+    """The serving loop's device generator (torch, here on the CPU) evaluates
+    the same Fourier sum as the FFT route used for the named workloads."""
+    import torch
+    from paper_2210_06528_amd import workloads as W
+    from paper_2210_06528_amd.serve import spectral_field_torch
+    for shape, kmax in [((40, 36, 30), 6), ((50, 44), 8), ((33, 65, 48), 4)]:
+        f = spectral_field_torch(shape, kmax, seed=7, device="cpu").numpy()
+        g = W.field_spectral(shape, kmax=kmax, seed=7, dtype=np.float32)
+        assert np.max(np.abs(f - g)) < 2e-6
