@@ -113,6 +113,10 @@ hipError_t run_chain(Handle &h, const Tin *in, Dims d, const std::vector<Step> &
 template <typename T>
 hipError_t project(Handle &h, const T *q) {
   TimeScope ts(h, MFA_K_PROJECT);
+  if (grid_pass_ok(h)) {
+    hipError_t e = launch_project_grid(h, q, sizeof(T) == sizeof(float));
+    if (e != hipErrorNotSupported) return e;
+  }
   std::vector<Step> st;
   for (int a = 2; a >= 0; --a)
     if (h.ax[a].active) st.push_back({a, &h.ax[a].NT});
@@ -601,6 +605,15 @@ mfa_status mfa_decode(mfa_handle *H, void *out_dev, mfa_dtype out_dtype, const i
   }
   hipError_t e;
   TimeScope ts(h, MFA_K_DECODE);
+  if (out_dtype != MFA_F32 && out_dtype != MFA_F64) return fail(MFA_EINVAL, "bad dtype");
+  if (grid_pass_ok(h)) {
+    int r[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a)
+      if (h.ax[a].active && deriv) r[a] = deriv[a - (3 - h.dim)];
+    e = launch_decode_grid(h, out_dev, out_dtype == MFA_F32, r);
+    if (e == hipSuccess) return MFA_OK;
+    if (e != hipErrorNotSupported) return hip_fail(e, "decode");
+  }
   if (out_dtype == MFA_F32)
     e = run_chain<double, float>(h, h.P, ctrl_dims(h), st, (float *)out_dev, EPI_STORE, nullptr, 0,
                                  nullptr, 0, h.s1, h.s2);

@@ -1,0 +1,427 @@
+// Streaming passes between the data grid and the control grid (Section 2.1:
+// the tensor-product basis N = N_0 x N_1 x N_2 of eq. nurbs-basis, W = 1):
+//
+//   projection  c = (N_0^T x N_1^T x N_2^T) Q      (the right-hand side N^T Q)
+//   decode      f = (N_0 x N_1 x N_2) P            (any derivative order per axis)
+//
+// Each is two kernels.  The inner kernel handles axes 1 and 2 of one slab i0
+// (axis 2 contiguous, staged through LDS); the outer kernel handles axis 0
+// with one thread per contiguous column.  Every element of the data grid is
+// read (projection) or written (decode) once, up to the few rows that two
+// neighbouring chunks share.
+//
+// Along an axis with m data points and n control points, point i touches the
+// p+1 control points span(i)-p .. span(i), and span grows by at most one from
+// one point to the next (m >= n).  A pass that walks the points in order
+// therefore keeps just p+1 open control rows in registers: when the span
+// moves on, the oldest row has received all its contributions and is written
+// (projection), or the next control row is read (decode).
+#include "mfa_internal.hpp"
+
+namespace mfa {
+
+namespace {
+
+__device__ __forceinline__ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// span(i) = min(n-1, p + floor(i (n-p) / (m-1))): the first point whose span
+// is >= s, and the last point whose span is <= s.
+__device__ __forceinline__ int64_t first_span_ge(int s, int64_t m, int n, int p) {
+  if (s <= p) return 0;
+  return cdiv((int64_t)(s - p) * (m - 1), n - p);
+}
+__device__ __forceinline__ int64_t last_span_le(int s, int64_t m, int n, int p) {
+  if (s >= n - 1) return m - 1;
+  return cdiv((int64_t)(s - p + 1) * (m - 1), n - p) - 1;
+}
+
+// Basis rows of one axis: point i has the p+1 values val[i*L + q] at control
+// points span[i]-p+q.
+struct Rows {
+  const int *span;
+  const double *val;
+  int L;
+  int64_t m;
+  int n;
+};
+
+// ---------------------------------------------------------------------------
+// projection, inner: out[i0][k1][k2] = sum_{i1,i2} N_1[i1][k1] N_2[i2][k2] Q[i0][i1][i2]
+// Workgroup: slab i0 (grid.y), a chunk [K1a, K1b) of k1 and a chunk of
+// blockDim k2 (grid.x).  RI rows of Q (the columns the k2 chunk needs) are
+// staged in LDS; each thread contracts them along axis 2 for its k2 with its
+// N_2^T row held in registers (NTR values at most), then folds the result
+// into the p+1 open k1 rows.
+template <typename TQ, int P, int RI, int NTR>
+__global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, double *__restrict__ out,
+                                                    int64_t m1, int64_t m2, int n1, int n2, int K1C,
+                                                    Rows r1, const int *__restrict__ nt2col,
+                                                    const int *__restrict__ nt2len,
+                                                    const double *__restrict__ nt2val, int LT2) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  TQ *rows = reinterpret_cast<TQ *>(smem);
+  const int BS = blockDim.x, tid = threadIdx.x;
+  const int nk1c = (n1 + K1C - 1) / K1C;
+  const int ck1 = blockIdx.x % nk1c, ck2 = blockIdx.x / nk1c;
+  const int64_t i0 = blockIdx.y;
+  const int K1a = ck1 * K1C, K1b = min(n1, K1a + K1C);
+  const int K2a = ck2 * BS, K2b = min(n2, K2a + BS);
+  const int k2 = K2a + tid;
+  const bool act = k2 < K2b;
+  const int64_t c_lo = first_span_ge(max(K2a, P), m2, n2, P);
+  const int64_t c_hi = last_span_le(min(K2b - 1 + P, n2 - 1), m2, n2, P) + 1;
+  const int W = (int)(c_hi - c_lo);
+  const int64_t r_lo = first_span_ge(max(K1a, P), m1, n1, P);
+  const int64_t r_hi = last_span_le(min(K1b - 1 + P, n1 - 1), m1, n1, P) + 1;
+
+  // this thread's row of N_2^T: contiguous data points from col0
+  double tv[NTR];
+  int len = 0, off = 0;
+  if (act) {
+    len = nt2len[k2];
+    off = (int)(nt2col[(int64_t)k2 * LT2] - c_lo);
+  }
+#pragma unroll
+  for (int t = 0; t < NTR; ++t) tv[t] = (act && t < len) ? nt2val[(int64_t)k2 * LT2 + t] : 0.0;
+
+  double acc[P + 1];
+#pragma unroll
+  for (int q = 0; q <= P; ++q) acc[q] = 0.0;
+  int cur = r1.span[r_lo];
+  double *dst = out + (i0 * n1) * (int64_t)n2 + k2;
+
+  for (int64_t g = r_lo; g < r_hi; g += RI) {
+    const int nr = (int)min((int64_t)RI, r_hi - g);
+    __syncthreads();   // the previous group's rows have been consumed
+    const TQ *src = Q + (i0 * m1 + g) * m2 + c_lo;
+    for (int rr = 0; rr < nr; ++rr)
+      for (int c = tid; c < W; c += BS) rows[rr * W + c] = src[(int64_t)rr * m2 + c];
+    __syncthreads();
+    for (int rr = 0; rr < nr; ++rr) {
+      const int64_t i1 = g + rr;
+      double v = 0.0;
+      const TQ *row = rows + rr * W + off;
+#pragma unroll
+      for (int t = 0; t < NTR; ++t)
+        if (t < len) v += tv[t] * (double)row[t];
+      const int s = r1.span[i1];
+      if (s != cur) {   // s == cur + 1: row cur-p is complete
+        const int k1 = cur - P;
+        if (act && k1 >= K1a && k1 < K1b) dst[(int64_t)k1 * n2] = acc[0];
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q] = acc[q + 1];
+        acc[P] = 0.0;
+        cur = s;
+      }
+      const double *w = r1.val + i1 * r1.L;
+#pragma unroll
+      for (int q = 0; q <= P; ++q) acc[q] += w[q] * v;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q <= P; ++q) {
+    const int k1 = cur - P + q;
+    if (act && k1 >= K1a && k1 < K1b) dst[(int64_t)k1 * n2] = acc[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// projection, outer: out[k0][j] = sum_i0 N_0[i0][k0] in[i0][j] for a chunk
+// [K0a, K0b) of k0 (grid.y) and 256 consecutive columns j (grid.x).
+template <int P>
+__global__ void __launch_bounds__(256) k_proj_outer(const double *__restrict__ in, double *__restrict__ out,
+                                                    int64_t J, int n0, int K0C, Rows r0) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = j < J;
+  const int K0a = blockIdx.y * K0C, K0b = min(n0, K0a + K0C);
+  const int64_t r_lo = first_span_ge(max(K0a, P), r0.m, n0, P);
+  const int64_t r_hi = last_span_le(min(K0b - 1 + P, n0 - 1), r0.m, n0, P) + 1;
+  double acc[P + 1];
+#pragma unroll
+  for (int q = 0; q <= P; ++q) acc[q] = 0.0;
+  int cur = r0.span[r_lo];
+  const double *src = in + (act ? j : 0);
+  constexpr int U = 4;
+  for (int64_t g = r_lo; g < r_hi; g += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = (act && g + u < r_hi) ? src[(g + u) * J] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i0 = g + u;
+      if (i0 < r_hi) {
+        const int s = r0.span[i0];
+        if (s != cur) {
+          const int k0 = cur - P;
+          if (act && k0 >= K0a && k0 < K0b) out[(int64_t)k0 * J + j] = acc[0];
+#pragma unroll
+          for (int q = 0; q < P; ++q) acc[q] = acc[q + 1];
+          acc[P] = 0.0;
+          cur = s;
+        }
+        const double *w = r0.val + i0 * r0.L;
+#pragma unroll
+        for (int q = 0; q <= P; ++q) acc[q] += w[q] * v[u];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q <= P; ++q) {
+    const int k0 = cur - P + q;
+    if (act && k0 >= K0a && k0 < K0b) out[(int64_t)k0 * J + j] = acc[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// decode, outer: out[i0][j] = sum_q N_0[i0][q] in[span0(i0)-p+q][j] for a
+// chunk of data rows i0 (grid.y) and 256 consecutive columns j (grid.x).  The
+// p+1 control rows under the current span sit in registers, the next one is
+// read ahead.
+template <int P>
+__global__ void __launch_bounds__(256) k_dec_outer(const double *__restrict__ in, double *__restrict__ out,
+                                                   int64_t J, int I0C, Rows r0) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  const int64_t I0a = (int64_t)blockIdx.y * I0C, I0b = min(r0.m, I0a + I0C);
+  int cur = r0.span[I0a];
+  double win[P + 1];
+#pragma unroll
+  for (int q = 0; q <= P; ++q) win[q] = in[(int64_t)(cur - P + q) * J + j];
+  double nxt = cur + 1 < r0.n ? in[(int64_t)(cur + 1) * J + j] : 0.0;
+  for (int64_t i0 = I0a; i0 < I0b; ++i0) {
+    const int s = r0.span[i0];
+    if (s != cur) {   // s == cur + 1
+#pragma unroll
+      for (int q = 0; q < P; ++q) win[q] = win[q + 1];
+      win[P] = nxt;
+      cur = s;
+      nxt = cur + 1 < r0.n ? in[(int64_t)(cur + 1) * J + j] : 0.0;
+    }
+    const double *w = r0.val + i0 * r0.L;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q <= P; ++q) v += w[q] * win[q];
+    out[i0 * J + j] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// decode, inner: out[i0][i1][i2] = sum_{q1,q2} N_1[i1][q1] N_2[i2][q2]
+//                                  in[i0][span1(i1)-p+q1][span2(i2)-p+q2]
+// Workgroup: slab i0 (grid.y) and a chunk of data rows i1 (grid.x).  Phase A:
+// thread k2 (< n2 <= blockDim) expands axis 1 from its p+1 open control rows
+// (registers) into RI rows in LDS.  Phase B: thread i2 (IS points per thread,
+// their N_2 rows in registers) expands axis 2 from LDS and writes the output.
+template <typename TO, int P, int RI, int IS>
+__global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in, TO *__restrict__ out,
+                                                   int64_t m1, int64_t m2, int n1, int n2, int I1C,
+                                                   Rows r1, Rows r2) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *rows = reinterpret_cast<double *>(smem);   // [RI][n2]
+  const int BS = blockDim.x, tid = threadIdx.x;
+  const int64_t i0 = blockIdx.y;
+  const int64_t I1a = (int64_t)blockIdx.x * I1C, I1b = min(m1, I1a + I1C);
+  const bool actk = tid < n2;
+  const double *slab = in + i0 * (int64_t)n1 * n2 + (actk ? tid : 0);
+
+  // phase-B rows of N_2 for this thread's points
+  double w2[IS][P + 1];
+  int c2[IS];
+#pragma unroll
+  for (int s = 0; s < IS; ++s) {
+    const int64_t i2 = tid + (int64_t)s * BS;
+    const bool ok = i2 < m2;
+    c2[s] = ok ? r2.span[i2] - P : 0;
+#pragma unroll
+    for (int q = 0; q <= P; ++q) w2[s][q] = ok ? r2.val[i2 * r2.L + q] : 0.0;
+  }
+
+  int cur = r1.span[I1a];
+  double win[P + 1];
+#pragma unroll
+  for (int q = 0; q <= P; ++q) win[q] = actk ? slab[(int64_t)(cur - P + q) * n2] : 0.0;
+  double nxt = (actk && cur + 1 < n1) ? slab[(int64_t)(cur + 1) * n2] : 0.0;
+  TO *dst = out + i0 * m1 * m2;
+
+  for (int64_t g = I1a; g < I1b; g += RI) {
+    const int nr = (int)min((int64_t)RI, I1b - g);
+    for (int rr = 0; rr < nr; ++rr) {
+      const int64_t i1 = g + rr;
+      const int s = r1.span[i1];
+      if (s != cur) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) win[q] = win[q + 1];
+        win[P] = nxt;
+        cur = s;
+        nxt = (actk && cur + 1 < n1) ? slab[(int64_t)(cur + 1) * n2] : 0.0;
+      }
+      const double *w = r1.val + i1 * r1.L;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q <= P; ++q) v += w[q] * win[q];
+      if (actk) rows[rr * n2 + tid] = v;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < nr; ++rr) {
+      const double *row = rows + rr * n2;
+      TO *o = dst + (g + rr) * m2;
+#pragma unroll
+      for (int s = 0; s < IS; ++s) {
+        const int64_t i2 = tid + (int64_t)s * BS;
+        if (i2 < m2) {
+          double v = 0.0;
+#pragma unroll
+          for (int q = 0; q <= P; ++q) v += w2[s][q] * row[c2[s] + q];
+          o[i2] = (TO)v;
+        }
+      }
+    }
+    __syncthreads();   // rows are rewritten by the next group
+  }
+}
+
+inline unsigned nblk(int64_t n, int64_t b) { return (unsigned)((n + b - 1) / b); }
+
+Rows rows_of(const Axis &X, int r) {
+  return Rows{X.d_span, X.N[r].val, X.N[r].L, X.m, X.n};
+}
+
+constexpr int kProjRI = 8;
+constexpr int kDecRI = 8;
+
+int pick_chunk(int64_t parallel, int n, int lo) {
+  // largest chunk in {64, 32, 16, lo} that still gives >= 2048 workgroups
+  for (int c : {64, 32, 16})
+    if (c >= lo && parallel * ((n + c - 1) / c) >= 2048) return c;
+  return lo;
+}
+
+template <int P>
+hipError_t project_p(Handle &h, const void *q, bool f32) {
+  const Axis &X0 = h.ax[0], &X1 = h.ax[1], &X2 = h.ax[2];
+  const int64_t m0 = X0.m, m1 = X1.m, m2 = X2.m;
+  const int n0 = X0.n, n1 = X1.n, n2 = X2.n;
+  // k2 chunk: up to 256 threads, narrower when the grid would be too small
+  int BS = n2 >= 256 ? 256 : ((n2 + 63) / 64) * 64;
+  while (BS > 64 && m0 * nblk(n1, 8) * nblk(n2, BS) < 1024) BS = ((BS / 2 + 63) / 64) * 64;
+  const int nk2c = (n2 + BS - 1) / BS;
+  const int K1C = pick_chunk(m0 * nk2c, n1, 8);
+  const int nk1c = (n1 + K1C - 1) / K1C;
+  // widest column range one k2 chunk needs (host copy of the span rule)
+  auto first_ge = [&](int s) -> int64_t {
+    return s <= P ? 0 : ((int64_t)(s - P) * (m2 - 1) + (n2 - P) - 1) / (n2 - P);
+  };
+  auto last_le = [&](int s) -> int64_t {
+    return s >= n2 - 1 ? m2 - 1 : ((int64_t)(s - P + 1) * (m2 - 1) + (n2 - P) - 1) / (n2 - P) - 1;
+  };
+  int64_t W = 0;
+  for (int c = 0; c < nk2c; ++c) {
+    const int a = c * BS, b = std::min(n2, a + BS);
+    W = std::max(W, last_le(std::min(b - 1 + P, n2 - 1)) + 1 - first_ge(std::max(a, P)));
+  }
+  const size_t esz = f32 ? sizeof(float) : sizeof(double);
+  const size_t lds = (size_t)kProjRI * W * esz;
+  if (lds > 64 * 1024) return hipErrorNotSupported;
+  const bool outer = X0.active;
+  if (outer && h.s1n < m0 * n1 * (int64_t)n2) return hipErrorNotSupported;
+  double *T = outer ? h.s1 : h.c;
+  const Rows r1 = rows_of(X1, 0);
+  const dim3 g1(nk1c * nk2c, (unsigned)m0);
+  const int LT2 = X2.NT.L;
+#define MFA_PI(TQ, NTR)                                                                            \
+  k_proj_inner<TQ, P, kProjRI, NTR><<<g1, BS, lds, h.stream>>>(                                     \
+      reinterpret_cast<const TQ *>(q), T, m1, m2, n1, n2, K1C, r1, X2.NT.col, X2.NT.len, X2.NT.val, \
+      LT2)
+  if (LT2 <= 12) {
+    if (f32) MFA_PI(float, 12);
+    else MFA_PI(double, 12);
+  } else if (LT2 <= 24) {
+    if (f32) MFA_PI(float, 24);
+    else MFA_PI(double, 24);
+  } else if (LT2 <= 48) {
+    if (f32) MFA_PI(float, 48);
+    else MFA_PI(double, 48);
+  } else {
+    return hipErrorNotSupported;
+  }
+#undef MFA_PI
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !outer) return e;
+  const int64_t J = (int64_t)n1 * n2;
+  const int K0C = pick_chunk((int64_t)nblk(J, 256), n0, 8);
+  const dim3 g0(nblk(J, 256), nblk(n0, K0C));
+  k_proj_outer<P><<<g0, 256, 0, h.stream>>>(T, h.c, J, n0, K0C, rows_of(X0, 0));
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t decode_p(Handle &h, void *out, bool f32, const int r[3]) {
+  const Axis &X0 = h.ax[0], &X1 = h.ax[1], &X2 = h.ax[2];
+  const int64_t m0 = X0.m, m1 = X1.m, m2 = X2.m;
+  const int n1 = X1.n, n2 = X2.n;
+  if (n2 > 256) return hipErrorNotSupported;
+  const int BS = m2 >= 256 || n2 > 128 ? 256 : (int)std::max<int64_t>(64, ((std::max<int64_t>(m2, n2) + 63) / 64) * 64);
+  const int IS = (int)((m2 + BS - 1) / BS);
+  if (IS > 4) return hipErrorNotSupported;
+  const double *src = h.P;
+  if (X0.active) {
+    if (h.s1n < m0 * n1 * (int64_t)n2) return hipErrorNotSupported;
+    const int64_t J = (int64_t)n1 * n2;
+    const int I0C = 64;
+    const dim3 g0(nblk(J, 256), nblk(m0, I0C));
+    k_dec_outer<P><<<g0, 256, 0, h.stream>>>(h.P, h.s1, J, I0C, rows_of(X0, r[0]));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src = h.s1;
+  }
+  int I1C = 64;
+  while (I1C > 8 && m0 * (int64_t)nblk(m1, I1C) < 2048) I1C /= 2;
+  const dim3 g1(nblk(m1, I1C), (unsigned)m0);
+  const size_t lds = (size_t)kDecRI * n2 * sizeof(double);
+  const Rows r1 = rows_of(X1, r[1]), r2 = rows_of(X2, r[2]);
+#define MFA_DI(TO, IS_)                                                                            \
+  k_dec_inner<TO, P, kDecRI, IS_><<<g1, BS, lds, h.stream>>>(src, reinterpret_cast<TO *>(out), m1, \
+                                                             m2, n1, n2, I1C, r1, r2)
+  if (IS == 1) {
+    if (f32) MFA_DI(float, 1);
+    else MFA_DI(double, 1);
+  } else if (IS == 2) {
+    if (f32) MFA_DI(float, 2);
+    else MFA_DI(double, 2);
+  } else {
+    if (f32) MFA_DI(float, 4);
+    else MFA_DI(double, 4);
+  }
+#undef MFA_DI
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool grid_pass_ok(const Handle &h) { return h.ax[1].active && h.ax[2].active && h.p >= 1 && h.p <= 6; }
+
+hipError_t launch_project_grid(Handle &h, const void *q, bool f32) {
+  switch (h.p) {
+    case 1: return project_p<1>(h, q, f32);
+    case 2: return project_p<2>(h, q, f32);
+    case 3: return project_p<3>(h, q, f32);
+    case 4: return project_p<4>(h, q, f32);
+    case 5: return project_p<5>(h, q, f32);
+    case 6: return project_p<6>(h, q, f32);
+    default: return hipErrorNotSupported;
+  }
+}
+
+hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3]) {
+  switch (h.p) {
+    case 1: return decode_p<1>(h, out, f32, r);
+    case 2: return decode_p<2>(h, out, f32, r);
+    case 3: return decode_p<3>(h, out, f32, r);
+    case 4: return decode_p<4>(h, out, f32, r);
+    case 5: return decode_p<5>(h, out, f32, r);
+    case 6: return decode_p<6>(h, out, f32, r);
+    default: return hipErrorNotSupported;
+  }
+}
+
+}  // namespace mfa

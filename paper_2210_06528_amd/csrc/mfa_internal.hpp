@@ -194,6 +194,12 @@ hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U);
 
 // mixed BF16 correction on the matrix cores
 size_t mfma_lds(int npad);
+// streaming projection / decode between the data grid and the control grid
+// (axes 1 and 2 active, p <= 6); hipErrorNotSupported when a shape needs the
+// generic pass chain instead (nothing is launched then)
+bool grid_pass_ok(const Handle &h);
+hipError_t launch_project_grid(Handle &h, const void *q, bool f32);
+hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3]);
 bool mfma_fits(int npad);
 hipError_t setup_mfma(Handle *h, int a);
 hipError_t launch_mfma_correct(Handle &h, int axis, const float *in, float *out, bool add);
