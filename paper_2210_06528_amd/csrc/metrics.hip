@@ -60,9 +60,14 @@ __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ 
                                                      unsigned long long *slots) {
   constexpr int jb = JB;
   extern __shared__ double V[];   // [jb][nc]
+  // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that
+  // each XCD takes a contiguous run of rows and their U rows stay in that
+  // XCD's L2 (a bijection on [0, gridDim.x)).
+  const unsigned G = gridDim.x, xcd = blockIdx.x % 8, per = G / 8, rem = G % 8;
+  const unsigned lb = xcd * per + min(xcd, rem) + blockIdx.x / 8;
   const int nbg = (Ob.m + jb - 1) / jb;
-  const int row = blockIdx.x / nbg;
-  const int ib0 = (blockIdx.x % nbg) * jb;
+  const int row = lb / nbg;
+  const int ib0 = (lb % nbg) * jb;
   const int nib = min(jb, Ob.m - ib0);
   const int nc = has_c ? Oc.n : 1;
   for (int e = threadIdx.x; e < jb * nc; e += blockDim.x) {
@@ -241,6 +246,153 @@ __global__ void __launch_bounds__(256) k_jump_project_inner(const TG *__restrict
     if (r < p) dst[row0 + r] = acc[r];
 }
 
+// Interface projection along the contiguous axis: a workgroup stages LPB
+// whole grid lines of g in LDS (one coalesced read) and computes every
+// (line, interface) pair, all orders from one pass over the interface's
+// support.
+template <typename TG>
+__global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict__ g,
+                                                            double *__restrict__ U, int64_t nlines,
+                                                            int n2, int nif, int p, int LPB,
+                                                            const int *__restrict__ Jcol,
+                                                            const int *__restrict__ Jlen,
+                                                            const double *__restrict__ Jval, int LJ) {
+  extern __shared__ double sg[];   // [LPB][n2]
+  const int64_t l0 = (int64_t)blockIdx.x * LPB;
+  const int nl = (int)min((int64_t)LPB, nlines - l0);
+  const TG *src = g + l0 * n2;
+  for (int e = threadIdx.x; e < nl * n2; e += blockDim.x) sg[e] = tod(src[e]);
+  __syncthreads();
+  for (int it = threadIdx.x; it < nl * nif; it += blockDim.x) {
+    const int li = it / nif, b = it - li * nif;
+    const int row0 = b * p;
+    const int c0 = Jcol[(int64_t)row0 * LJ];
+    const int len = Jlen[row0];
+    const double *x = sg + li * n2 + c0;
+    double acc[kMaxP];
+#pragma unroll
+    for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
+    for (int t = 0; t < len; ++t) {
+      const double v = x[t];
+#pragma unroll
+      for (int r = 0; r < kMaxP; ++r)
+        if (r < p) acc[r] += Jval[(int64_t)(row0 + r) * LJ + t] * v;
+    }
+    double *dst = U + (l0 + li) * (int64_t)(nif * p) + row0;
+#pragma unroll
+    for (int r = 0; r < kMaxP; ++r)
+      if (r < p) dst[r] = acc[r];
+  }
+}
+
+// S_r^a for all axes and orders r < p.  Workgroup: a 16 x 64 tile of
+// (k1, k2) and a chunk [k0a, k0b) of k0; 64 x 4 threads, each owning 4 rows of
+// the tile.  Each plane of P (tile plus p-1 halo rows and columns) is staged
+// in LDS once for the axis-1 and axis-2 coefficients; every thread keeps its
+// points' last p values along axis 0 in registers for the axis-0
+// coefficients, which lag p-1 planes behind (the planes past the chunk are
+// read as halo, those past the grid as zeros that no coefficient uses).
+template <int PP>
+__global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restrict__ P, int n0, int n1,
+                                                           int n2, int K0C, DTab d0, DTab d1, DTab d2,
+                                                           int act0, int act1, int act2,
+                                                           unsigned long long *slots) {
+  constexpr int TX = 64, TY = 16, RY = 4, H = PP - 1;
+  __shared__ double tile[TY + H][TX + H + 1];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int k2a = blockIdx.x * TX, k1a = blockIdx.y * TY;
+  const int k0a = blockIdx.z * K0C, k0b = min(n0, k0a + K0C);
+  const int k2 = k2a + tx;
+  // this thread's axis-2 coefficient rows (fixed k2)
+  double dv2[PP][PP];
+  {
+    int rowoff = 0;
+#pragma unroll
+    for (int r = 0; r < PP; ++r) {
+#pragma unroll
+      for (int q = 0; q < PP; ++q)
+        dv2[r][q] = (act2 && q <= r && k2 <= n2 - 1 - r) ? d2.val[(int64_t)(rowoff + k2) * d2.L + q] : 0.0;
+      rowoff += n2 - r;
+    }
+  }
+  double win[RY][PP];
+  double mx[3][PP];
+#pragma unroll
+  for (int j = 0; j < RY; ++j)
+#pragma unroll
+    for (int q = 0; q < PP; ++q) win[j][q] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int r = 0; r < PP; ++r) mx[a][r] = 0.0;
+
+  for (int k0 = k0a; k0 < k0b + H; ++k0) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < (TY + H) * (TX + H); e += 256) {
+      const int r = e / (TX + H), c = e - r * (TX + H);
+      const int k1 = k1a + r, kk2 = k2a + c;
+      tile[r][c] = (k0 < n0 && k1 < n1 && kk2 < n2) ? P[((int64_t)k0 * n1 + k1) * n2 + kk2] : 0.0;
+    }
+    __syncthreads();
+    const bool own = k0 < k0b;
+    const int idx = k0 - H;   // axis-0 index whose window is complete
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      const int ly = ty + 4 * j, k1 = k1a + ly;
+      const double c = tile[ly][tx];
+#pragma unroll
+      for (int q = 0; q + 1 < PP; ++q) win[j][q] = win[j][q + 1];
+      win[j][PP - 1] = c;
+      if (k1 >= n1 || k2 >= n2) continue;
+      if (own && act2) {
+#pragma unroll
+        for (int r = 0; r < PP; ++r) {
+          if (k2 <= n2 - 1 - r) {
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q <= r; ++q) sum += dv2[r][q] * tile[ly][tx + q];
+            mx[2][r] = fmax(mx[2][r], fabs(sum));
+          }
+        }
+      }
+      if (own && act1) {
+        int rowoff = 0;
+#pragma unroll
+        for (int r = 0; r < PP; ++r) {
+          if (k1 <= n1 - 1 - r) {
+            const double *dv = d1.val + (int64_t)(rowoff + k1) * d1.L;
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q <= r; ++q) sum += dv[q] * tile[ly + q][tx];
+            mx[1][r] = fmax(mx[1][r], fabs(sum));
+          }
+          rowoff += n1 - r;
+        }
+      }
+      if (act0 && idx >= k0a && idx < k0b) {
+        int rowoff = 0;
+#pragma unroll
+        for (int r = 0; r < PP; ++r) {
+          if (idx <= n0 - 1 - r) {
+            const double *dv = d0.val + (int64_t)(rowoff + idx) * d0.L;
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q <= r; ++q) sum += dv[q] * win[j][q];
+            mx[0][r] = fmax(mx[0][r], fabs(sum));
+          }
+          rowoff += n0 - r;
+        }
+      }
+    }
+  }
+  const int act[3] = {act0, act1, act2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int r = 0; r < PP; ++r)
+      if (act[a]) slot_max_w(slots, kSlotS + a * kMaxP + r, mx[a][r]);
+}
+
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 DTab dtab(const Axis &X) { return DTab{X.D.len, X.D.col, X.D.val, X.D.L, X.n}; }
@@ -250,7 +402,31 @@ OmTab otab(const Axis &X) {
 
 }  // namespace
 
+template <int PP>
+hipError_t deriv_scale_tiles(Handle &h) {
+  const int n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
+  const unsigned gx = nblk(n2, 64), gy = nblk(n1, 16);
+  int K0C = 32;
+  while (K0C > 4 && (int64_t)gx * gy * nblk(n0, K0C) < 1024) K0C /= 2;
+  const dim3 grid(gx, gy, nblk(n0, K0C));
+  k_deriv_scale_tiles<PP><<<grid, 256, 0, h.stream>>>(h.P, n0, n1, n2, K0C, dtab(h.ax[0]), dtab(h.ax[1]),
+                                                     dtab(h.ax[2]), h.ax[0].active, h.ax[1].active,
+                                                     h.ax[2].active, h.slots);
+  return hipGetLastError();
+}
+
 hipError_t launch_deriv_scale(Handle &h) {
+  switch (h.p) {
+    case 1: return deriv_scale_tiles<1>(h);
+    case 2: return deriv_scale_tiles<2>(h);
+    case 3: return deriv_scale_tiles<3>(h);
+    case 4: return deriv_scale_tiles<4>(h);
+    case 5: return deriv_scale_tiles<5>(h);
+    case 6: return deriv_scale_tiles<6>(h);
+    case 7: return deriv_scale_tiles<7>(h);
+    case 8: return deriv_scale_tiles<8>(h);
+    default: break;
+  }
   const int n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
   const int bs = n2 >= 256 ? 256 : ((n2 + 63) / 64) * 64;
   const int rows = 32;
@@ -264,6 +440,13 @@ hipError_t launch_deriv_scale(Handle &h) {
 template <typename TG>
 hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U) {
   const Axis &X = h.ax[a];
+  if (a == 2 && (int64_t)X.n * 8 <= 32768) {
+    const int64_t nlines = (int64_t)h.ax[0].n * h.ax[1].n;
+    const int LPB = std::max(1, std::min(32, 32768 / (8 * X.n)));
+    k_jump_project_lines<TG><<<nblk(nlines, LPB), 256, sizeof(double) * LPB * X.n, h.stream>>>(
+        g, U, nlines, X.n, X.B - 1, h.p, LPB, X.J.col, X.J.len, X.J.val, X.J.L);
+    return hipGetLastError();
+  }
   if (a == 2) {
     const int64_t nlines = (int64_t)h.ax[0].n * h.ax[1].n;
     const dim3 grid(nblk(nlines, 256), X.B - 1);
