@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--max-sweeps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=2)
-    ap.add_argument("--no-validate", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="skip timing the FP64 GPU paths on the same input")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="run only a plain device copy of MIB MiB (float32, read once, "
                          "written once) to calibrate the HBM byte counters, then exit")
@@ -110,6 +111,46 @@ def roofline(w, ktimes):
     return {"kernel": "k_resid", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
             "bytes_per_launch": per, "avg_launch_us": avg_s * 1e6, "launches": n}
+
+
+def compare_fp64(w, q, out, max_sweeps, tol, args, ms_mixed):
+    """The same encode on the plain FP64 GPU paths: the control-space form
+    (banded solves in float64) and the literal per-subdomain data-box form of
+    Algorithm 1.  Reports their time per step and the largest decoded
+    difference of this run's result from the FP64 fit, relative to the
+    largest decoded value."""
+    import torch
+    from paper_2210_06528_amd import _lib
+    ref = None
+    rep = {}
+    for rhs, nsteps in (("normal", 3), ("databox", 1)):
+        e = _lib.Encoder(w.npts, w.degree, w.sizes, w.overlap, "fp64", w.combine, rhs,
+                         device=q.device)
+        o = torch.empty_like(out)
+
+        def step():
+            e.recreate()
+            st = e.encode(q, max_sweeps, tol, args.check_every)
+            e.decode(o)
+            return st
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            st = step()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) * 1e3 / nsteps
+        rep[f"{rhs}_ms_per_step"] = t
+        rep[f"{rhs}_sweeps"] = st["sweep"]
+        rep[f"speedup_vs_fp64_{rhs}"] = t / ms_mixed
+        if rhs == "normal":
+            ref = o.double()
+        e.close()
+        del e, o
+    rep["max_rel_decode_err_vs_fp64"] = float((out.double() - ref).abs().max() / ref.abs().max())
+    print(f"[bench] fp64 paths: {rep}", file=sys.stderr, flush=True)
+    return rep
 
 
 def cpu_baseline(w, Q, nsweeps_gpu, nsample):
@@ -288,6 +329,8 @@ def main():
     }
     res["kernels_ms"] = {k: {"total_ms": v[0] / args.steps, "launches": v[1] / args.steps}
                          for k, v in ktimes.items()}
+    if w.precision != "fp64" and not args.no_fp64_compare:
+        res["fp64_paths"] = compare_fp64(w, q, out, max_sweeps, tol, args, ms)
     res["roofline"] = roofline(w, ktimes)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
