@@ -485,7 +485,9 @@ static mfa_status load_q(Handle &h, const void *q, mfa_dtype dt) {
 }
 
 static mfa_status do_sweep(Handle &h, bool metrics) {
-  hipError_t e = launch_zero_slots(h.stream, h.slots, kNumSlots * kSlotCopies);
+  // record the previous sweep's max |correction| (sweep h.sweep, 1-based)
+  hipError_t e = launch_zero_slots(h.stream, h.slots, kNumSlots * kSlotCopies,
+                                   h.sweep >= 1 ? h.hist : nullptr, (h.sweep - 1 + kHist) % kHist);
   if (e != hipSuccess) return hip_fail(e, "zero slots");
   if (h.rhs == MFA_RHS_DATABOX) {
     e = sweep_databox(h, metrics);
@@ -543,13 +545,14 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
   h.warm = false;
   mfa_step_stats st{};
   bool converged = false;
-  // check schedule: fixed stride, or (check_every <= 0) predicted from the
-  // observed geometric decay of the jumps between the last two checks
-  // adaptive: first checks at sweeps 4 and 8 (past the first sweeps'
-  // transient), then at the predicted crossing of the tolerance
-  int next_check = jump_tol > 0.0 ? (check_every > 0 ? check_every : 4) : max_sweeps;
-  double prev_j = -1.0;
-  int prev_k = 0;
+  // Check schedule: a fixed stride, or (check_every <= 0) predicted.  Past
+  // the first sweeps' transient the jumps decay at the same geometric rate
+  // as max |correction|, which every sweep reduces anyway (recorded in
+  // h.hist): a check at sweep k with largest jump J predicts the crossing of
+  // the tolerance after log(tol / J) / log(rate) more sweeps, the rate taken
+  // from the corrections of sweeps k-2 .. k.  The first check comes at sweep
+  // 6, after the transient.
+  int next_check = jump_tol > 0.0 ? (check_every > 0 ? check_every : 6) : max_sweeps;
   for (int k = 1; k <= max_sweeps; ++k) {
     const bool check = k == next_check || k == max_sweeps;
     s = do_sweep(h, check);
@@ -572,16 +575,19 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
       double jm = 0.0;
       for (int r = 0; r < h.p; ++r) jm = std::max(jm, st.jump[r]);
       int stride = 4;
-      if (prev_j > 0.0 && jm < prev_j && jm > 0.0) {
-        const double rate = std::pow(jm / prev_j, 1.0 / (k - prev_k));
-        const double need = std::log(jump_tol / jm) / std::log(rate);
-        // never extrapolate past twice the last interval (the jumps of the
-        // highest derivative order plateau for a few sweeps before the
-        // geometric decay sets in)
-        stride = (int)std::min(std::min(32.0, 2.0 * (k - prev_k)), std::max(1.0, std::ceil(need)));
+      if (k >= 3) {
+        double d2 = 0.0;
+        HIP_CHECK(hipMemcpyAsync(&d2, h.hist + (k - 3) % kHist, sizeof(double), hipMemcpyDeviceToHost,
+                                 h.stream),
+                  "read correction history");
+        HIP_CHECK(hipStreamSynchronize(h.stream), "read correction history");
+        const double d0 = st.max_dP;
+        if (d2 > 0.0 && d0 > 0.0 && d0 < d2 && jm > 0.0) {
+          const double rate = std::sqrt(d0 / d2);
+          const double need = std::log(jump_tol / jm) / std::log(rate);
+          stride = (int)std::min(32.0, std::max(1.0, std::ceil(need)));
+        }
       }
-      prev_j = jm;
-      prev_k = k;
       next_check = k + stride;
     }
   }

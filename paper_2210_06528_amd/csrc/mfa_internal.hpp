@@ -111,6 +111,7 @@ struct Handle {
   int64_t b1n = 0, b2n = 0;
   unsigned long long *slots = nullptr;   // reductions, see kSlot*
   int *flag = nullptr;                   // setup error flag
+  double *hist = nullptr;                // max |correction| of recent sweeps (ring of kHist)
   bool have_rhs = false;
   const void *q = nullptr;  // data of the last encode / step (read every sweep in DATABOX mode)
   int q_dtype = 0;
@@ -170,7 +171,11 @@ hipError_t launch_fill(hipStream_t st, double *x, int64_t n, double v);
 template <typename TQ>
 hipError_t launch_box_resid(hipStream_t st, const TQ *q, Dims qd, double *r, Dims rd,
                             const int *qm0, const int *qm1, const int *qm2);
-hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n);
+// zero the reduction slots; first record the previous sweep's max |correction|
+// (slot kSlotMaxDP) into hist[idx] when hist is given
+constexpr int kHist = 64;
+hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n, double *hist = nullptr,
+                             int idx = 0);
 hipError_t launch_maxabs(hipStream_t st, const double *x, int64_t n, unsigned long long *slot);
 
 // setup kernels (one axis at a time)

@@ -373,6 +373,7 @@ size_t layout_workspace(Handle *h, char *base) {
   }
   h->slots = bp.take<unsigned long long>((int64_t)kNumSlots * kSlotCopies);
   h->flag = bp.take<int>(4);
+  h->hist = bp.take<double>(kHist);
   return bp.off + 256;
 }
 
