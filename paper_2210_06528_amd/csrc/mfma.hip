@@ -57,7 +57,9 @@ __device__ __forceinline__ floatx4 mfma3(const bf16x8 &ahi, const bf16x8 &alo, c
   return acc;
 }
 
-constexpr int kIT = 32;   // columns per workgroup on the strided axes
+constexpr int kIT = 32;    // columns per workgroup on the strided axes
+constexpr int kStage = 16; // staging loads per thread issued before the first wait
+constexpr int kPre = 4;    // K chunks of a tile's M fragments requested up front
 
 // Strided axis: the array is [outer][n][inner] (FP32); workgroup = (one outer
 // index, kIT columns of inner), all n output rows.  IN[:, i0:i0+kIT] is staged
@@ -78,11 +80,21 @@ __global__ void __launch_bounds__(256) k_mfma_strided(const float *__restrict__ 
   __hip_bfloat16 *Thi = T, *Tlo = T + kIT * ld;
   const int64_t o = blockIdx.y;
   const int64_t i0 = (int64_t)blockIdx.x * kIT;
-  for (int e = threadIdx.x; e < npad * kIT; e += 256) {
-    const int j = e / kIT, ii = e - j * kIT;
-    float v = 0.f;
-    if (j < n && i0 + ii < inner) v = in[(o * n + j) * inner + i0 + ii];
-    split_bf16(v, Thi[ii * ld + j], Tlo[ii * ld + j]);
+  // staging: kStage loads per thread in flight before the first wait
+  for (int e0 = 0; e0 < npad * kIT; e0 += 256 * kStage) {
+    float v[kStage];
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = e0 + threadIdx.x + 256 * r;
+      const int j = e / kIT, ii = e - j * kIT;
+      v[r] = (e < npad * kIT && j < n && i0 + ii < inner) ? in[(o * n + j) * inner + i0 + ii] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = e0 + threadIdx.x + 256 * r;
+      const int j = e / kIT, ii = e - j * kIT;
+      if (e < npad * kIT) split_bf16(v[r], Thi[ii * ld + j], Tlo[ii * ld + j]);
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -95,13 +107,33 @@ __global__ void __launch_bounds__(256) k_mfma_strided(const float *__restrict__ 
     for (int s = 0; s < kIT / 16; ++s) acc[s] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int lo = klo[t], nc = knc[t];
     const int64_t moff = (int64_t)(16 * t + r16) * npad + 8 * kq;
-    for (int c = 0; c < nc; ++c) {
+    // the tile's M fragments (all K chunks) are requested before the first MFMA
+    bf16x8 ahi[kPre], alo[kPre];
+#pragma unroll
+    for (int c = 0; c < kPre; ++c) {
+      if (c < nc) {
+        ahi[c] = load8(Mhi + moff + lo + 32 * c);
+        alo[c] = load8(Mlo + moff + lo + 32 * c);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kPre; ++c) {
+      if (c < nc) {
+        const int j0 = lo + 32 * c;
+#pragma unroll
+        for (int s = 0; s < kIT / 16; ++s) {
+          const int toff = (16 * s + r16) * ld + j0 + 8 * kq;
+          acc[s] = mfma3(ahi[c], alo[c], load8(Thi + toff), load8(Tlo + toff), acc[s]);
+        }
+      }
+    }
+    for (int c = kPre; c < nc; ++c) {
       const int j0 = lo + 32 * c;
-      const bf16x8 ahi = load8(Mhi + moff + j0), alo = load8(Mlo + moff + j0);
+      const bf16x8 bh = load8(Mhi + moff + j0), bl = load8(Mlo + moff + j0);
 #pragma unroll
       for (int s = 0; s < kIT / 16; ++s) {
         const int toff = (16 * s + r16) * ld + j0 + 8 * kq;
-        acc[s] = mfma3(ahi, alo, load8(Thi + toff), load8(Tlo + toff), acc[s]);
+        acc[s] = mfma3(bh, bl, load8(Thi + toff), load8(Tlo + toff), acc[s]);
       }
     }
 #pragma unroll
@@ -143,11 +175,21 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
   const int lpw = blockDim.x / 4;          // 16 lines per wave
   __hip_bfloat16 *Lhi = Ls, *Llo = Ls + lpw * ld;
   const int64_t l0 = (int64_t)blockIdx.x * lpw;
-  for (int e = threadIdx.x; e < npad * lpw; e += blockDim.x) {
-    const int li = e / npad, j = e - li * npad;
-    float v = 0.f;
-    if (j < n && l0 + li < nlines) v = in[(l0 + li) * n + j];
-    split_bf16(v, Lhi[li * ld + j], Llo[li * ld + j]);
+  const int nt = blockDim.x;
+  for (int e0 = 0; e0 < npad * lpw; e0 += nt * kStage) {
+    float v[kStage];
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = e0 + threadIdx.x + nt * r;
+      const int li = e / npad, j = e - li * npad;
+      v[r] = (e < npad * lpw && j < n && l0 + li < nlines) ? in[(l0 + li) * n + j] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = e0 + threadIdx.x + nt * r;
+      const int li = e / npad, j = e - li * npad;
+      if (e < npad * lpw) split_bf16(v[r], Lhi[li * ld + j], Llo[li * ld + j]);
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -159,7 +201,22 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
     floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
     const int lo = klo[t], nc = knc[t];
     const int64_t moff = (int64_t)(16 * t + r16) * npad + 8 * kq;
-    for (int c = 0; c < nc; ++c) {
+    bf16x8 bhi[kPre], blo[kPre];
+#pragma unroll
+    for (int c = 0; c < kPre; ++c) {
+      if (c < nc) {
+        bhi[c] = load8(Mhi + moff + lo + 32 * c);
+        blo[c] = load8(Mlo + moff + lo + 32 * c);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kPre; ++c) {
+      if (c < nc) {
+        const int j0 = lo + 32 * c;
+        acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), bhi[c], blo[c], acc);
+      }
+    }
+    for (int c = kPre; c < nc; ++c) {
       const int j0 = lo + 32 * c;
       acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), load8(Mhi + moff + j0),
                   load8(Mlo + moff + j0), acc);
