@@ -57,9 +57,13 @@ __global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, do
                                                     int64_t m1, int64_t m2, int n1, int n2, int K1C,
                                                     Rows r1, const int *__restrict__ nt2col,
                                                     const int *__restrict__ nt2len,
-                                                    const double *__restrict__ nt2val, int LT2) {
+                                                    const double *__restrict__ nt2val, int LT2,
+                                                    int maxrows) {
   extern __shared__ __align__(16) unsigned char smem[];
-  TQ *rows = reinterpret_cast<TQ *>(smem);
+  // LDS: this chunk's axis-1 weights and spans, then the staged rows of Q
+  double *sw = reinterpret_cast<double *>(smem);
+  int *ss = reinterpret_cast<int *>(sw + (size_t)maxrows * (P + 1));
+  TQ *rows = reinterpret_cast<TQ *>(ss + ((maxrows + 3) & ~3));
   const int BS = blockDim.x, tid = threadIdx.x;
   const int nk1c = (n1 + K1C - 1) / K1C;
   const int ck1 = blockIdx.x % nk1c, ck2 = blockIdx.x / nk1c;
@@ -84,10 +88,17 @@ __global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, do
 #pragma unroll
   for (int t = 0; t < NTR; ++t) tv[t] = (act && t < len) ? nt2val[(int64_t)k2 * LT2 + t] : 0.0;
 
+  const int nrow = (int)(r_hi - r_lo);
+  for (int e = tid; e < nrow * (P + 1); e += BS) {
+    const int rr = e / (P + 1);
+    sw[e] = r1.val[(r_lo + rr) * r1.L + (e - rr * (P + 1))];
+  }
+  for (int e = tid; e < nrow; e += BS) ss[e] = r1.span[r_lo + e];
+  __syncthreads();
   double acc[P + 1];
 #pragma unroll
   for (int q = 0; q <= P; ++q) acc[q] = 0.0;
-  int cur = r1.span[r_lo];
+  int cur = ss[0];
   double *dst = out + (i0 * n1) * (int64_t)n2 + k2;
 
   for (int64_t g = r_lo; g < r_hi; g += RI) {
@@ -104,7 +115,7 @@ __global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, do
 #pragma unroll
       for (int t = 0; t < NTR; ++t)
         if (t < len) v += tv[t] * (double)row[t];
-      const int s = r1.span[i1];
+      const int s = ss[i1 - r_lo];
       if (s != cur) {   // s == cur + 1: row cur-p is complete
         const int k1 = cur - P;
         if (act && k1 >= K1a && k1 < K1b) dst[(int64_t)k1 * n2] = acc[0];
@@ -113,7 +124,7 @@ __global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, do
         acc[P] = 0.0;
         cur = s;
       }
-      const double *w = r1.val + i1 * r1.L;
+      const double *w = sw + (i1 - r_lo) * (P + 1);
 #pragma unroll
       for (int q = 0; q <= P; ++q) acc[q] += w[q] * v;
     }
@@ -130,16 +141,26 @@ __global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, do
 // [K0a, K0b) of k0 (grid.y) and 256 consecutive columns j (grid.x).
 template <int P>
 __global__ void __launch_bounds__(256) k_proj_outer(const double *__restrict__ in, double *__restrict__ out,
-                                                    int64_t J, int n0, int K0C, Rows r0) {
+                                                    int64_t J, int n0, int K0C, Rows r0, int maxrows) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *sw = reinterpret_cast<double *>(smem);
+  int *ss = reinterpret_cast<int *>(sw + (size_t)maxrows * (P + 1));
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = j < J;
   const int K0a = blockIdx.y * K0C, K0b = min(n0, K0a + K0C);
   const int64_t r_lo = first_span_ge(max(K0a, P), r0.m, n0, P);
   const int64_t r_hi = last_span_le(min(K0b - 1 + P, n0 - 1), r0.m, n0, P) + 1;
+  const int nrow = (int)(r_hi - r_lo);
+  for (int e = threadIdx.x; e < nrow * (P + 1); e += blockDim.x) {
+    const int rr = e / (P + 1);
+    sw[e] = r0.val[(r_lo + rr) * r0.L + (e - rr * (P + 1))];
+  }
+  for (int e = threadIdx.x; e < nrow; e += blockDim.x) ss[e] = r0.span[r_lo + e];
+  __syncthreads();
   double acc[P + 1];
 #pragma unroll
   for (int q = 0; q <= P; ++q) acc[q] = 0.0;
-  int cur = r0.span[r_lo];
+  int cur = ss[0];
   const double *src = in + (act ? j : 0);
   constexpr int U = 4;
   for (int64_t g = r_lo; g < r_hi; g += U) {
@@ -150,7 +171,7 @@ __global__ void __launch_bounds__(256) k_proj_outer(const double *__restrict__ i
     for (int u = 0; u < U; ++u) {
       const int64_t i0 = g + u;
       if (i0 < r_hi) {
-        const int s = r0.span[i0];
+        const int s = ss[i0 - r_lo];
         if (s != cur) {
           const int k0 = cur - P;
           if (act && k0 >= K0a && k0 < K0b) out[(int64_t)k0 * J + j] = acc[0];
@@ -159,7 +180,7 @@ __global__ void __launch_bounds__(256) k_proj_outer(const double *__restrict__ i
           acc[P] = 0.0;
           cur = s;
         }
-        const double *w = r0.val + i0 * r0.L;
+        const double *w = sw + (i0 - r_lo) * (P + 1);
 #pragma unroll
         for (int q = 0; q <= P; ++q) acc[q] += w[q] * v[u];
       }
@@ -180,16 +201,27 @@ __global__ void __launch_bounds__(256) k_proj_outer(const double *__restrict__ i
 template <int P>
 __global__ void __launch_bounds__(256) k_dec_outer(const double *__restrict__ in, double *__restrict__ out,
                                                    int64_t J, int I0C, Rows r0) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *sw = reinterpret_cast<double *>(smem);                // [I0C][P+1]
+  int *ss = reinterpret_cast<int *>(sw + (size_t)I0C * (P + 1));  // [I0C]
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= J) return;
+  const bool act = j < J;
   const int64_t I0a = (int64_t)blockIdx.y * I0C, I0b = min(r0.m, I0a + I0C);
-  int cur = r0.span[I0a];
+  const int nrow = (int)(I0b - I0a);
+  for (int e = threadIdx.x; e < nrow * (P + 1); e += blockDim.x) {
+    const int rr = e / (P + 1);
+    sw[e] = r0.val[(I0a + rr) * r0.L + (e - rr * (P + 1))];
+  }
+  for (int e = threadIdx.x; e < nrow; e += blockDim.x) ss[e] = r0.span[I0a + e];
+  __syncthreads();
+  if (!act) return;
+  int cur = ss[0];
   double win[P + 1];
 #pragma unroll
   for (int q = 0; q <= P; ++q) win[q] = in[(int64_t)(cur - P + q) * J + j];
   double nxt = cur + 1 < r0.n ? in[(int64_t)(cur + 1) * J + j] : 0.0;
-  for (int64_t i0 = I0a; i0 < I0b; ++i0) {
-    const int s = r0.span[i0];
+  for (int rr = 0; rr < nrow; ++rr) {
+    const int s = ss[rr];
     if (s != cur) {   // s == cur + 1
 #pragma unroll
       for (int q = 0; q < P; ++q) win[q] = win[q + 1];
@@ -197,11 +229,11 @@ __global__ void __launch_bounds__(256) k_dec_outer(const double *__restrict__ in
       cur = s;
       nxt = cur + 1 < r0.n ? in[(int64_t)(cur + 1) * J + j] : 0.0;
     }
-    const double *w = r0.val + i0 * r0.L;
+    const double *w = sw + rr * (P + 1);
     double v = 0.0;
 #pragma unroll
     for (int q = 0; q <= P; ++q) v += w[q] * win[q];
-    out[i0 * J + j] = v;
+    out[(I0a + rr) * J + j] = v;
   }
 }
 
@@ -217,10 +249,21 @@ __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in
                                                    int64_t m1, int64_t m2, int n1, int n2, int I1C,
                                                    Rows r1, Rows r2) {
   extern __shared__ __align__(16) unsigned char smem[];
-  double *rows = reinterpret_cast<double *>(smem);   // [RI][n2]
+  double *rows = reinterpret_cast<double *>(smem);                // [RI][n2]
+  double *sw = rows + (size_t)RI * n2;                            // [I1C][P+1] axis-1 weights
+  int *ss = reinterpret_cast<int *>(sw + (size_t)I1C * (P + 1));  // [I1C] axis-1 spans
   const int BS = blockDim.x, tid = threadIdx.x;
   const int64_t i0 = blockIdx.y;
   const int64_t I1a = (int64_t)blockIdx.x * I1C, I1b = min(m1, I1a + I1C);
+  {
+    const int nrow = (int)(I1b - I1a);
+    for (int e = tid; e < nrow * (P + 1); e += BS) {
+      const int rr = e / (P + 1);
+      sw[e] = r1.val[(I1a + rr) * r1.L + (e - rr * (P + 1))];
+    }
+    for (int e = tid; e < nrow; e += BS) ss[e] = r1.span[I1a + e];
+  }
+  __syncthreads();
   const bool actk = tid < n2;
   const double *slab = in + i0 * (int64_t)n1 * n2 + (actk ? tid : 0);
 
@@ -236,7 +279,7 @@ __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in
     for (int q = 0; q <= P; ++q) w2[s][q] = ok ? r2.val[i2 * r2.L + q] : 0.0;
   }
 
-  int cur = r1.span[I1a];
+  int cur = ss[0];
   double win[P + 1];
 #pragma unroll
   for (int q = 0; q <= P; ++q) win[q] = actk ? slab[(int64_t)(cur - P + q) * n2] : 0.0;
@@ -247,7 +290,7 @@ __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in
     const int nr = (int)min((int64_t)RI, I1b - g);
     for (int rr = 0; rr < nr; ++rr) {
       const int64_t i1 = g + rr;
-      const int s = r1.span[i1];
+      const int s = ss[i1 - I1a];
       if (s != cur) {
 #pragma unroll
         for (int q = 0; q < P; ++q) win[q] = win[q + 1];
@@ -255,7 +298,7 @@ __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in
         cur = s;
         nxt = (actk && cur + 1 < n1) ? slab[(int64_t)(cur + 1) * n2] : 0.0;
       }
-      const double *w = r1.val + i1 * r1.L;
+      const double *w = sw + (i1 - I1a) * (P + 1);
       double v = 0.0;
 #pragma unroll
       for (int q = 0; q <= P; ++q) v += w[q] * win[q];
@@ -320,7 +363,18 @@ hipError_t project_p(Handle &h, const void *q, bool f32) {
     W = std::max(W, last_le(std::min(b - 1 + P, n2 - 1)) + 1 - first_ge(std::max(a, P)));
   }
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
-  const size_t lds = (size_t)kProjRI * W * esz;
+  // most axis-1 rows one k1 chunk touches (same rule as the kernel)
+  auto rows_of_chunk = [&](int64_t m, int n, int a, int b) -> int64_t {
+    const int s0 = std::max(a, P), s1 = std::min(b - 1 + P, n - 1);
+    const int64_t lo = s0 <= P ? 0 : ((int64_t)(s0 - P) * (m - 1) + (n - P) - 1) / (n - P);
+    const int64_t hi = s1 >= n - 1 ? m - 1 : ((int64_t)(s1 - P + 1) * (m - 1) + (n - P) - 1) / (n - P) - 1;
+    return hi + 1 - lo;
+  };
+  int maxrows1 = 0;
+  for (int c = 0; c < nk1c; ++c)
+    maxrows1 = (int)std::max<int64_t>(maxrows1, rows_of_chunk(m1, n1, c * K1C, std::min(n1, c * K1C + K1C)));
+  const size_t lds = (size_t)maxrows1 * (P + 1) * sizeof(double) + ((maxrows1 + 3) & ~3) * sizeof(int) +
+                     (size_t)kProjRI * W * esz;
   if (lds > 64 * 1024) return hipErrorNotSupported;
   const bool outer = X0.active;
   if (outer && h.s1n < m0 * n1 * (int64_t)n2) return hipErrorNotSupported;
@@ -331,7 +385,7 @@ hipError_t project_p(Handle &h, const void *q, bool f32) {
 #define MFA_PI(TQ, NTR)                                                                            \
   k_proj_inner<TQ, P, kProjRI, NTR><<<g1, BS, lds, h.stream>>>(                                     \
       reinterpret_cast<const TQ *>(q), T, m1, m2, n1, n2, K1C, r1, X2.NT.col, X2.NT.len, X2.NT.val, \
-      LT2)
+      LT2, maxrows1)
   if (LT2 <= 12) {
     if (f32) MFA_PI(float, 12);
     else MFA_PI(double, 12);
@@ -349,8 +403,13 @@ hipError_t project_p(Handle &h, const void *q, bool f32) {
   if (e != hipSuccess || !outer) return e;
   const int64_t J = (int64_t)n1 * n2;
   const int K0C = pick_chunk((int64_t)nblk(J, 256), n0, 8);
+  int maxrows0 = 0;
+  for (int c = 0; c < (int)nblk(n0, K0C); ++c)
+    maxrows0 = (int)std::max<int64_t>(maxrows0, rows_of_chunk(m0, n0, c * K0C, std::min(n0, c * K0C + K0C)));
+  const size_t lds0 = (size_t)maxrows0 * ((P + 1) * sizeof(double) + sizeof(int));
+  if (lds0 > 64 * 1024) return hipErrorInvalidValue;
   const dim3 g0(nblk(J, 256), nblk(n0, K0C));
-  k_proj_outer<P><<<g0, 256, 0, h.stream>>>(T, h.c, J, n0, K0C, rows_of(X0, 0));
+  k_proj_outer<P><<<g0, 256, lds0, h.stream>>>(T, h.c, J, n0, K0C, rows_of(X0, 0), maxrows0);
   return hipGetLastError();
 }
 
@@ -369,7 +428,8 @@ hipError_t decode_p(Handle &h, void *out, bool f32, const int r[3]) {
     const int64_t J = (int64_t)n1 * n2;
     const int I0C = 64;
     const dim3 g0(nblk(J, 256), nblk(m0, I0C));
-    k_dec_outer<P><<<g0, 256, 0, h.stream>>>(h.P, h.s1, J, I0C, rows_of(X0, r[0]));
+    const size_t lds0 = (size_t)I0C * ((P + 1) * sizeof(double) + sizeof(int));
+    k_dec_outer<P><<<g0, 256, lds0, h.stream>>>(h.P, h.s1, J, I0C, rows_of(X0, r[0]));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     src = h.s1;
@@ -377,7 +437,7 @@ hipError_t decode_p(Handle &h, void *out, bool f32, const int r[3]) {
   int I1C = 64;
   while (I1C > 8 && m0 * (int64_t)nblk(m1, I1C) < 2048) I1C /= 2;
   const dim3 g1(nblk(m1, I1C), (unsigned)m0);
-  const size_t lds = (size_t)kDecRI * n2 * sizeof(double);
+  const size_t lds = (size_t)kDecRI * n2 * sizeof(double) + (size_t)I1C * ((P + 1) * sizeof(double) + sizeof(int));
   const Rows r1 = rows_of(X1, r[1]), r2 = rows_of(X2, r[2]);
 #define MFA_DI(TO, IS_)                                                                            \
   k_dec_inner<TO, P, kDecRI, IS_><<<g1, BS, lds, h.stream>>>(src, reinterpret_cast<TO *>(out), m1, \

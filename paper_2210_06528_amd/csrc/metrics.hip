@@ -27,6 +27,8 @@ __device__ __forceinline__ double tod(double v) { return v; }
 __device__ __forceinline__ double tod(float v) { return (double)v; }
 __device__ __forceinline__ double tod(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
 
+constexpr int kStageM = 8;   // staging loads per thread issued before the first wait
+
 struct DTab {
   const int *len;
   const int *col;
@@ -70,16 +72,33 @@ __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ 
   const int ib0 = (lb % nbg) * jb;
   const int nib = min(jb, Ob.m - ib0);
   const int nc = has_c ? Oc.n : 1;
+  // the group's Om_b rows (jb x Ob.L) and their column starts and lengths
+  double *VB = V + jb * nc;
+  int *CB = reinterpret_cast<int *>(VB + jb * Ob.L);
+  for (int e = threadIdx.x; e < jb * Ob.L; e += blockDim.x) {
+    const int i = e / Ob.L;
+    VB[e] = i < nib ? Ob.val[(int64_t)(ib0 + i) * Ob.L + (e - i * Ob.L)] : 0.0;
+  }
+  for (int i = threadIdx.x; i < jb; i += blockDim.x) {
+    CB[2 * i] = i < nib ? Ob.col[(int64_t)(ib0 + i) * Ob.L] : 0;
+    CB[2 * i + 1] = i < nib ? Ob.len[ib0 + i] : 0;
+  }
+  __syncthreads();
   for (int e = threadIdx.x; e < jb * nc; e += blockDim.x) {
     const int i = e / nc, kc = e - i * nc;
     double s = 0.0;
     if (i < nib) {
-      const int ib = ib0 + i;
-      const int lb = Ob.len[ib];
-      const int cb0 = Ob.col[(int64_t)ib * Ob.L];
-      const double *vb = Ob.val + (int64_t)ib * Ob.L;
+      const int cb0 = CB[2 * i], lb = CB[2 * i + 1];
+      const double *vb = VB + i * Ob.L;
       const double *u = U + row * sr + (int64_t)cb0 * sb + (int64_t)kc * sc;
-      for (int t = 0; t < lb; ++t) s += vb[t] * u[(int64_t)t * sb];
+      // eight strided loads in flight per step
+      for (int t0 = 0; t0 < lb; t0 += 8) {
+        double x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = t0 + q < lb ? u[(int64_t)(t0 + q) * sb] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += vb[min(t0 + q, Ob.L - 1)] * x[q];
+      }
     }
     V[e] = s;
   }
@@ -261,7 +280,19 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
   const int64_t l0 = (int64_t)blockIdx.x * LPB;
   const int nl = (int)min((int64_t)LPB, nlines - l0);
   const TG *src = g + l0 * n2;
-  for (int e = threadIdx.x; e < nl * n2; e += blockDim.x) sg[e] = tod(src[e]);
+  for (int e0 = 0; e0 < nl * n2; e0 += blockDim.x * kStageM) {
+    double v[kStageM];
+#pragma unroll
+    for (int u = 0; u < kStageM; ++u) {
+      const int e = e0 + threadIdx.x + blockDim.x * u;
+      v[u] = e < nl * n2 ? tod(src[e]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageM; ++u) {
+      const int e = e0 + threadIdx.x + blockDim.x * u;
+      if (e < nl * n2) sg[e] = v[u];
+    }
+  }
   __syncthreads();
   for (int it = threadIdx.x; it < nl * nif; it += blockDim.x) {
     const int li = it / nif, b = it - li * nif;
@@ -328,10 +359,24 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
 
   for (int k0 = k0a; k0 < k0b + H; ++k0) {
     __syncthreads();
-    for (int e = threadIdx.x; e < (TY + H) * (TX + H); e += 256) {
-      const int r = e / (TX + H), c = e - r * (TX + H);
-      const int k1 = k1a + r, kk2 = k2a + c;
-      tile[r][c] = (k0 < n0 && k1 < n1 && kk2 < n2) ? P[((int64_t)k0 * n1 + k1) * n2 + kk2] : 0.0;
+    {
+      constexpr int NT = ((TY + H) * (TX + H) + 255) / 256;
+      double v[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int r = e / (TX + H), c = e - r * (TX + H);
+        const int k1 = k1a + r, kk2 = k2a + c;
+        v[u] = (e < (TY + H) * (TX + H) && k0 < n0 && k1 < n1 && kk2 < n2)
+                   ? P[((int64_t)k0 * n1 + k1) * n2 + kk2]
+                   : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int r = e / (TX + H), c = e - r * (TX + H);
+        if (e < (TY + H) * (TX + H)) tile[r][c] = v[u];
+      }
     }
     __syncthreads();
     const bool own = k0 < k0b;
@@ -494,7 +539,7 @@ hipError_t launch_jump_expand(Handle &h, int a, const double *U) {
   }
   const int jb = nc <= 384 ? 16 : (nc <= 768 ? 8 : (nc <= 1536 ? 4 : 1));
   const unsigned grid = (unsigned)((int64_t)R * ((Ob.m + jb - 1) / jb));
-  const size_t lds = sizeof(double) * jb * nc;
+  const size_t lds = sizeof(double) * jb * (nc + Ob.L) + sizeof(int) * 2 * jb;
   if (lds > 64 * 1024) return hipErrorInvalidValue;
 #define MFA_JE(JB)                                                                                  \
   k_jump_expand<JB><<<grid, 256, lds, h.stream>>>(U, R, st[a], st[oth[0]], sc, Ob, Oc, has_c, h.p, \
