@@ -380,6 +380,28 @@ mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes) {
   return MFA_OK;
 }
 
+// Two auxiliary streams (default priority) and fork/join events per host
+// thread and device, created on first use and kept for the life of the
+// process: concurrent handles on different threads never share them.
+struct AuxStreams {
+  hipStream_t s[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+};
+
+static AuxStreams *aux_streams(int device) {
+  static thread_local AuxStreams per_dev[16];
+  if (device < 0 || device >= 16) return nullptr;
+  AuxStreams &a = per_dev[device];
+  if (!a.fork) {
+    for (int i = 0; i < 2; ++i) {
+      if (hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking) != hipSuccess) return nullptr;
+      if (hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming) != hipSuccess) return nullptr;
+    }
+    if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+  }
+  return &a;
+}
+
 mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, void *hip_stream,
                       mfa_handle **out) {
   if (!prob || !out) return fail(MFA_EINVAL, "null pointer");
@@ -415,11 +437,31 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
   if ((e = launch_zero_slots(h.stream, (unsigned long long *)h.flag, 2)) != hipSuccess)
     return bail(e, "zero flag");
   if ((e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0)) != hipSuccess) return bail(e, "fill P");
+  if ((e = upload_plan(&h)) != hipSuccess) return bail(e, "upload plan");
+  // The per-axis setup chains (basis, Gram, batched Cholesky, inverses,
+  // operator tables) are independent and each kernel runs only a few
+  // workgroups: the first active axis runs on the caller's stream, the others
+  // on two auxiliary streams forked from it and joined back.
+  AuxStreams *aux = aux_streams(h.device);
+  if (!aux) return bail(hipErrorOutOfMemory, "auxiliary streams");
+  if ((e = hipEventRecord(aux->fork, h.stream)) != hipSuccess) return bail(e, "fork");
+  int used = 0;
   for (int a = 0; a < 3; ++a) {
-    if (h.ax[a].active && (e = setup_axis(&h, a)) != hipSuccess) return bail(e, "setup");
-    if ((e = setup_acoef(&h, a)) != hipSuccess) return bail(e, "setup");
-    if (h.ax[a].active && h.precision == MFA_PREC_MIXED_BF16 && (e = setup_mfma(&h, a)) != hipSuccess)
+    if (!h.ax[a].active) continue;
+    hipStream_t st = h.stream;
+    if (used > 0) {
+      st = aux->s[used - 1];
+      if ((e = hipStreamWaitEvent(st, aux->fork, 0)) != hipSuccess) return bail(e, "fork");
+    }
+    if ((e = setup_axis(&h, a, st)) != hipSuccess) return bail(e, "setup");
+    if ((e = setup_acoef(&h, a, st)) != hipSuccess) return bail(e, "setup");
+    if (h.precision == MFA_PREC_MIXED_BF16 && (e = setup_mfma(&h, a, st)) != hipSuccess)
       return bail(e, "setup");
+    if (used > 0) {
+      if ((e = hipEventRecord(aux->join[used - 1], st)) != hipSuccess) return bail(e, "join");
+      if ((e = hipStreamWaitEvent(h.stream, aux->join[used - 1], 0)) != hipSuccess) return bail(e, "join");
+    }
+    ++used;
   }
   int flag = 0;
   if ((e = hipMemcpyAsync(&flag, h.flag, sizeof(int), hipMemcpyDeviceToHost, h.stream)) != hipSuccess)

@@ -112,6 +112,7 @@ struct Handle {
   unsigned long long *slots = nullptr;   // reductions, see kSlot*
   int *flag = nullptr;                   // setup error flag
   double *hist = nullptr;                // max |correction| of recent sweeps (ring of kHist)
+  size_t upload_bytes = 0;               // host-planned tables: workspace bytes [0, upload_bytes)
   bool have_rhs = false;
   const void *q = nullptr;  // data of the last encode / step (read every sweep in DATABOX mode)
   int q_dtype = 0;
@@ -179,9 +180,12 @@ hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n, d
 hipError_t launch_maxabs(hipStream_t st, const double *x, int64_t n, unsigned long long *slot);
 
 // setup kernels (one axis at a time)
-hipError_t setup_axis(Handle *h, int a);
+// one copy of every host-planned table (block bounds, owners, n_s, interface
+// parameters, identity stencil rows of inactive axes) into the workspace
+hipError_t upload_plan(Handle *h);
+hipError_t setup_axis(Handle *h, int a, hipStream_t st);
 // stencil rows of A for the residual kernel (identity row for inactive axes)
-hipError_t setup_acoef(Handle *h, int a);
+hipError_t setup_acoef(Handle *h, int a, hipStream_t st);
 
 // sweep kernels
 template <typename TG>
@@ -206,7 +210,7 @@ bool grid_pass_ok(const Handle &h);
 hipError_t launch_project_grid(Handle &h, const void *q, bool f32);
 hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3]);
 bool mfma_fits(int npad);
-hipError_t setup_mfma(Handle *h, int a);
+hipError_t setup_mfma(Handle *h, int a, hipStream_t st);
 hipError_t launch_mfma_correct(Handle &h, int axis, const float *in, float *out, bool add);
 
 // LDS bytes the banded-solve kernel needs for segments of length fmax

@@ -294,13 +294,13 @@ static int contig_lines(int npad) {
 
 bool mfma_fits(int npad) { return mfma_lds(npad) <= 64 * 1024 && contig_lines(npad) > 0; }
 
-hipError_t setup_mfma(Handle *h, int ia) {
+hipError_t setup_mfma(Handle *h, int ia, hipStream_t st) {
   Axis &X = h->ax[ia];
   const int nrows = (X.n + 15) / 16 * 16;
   __hip_bfloat16 *Mhi = reinterpret_cast<__hip_bfloat16 *>(X.d_Mb);
   __hip_bfloat16 *Mlo = Mhi + (int64_t)nrows * X.npad;
-  k_tab_Mbf16<<<nrows, 128, 0, h->stream>>>(X.n, nrows, X.npad, X.M, Mhi, Mlo);
-  k_tab_ktiles<<<nblk((X.n + 15) / 16, 64), 64, 0, h->stream>>>(X.n, X.M, X.d_klo, X.d_knc);
+  k_tab_Mbf16<<<nrows, 128, 0, st>>>(X.n, nrows, X.npad, X.M, Mhi, Mlo);
+  k_tab_ktiles<<<nblk((X.n + 15) / 16, 64), 64, 0, st>>>(X.n, X.M, X.d_klo, X.d_knc);
   return hipGetLastError();
 }
 

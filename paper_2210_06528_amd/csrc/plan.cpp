@@ -235,12 +235,32 @@ size_t layout_workspace(Handle *h, char *base) {
   Bump bp(base);
   const int p = h->p;
   const bool mixed = h->precision != MFA_PREC_FP64;
+  // host-planned tables of every axis first, in one contiguous region that
+  // setup uploads with a single copy
   for (int ia = 0; ia < 3; ++ia) {
     Axis &X = h->ax[ia];
-    X.d_acoef = bp.take<double>((int64_t)(2 * p + 1) * X.n);
-    if (!X.active) continue;
+    if (!X.active) {
+      X.d_acoef = bp.take<double>((int64_t)(2 * p + 1) * X.n);
+      continue;
+    }
+    const int n = X.n;
+    const int nif = X.B - 1;
     X.d_choff = bp.take<int>(X.B);
     X.d_foff = bp.take<int>(X.B);
+    X.d_blk = bp.take<int>(8LL * X.B);
+    X.d_blo = bp.take<int>(n);
+    X.d_bhi = bp.take<int>(n);
+    X.d_owner = bp.take<int>(n);
+    X.d_ns = bp.take<int>(n);
+    X.d_pown = bp.take<int>(X.m);
+    X.d_ustar = bp.take<double>(nif);
+    X.d_span_if = bp.take<int>(nif);
+  }
+  h->upload_bytes = bp.off;
+  for (int ia = 0; ia < 3; ++ia) {
+    Axis &X = h->ax[ia];
+    if (!X.active) continue;
+    X.d_acoef = bp.take<double>((int64_t)(2 * p + 1) * X.n);
     X.d_rdiag = bp.take<double>(X.SF);
     const int n = X.n;
     const int64_t m = X.m;
@@ -250,14 +270,6 @@ size_t layout_workspace(Handle *h, char *base) {
     X.d_gram = bp.take<double>((int64_t)(p + 1) * n);
     X.d_chol = bp.take<double>(X.chol_total);
     X.d_inv = bp.take<double>(X.inv_total);
-    X.d_blk = bp.take<int>(8LL * X.B);
-    X.d_blo = bp.take<int>(n);
-    X.d_bhi = bp.take<int>(n);
-    X.d_owner = bp.take<int>(n);
-    X.d_ns = bp.take<int>(n);
-    X.d_pown = bp.take<int>(m);
-    X.d_ustar = bp.take<double>(nif);
-    X.d_span_if = bp.take<int>(nif);
     X.d_dbas_if = bp.take<double>((int64_t)nif * p * (p + 1));
     X.d_gidJ = bp.take<int>((int64_t)nif * p);
     X.d_gidD = bp.take<int>(X.ND);

@@ -3,6 +3,9 @@
 #include <algorithm>
 #include <vector>
 
+#include <cstring>
+#include <vector>
+
 #include "mfa_internal.hpp"
 
 namespace mfa {
@@ -524,18 +527,10 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 
 }  // namespace
 
-hipError_t setup_acoef(Handle *h, int ia) {
+hipError_t setup_acoef(Handle *h, int ia, hipStream_t st) {
   Axis &X = h->ax[ia];
-  const int p = h->p;
-  if (!X.active) {
-    std::vector<double> id(2 * p + 1, 0.0);
-    id[p] = 1.0;
-    hipError_t e = hipMemcpyAsync(X.d_acoef, id.data(), sizeof(double) * id.size(),
-                                  hipMemcpyHostToDevice, h->stream);
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(h->stream);
-  }
-  k_acoef<<<nblk(X.n, 128), 128, 0, h->stream>>>(X.n, p, X.d_gram, X.d_acoef);
+  if (!X.active) return hipSuccess;   // identity row, uploaded with the plan
+  k_acoef<<<nblk(X.n, 128), 128, 0, st>>>(X.n, h->p, X.d_gram, X.d_acoef);
   return hipGetLastError();
 }
 
@@ -545,39 +540,52 @@ hipError_t setup_acoef(Handle *h, int ia) {
     if (e_ != hipSuccess) return e_;     \
   } while (0)
 
-hipError_t setup_axis(Handle *h, int ia) {
+hipError_t upload_plan(Handle *h) {
+  std::vector<char> img(h->upload_bytes, 0);
+  auto put = [&](void *dev, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(img.data() + ((char *)dev - h->ws), src, bytes);
+  };
+  const int p = h->p;
+  for (int ia = 0; ia < 3; ++ia) {
+    Axis &X = h->ax[ia];
+    if (!X.active) {
+      std::vector<double> id((size_t)(2 * p + 1) * X.n, 0.0);
+      for (int k = 0; k < X.n; ++k) id[(size_t)k * (2 * p + 1) + p] = 1.0;
+      put(X.d_acoef, id.data(), sizeof(double) * id.size());
+      continue;
+    }
+    const int n = X.n, B = X.B, nif = B - 1;
+    std::vector<int> blk(8 * B), choff(B), foff(B);
+    for (int b = 0; b < B; ++b) {
+      const Block &Bk = X.blk[b];
+      int *e = &blk[8 * b];
+      e[0] = Bk.c0; e[1] = Bk.c1; e[2] = Bk.F0; e[3] = Bk.F1;
+      e[4] = (int)Bk.own0; e[5] = (int)Bk.own1; e[6] = (int)Bk.D0; e[7] = (int)Bk.D1;
+      choff[b] = (int)X.chol_off[b];
+      foff[b] = (int)X.foff[b];
+    }
+    put(X.d_blk, blk.data(), sizeof(int) * blk.size());
+    put(X.d_blo, X.blo.data(), sizeof(int) * n);
+    put(X.d_bhi, X.bhi.data(), sizeof(int) * n);
+    put(X.d_owner, X.owner.data(), sizeof(int) * n);
+    put(X.d_ns, X.ns.data(), sizeof(int) * n);
+    put(X.d_pown, X.pown.data(), sizeof(int) * X.m);
+    put(X.d_choff, choff.data(), sizeof(int) * B);
+    put(X.d_foff, foff.data(), sizeof(int) * B);
+    if (nif > 0) {
+      put(X.d_ustar, X.ustar.data(), sizeof(double) * nif);
+      put(X.d_span_if, X.span_if.data(), sizeof(int) * nif);
+    }
+  }
+  MFA_TRY(hipMemcpyAsync(h->ws, img.data(), img.size(), hipMemcpyHostToDevice, h->stream));
+  // the image is a local: wait for the copy before it goes out of scope
+  return hipStreamSynchronize(h->stream);
+}
+
+hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
   Axis &X = h->ax[ia];
-  hipStream_t st = h->stream;
   const int p = h->p, n = X.n, B = X.B, nif = B - 1;
   const int64_t m = X.m;
-  // host-planned integer tables
-  std::vector<int> blk(8 * B);
-  for (int b = 0; b < B; ++b) {
-    const Block &Bk = X.blk[b];
-    int *e = &blk[8 * b];
-    e[0] = Bk.c0; e[1] = Bk.c1; e[2] = Bk.F0; e[3] = Bk.F1;
-    e[4] = (int)Bk.own0; e[5] = (int)Bk.own1; e[6] = (int)Bk.D0; e[7] = (int)Bk.D1;
-  }
-  MFA_TRY(hipMemcpyAsync(X.d_blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice, st));
-  MFA_TRY(hipMemcpyAsync(X.d_blo, X.blo.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-  MFA_TRY(hipMemcpyAsync(X.d_bhi, X.bhi.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-  MFA_TRY(hipMemcpyAsync(X.d_owner, X.owner.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-  MFA_TRY(hipMemcpyAsync(X.d_ns, X.ns.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-  MFA_TRY(hipMemcpyAsync(X.d_pown, X.pown.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
-  std::vector<int> choff(B), foff(B);
-  for (int b = 0; b < B; ++b) {
-    choff[b] = (int)X.chol_off[b];
-    foff[b] = (int)X.foff[b];
-  }
-  MFA_TRY(hipMemcpyAsync(X.d_choff, choff.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
-  MFA_TRY(hipMemcpyAsync(X.d_foff, foff.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
-  if (nif > 0) {
-    MFA_TRY(hipMemcpyAsync(X.d_ustar, X.ustar.data(), sizeof(double) * nif, hipMemcpyHostToDevice, st));
-    MFA_TRY(hipMemcpyAsync(X.d_span_if, X.span_if.data(), sizeof(int) * nif, hipMemcpyHostToDevice, st));
-  }
-  // pageable host copies above complete before the call returns; the vectors
-  // may go out of scope afterwards.
-  MFA_TRY(hipStreamSynchronize(st));
 
   // basis values and derivative tables at the data points
   for (int r = 0; r <= p; ++r) {
