@@ -182,21 +182,24 @@ typedef enum {
 mfa_status mfa_inspect(mfa_handle *h, int32_t table, int32_t axis, int32_t block,
                        double *host_out, size_t count, size_t *needed);
 
-/* Per-kernel event timing (measurement support).  With enable != 0 the
- * library records a HIP event pair on its stream around every launch of each
- * kernel class below; mfa_kernel_time synchronises the stream and returns the
- * summed duration in milliseconds and the number of launches of one class
- * since timing was enabled (or since the class was last read, which resets
- * it).  Disabled by default; enabling costs two event records per launch.  */
+/* Per-kernel event timing (measurement support).  class_mask selects the
+ * kernel classes below (bit c for class c; MFA_K_ALL for every class, 0 to
+ * disable): the library records a HIP event pair on its stream around every
+ * launch of a selected class; mfa_kernel_time synchronises the stream and
+ * returns the summed duration in milliseconds and the number of launches of
+ * one class since timing was set (or since the class was last read, which
+ * resets it).  Disabled by default; every timed launch costs two event
+ * records on the stream.  */
 typedef enum {
   MFA_K_PROJECT = 0,   /* c = N^T Q passes                                 */
   MFA_K_RESID = 1,     /* residual stencil g = c - N^T N P                 */
   MFA_K_CORRECT = 2,   /* Schwarz correction passes (banded solves)        */
   MFA_K_METRICS = 3,   /* interface jumps and derivative scales            */
   MFA_K_DECODE = 4,    /* decode passes                                    */
-  MFA_K_COUNT = 5
+  MFA_K_COUNT = 5,
+  MFA_K_ALL = (1 << 5) - 1
 } mfa_kernel_class;
-mfa_status mfa_set_timing(mfa_handle *h, int32_t enable);
+mfa_status mfa_set_timing(mfa_handle *h, int32_t class_mask);
 mfa_status mfa_kernel_time(mfa_handle *h, int32_t kclass, double *total_ms, int64_t *launches);
 
 /* Release the handle (not the caller-owned workspace).  NULL is ignored.   */

@@ -258,8 +258,12 @@ class Encoder:
         ctrl = ctrl.contiguous()
         check(self.lib.mfa_set_ctrl(self.handle, c_void_p(ctrl.data_ptr()), 1))
 
-    def set_timing(self, enable=True):
-        check(self.lib.mfa_set_timing(self.handle, 1 if enable else 0))
+    def set_timing(self, enable=True, classes=None):
+        """Event-time the kernel classes named in `classes` (all when None)."""
+        mask = 0
+        if enable:
+            mask = 31 if classes is None else sum(1 << KERNEL_CLASSES[c] for c in classes)
+        check(self.lib.mfa_set_timing(self.handle, mask))
 
     def kernel_time(self, kclass):
         """(total ms, launches) of one kernel class since the last read."""

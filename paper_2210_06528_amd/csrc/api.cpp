@@ -39,14 +39,14 @@ static hipEvent_t take_event(Handle &h) {
 }
 
 TimeScope::TimeScope(Handle &hh, int c) : h(hh), cls(c) {
-  if (!h.timing) return;
+  if (!(h.timing & (1 << c))) return;
   e0 = take_event(h);
   e1 = take_event(h);
   if (e0) hipEventRecord(e0, h.stream);
 }
 
 TimeScope::~TimeScope() {
-  if (!h.timing || !e0 || !e1) return;
+  if (!e0 || !e1) return;
   hipEventRecord(e1, h.stream);
   h.ev_used[cls].push_back({e0, e1});
 }
@@ -478,7 +478,7 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
 
 void mfa_destroy(mfa_handle *h) { delete h; }
 
-mfa_status mfa_set_timing(mfa_handle *H, int32_t enable) {
+mfa_status mfa_set_timing(mfa_handle *H, int32_t class_mask) {
   if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
   Handle &h = H->h;
   HIP_CHECK(hipStreamSynchronize(h.stream), "set_timing");
@@ -489,7 +489,7 @@ mfa_status mfa_set_timing(mfa_handle *H, int32_t enable) {
     }
     v.clear();
   }
-  h.timing = enable != 0;
+  h.timing = class_mask & MFA_K_ALL;
   return MFA_OK;
 }
 

@@ -120,7 +120,7 @@ struct Handle {
   bool warm = false;        // P was set by mfa_set_ctrl: the next encode starts there
   int sweep = 0;
   // per-class event timing
-  bool timing = false;
+  int timing = 0;                        // mask of timed kernel classes
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[MFA_K_COUNT];
   std::vector<hipEvent_t> ev_pool;
   ~Handle();
