@@ -157,6 +157,20 @@ mfa_status mfa_schwarz_step(mfa_handle *h, const void *q_dev, mfa_dtype q_dtype,
 mfa_status mfa_decode(mfa_handle *h, void *out_dev, mfa_dtype out_dtype,
                       const int32_t *deriv);
 
+/* Decode at arbitrary parameter points (Section 2.1: the tensor-product
+ * B-spline of eq. nurbs-basis with W = 1, evaluated away from the grid, the
+ * analysis use of the fitted model).  For point i with parameters
+ * u_dev[i*dim + a] (row-major, npoints x dim, device memory, float64):
+ *   out[i] = sum_k P[k] prod_a d^{r_a}/du_a^{r_a} N_{k_a,p}(u_a)
+ * with r_a = deriv[a] (0..p; nullable = values), spans taken right-continuous
+ * as for the data grid (u = t_j belongs to span j, u = 1 to span n-1).
+ * Parameters outside [0, 1] are clamped to the nearest end.  out_dev holds
+ * npoints values of out_dtype.  Asynchronous on the handle's stream; reads
+ * the current control points.  EINVAL for null pointers, npoints < 0 or a
+ * derivative order outside 0..p.  */
+mfa_status mfa_decode_points(mfa_handle *h, const double *u_dev, int64_t npoints, void *out_dev,
+                             mfa_dtype out_dtype, const int32_t *deriv);
+
 /* Copy the control points (float64, nctrl[0] x ...) out of / into the handle
  * ("write MFA to disk" of Algorithm 1; set_ctrl is a warm start or refit).
  * on_device != 0: the pointer is a device pointer; otherwise host memory

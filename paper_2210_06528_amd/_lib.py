@@ -28,6 +28,7 @@ STATUS_NAMES = {0: "MFA_OK", -1: "MFA_EINVAL", -2: "MFA_ENOMEM", -3: "MFA_EDEVIC
 # every entry point the header declares
 EXPORTS = ["mfa_workspace_size", "mfa_create", "mfa_encode", "mfa_schwarz_step", "mfa_decode",
            "mfa_get_ctrl", "mfa_set_ctrl", "mfa_inspect", "mfa_set_timing", "mfa_kernel_time",
+           "mfa_decode_points",
            "mfa_destroy", "mfa_last_error"]
 KERNEL_CLASSES = {"project": 0, "resid": 1, "correct": 2, "metrics": 3, "decode": 4}
 
@@ -93,6 +94,9 @@ def load(path=LIB_PATH):
     lib.mfa_schwarz_step.restype = c_int32
     lib.mfa_decode.argtypes = [c_void_p, c_void_p, c_int32, POINTER(c_int32)]
     lib.mfa_decode.restype = c_int32
+    lib.mfa_decode_points.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_int32,
+                                      POINTER(c_int32)]
+    lib.mfa_decode_points.restype = c_int32
     lib.mfa_get_ctrl.argtypes = [c_void_p, c_void_p, c_int32]
     lib.mfa_get_ctrl.restype = c_int32
     lib.mfa_set_ctrl.argtypes = [c_void_p, c_void_p, c_int32]
@@ -244,6 +248,26 @@ class Encoder:
             arr = (c_int32 * 3)(*([int(r) for r in deriv] + [0] * (3 - len(deriv))))
             dptr = ctypes.cast(arr, POINTER(c_int32))
         check(self.lib.mfa_decode(self.handle, c_void_p(out.data_ptr()), self._dt(out), dptr))
+        return out
+
+    def decode_points(self, u, dtype=None, deriv=None, out=None):
+        """Spline (or a mixed partial derivative) at parameter points u
+        (npoints x dim float64 device tensor, values in [0, 1])."""
+        torch = self.torch
+        if u.dtype != torch.float64 or not u.is_contiguous() or u.dim() != 2 or \
+                u.shape[1] != len(self.npts) or u.device != self.device:
+            raise ValueError("u must be a contiguous (npoints, dim) float64 tensor on the device")
+        npts = u.shape[0]
+        if out is None:
+            out = torch.empty(npts, dtype=dtype or torch.float64, device=self.device)
+        if tuple(out.shape) != (npts,) or not out.is_contiguous():
+            raise ValueError("bad output tensor")
+        dt = MFA_F32 if out.dtype == torch.float32 else MFA_F64
+        dv = None
+        if deriv is not None:
+            dv = (c_int32 * len(deriv))(*[int(x) for x in deriv])
+        check(self.lib.mfa_decode_points(self.handle, c_void_p(u.data_ptr()), npts,
+                                         c_void_p(out.data_ptr()), dt, dv))
         return out
 
     def get_ctrl(self):

@@ -674,6 +674,26 @@ mfa_status mfa_decode(mfa_handle *H, void *out_dev, mfa_dtype out_dtype, const i
   return MFA_OK;
 }
 
+mfa_status mfa_decode_points(mfa_handle *H, const double *u_dev, int64_t npoints, void *out_dev,
+                             mfa_dtype out_dtype, const int32_t *deriv) {
+  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  if (npoints < 0) return fail(MFA_EINVAL, "negative point count");
+  if (npoints > 0 && (!u_dev || !out_dev)) return fail(MFA_EINVAL, "null pointer");
+  if (out_dtype != MFA_F32 && out_dtype != MFA_F64) return fail(MFA_EINVAL, "bad dtype");
+  Handle &h = H->h;
+  hipSetDevice(h.device);
+  int r[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a) {
+    if (!h.ax[a].active || !deriv) continue;
+    r[a] = deriv[a - (3 - h.dim)];
+    if (r[a] < 0 || r[a] > h.p) return fail(MFA_EINVAL, "derivative order out of range");
+  }
+  TimeScope ts(h, MFA_K_DECODE);
+  hipError_t e = launch_decode_points(h, u_dev, npoints, out_dev, out_dtype == MFA_F32, r);
+  if (e != hipSuccess) return hip_fail(e, "decode points");
+  return MFA_OK;
+}
+
 mfa_status mfa_get_ctrl(mfa_handle *H, double *ctrl, int32_t on_device) {
   if (!valid_handle(H) || !ctrl) return fail(MFA_EINVAL, "null pointer");
   Handle &h = H->h;

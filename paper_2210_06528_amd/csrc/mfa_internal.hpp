@@ -183,6 +183,9 @@ hipError_t launch_maxabs(hipStream_t st, const double *x, int64_t n, unsigned lo
 // one copy of every host-planned table (block bounds, owners, n_s, interface
 // parameters, identity stencil rows of inactive axes) into the workspace
 hipError_t upload_plan(Handle *h);
+// decode at arbitrary parameter points (npts x dim, float64, device)
+hipError_t launch_decode_points(Handle &h, const double *u, int64_t npts, void *out, bool f32,
+                                const int r[3]);
 hipError_t setup_axis(Handle *h, int a, hipStream_t st);
 // stencil rows of A for the residual kernel (identity row for inactive axes)
 hipError_t setup_acoef(Handle *h, int a, hipStream_t st);

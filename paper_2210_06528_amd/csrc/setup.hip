@@ -523,6 +523,52 @@ __global__ void k_acoef(int n, int p, const double *band, double *acoef) {
   }
 }
 
+// Decode at arbitrary points: one thread per point, the p+1 basis values
+// (or derivatives) per active axis from the Cox-de Boor recurrence, then the
+// (p+1)^d tensor sum over the control points under the point's spans.
+struct PtAxes {
+  int n[3], active[3], ua[3], r[3];
+};
+
+template <typename TO>
+__global__ void k_decode_points(const double *__restrict__ u, int64_t npts, int dim, int p, PtAxes ax,
+                                const double *__restrict__ P, TO *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npts) return;
+  double val[3][kMaxP + 1];
+  int s0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!ax.active[a]) {
+      s0[a] = 0;
+      val[a][0] = 1.0;
+      continue;
+    }
+    const int n = ax.n[a];
+    double x = u[i * dim + ax.ua[a]];
+    x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+    int s = p + (int)floor(x * (double)(n - p));
+    s = s < p ? p : (s > n - 1 ? n - 1 : s);
+    // largest s in [p, n-1] with t_s <= x (right-continuous, as on the grid)
+    while (s > p && knot(s, n, p) > x) --s;
+    while (s < n - 1 && knot(s + 1, n, p) <= x) ++s;
+    basis_deriv(x, s, n, p, ax.r[a], val[a]);
+    s0[a] = s - p;
+  }
+  const int w0 = ax.active[0] ? p + 1 : 1, w1 = ax.active[1] ? p + 1 : 1, w2 = ax.active[2] ? p + 1 : 1;
+  const int64_t n1 = ax.n[1], n2 = ax.n[2];
+  double acc = 0.0;
+  for (int q0 = 0; q0 < w0; ++q0)
+    for (int q1 = 0; q1 < w1; ++q1) {
+      const double v01 = val[0][q0] * val[1][q1];
+      const double *row = P + ((int64_t)(s0[0] + q0) * n1 + (s0[1] + q1)) * n2 + s0[2];
+      double t = 0.0;
+      for (int q2 = 0; q2 < w2; ++q2) t += val[2][q2] * row[q2];
+      acc += v01 * t;
+    }
+  out[i] = (TO)acc;
+}
+
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -627,6 +673,25 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
     MFA_TRY(hipGetLastError());
   }
   return hipSuccess;
+}
+
+
+hipError_t launch_decode_points(Handle &h, const double *u, int64_t npts, void *out, bool f32,
+                                const int r[3]) {
+  if (npts == 0) return hipSuccess;
+  PtAxes ax{};
+  for (int a = 0; a < 3; ++a) {
+    ax.n[a] = h.ax[a].n;
+    ax.active[a] = h.ax[a].active;
+    ax.ua[a] = a - (3 - h.dim);
+    ax.r[a] = r[a];
+  }
+  const unsigned grid = (unsigned)((npts + 255) / 256);
+  if (f32)
+    k_decode_points<float><<<grid, 256, 0, h.stream>>>(u, npts, h.dim, h.p, ax, h.P, (float *)out);
+  else
+    k_decode_points<double><<<grid, 256, 0, h.stream>>>(u, npts, h.dim, h.p, ax, h.P, (double *)out);
+  return hipGetLastError();
 }
 
 }  // namespace mfa

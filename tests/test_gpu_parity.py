@@ -249,3 +249,43 @@ def test_predicted_check_schedule_stops_at_or_just_after_the_crossing(precision)
     st = enc.encode(torch.from_numpy(Q).cuda(), 40, w.jump_tol, 0)
     assert st["converged"] and max(st["jump"]) < w.jump_tol
     assert len(hist) <= st["sweep"] <= len(hist) + 3, (st["sweep"], len(hist))
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "3d", "3d-p4"])
+def test_decode_points_match_oracle(name):
+    """Decode at arbitrary parameter points: random points, every knot exactly
+    (right-continuous spans, so order-p derivatives take the right-hand
+    polynomial), the ends, and parameters outside [0, 1] (clamped), against
+    the oracle's collocation rows."""
+    w = SMALL[name]()
+    S = _oracle(w)
+    p = w.degree
+    rng = np.random.default_rng(21)
+    P = rng.standard_normal(w.nctrl)
+    enc = _enc(w)
+    enc.set_ctrl(torch.from_numpy(P).cuda())
+    U = rng.random((500, w.dim))
+    for a, ax in enumerate(S.plan.axes):
+        kn = np.unique(ax.knots)
+        U[:len(kn), a] = kn
+    U[-1], U[-2] = 1.0, 0.0
+    U[-3, 0], U[-4, -1] = -0.25, 1.5
+    Uc = np.clip(U, 0.0, 1.0)
+    ud = torch.from_numpy(U).cuda()
+    orders = [None, (1,) * w.dim, (p,) + (0,) * (w.dim - 1), tuple(min(a + 1, p) for a in range(w.dim))]
+    for der in orders:
+        got = enc.decode_points(ud, deriv=der).cpu().numpy()
+        r = der or (0,) * w.dim
+        rows = [bspline.collocation(ax.knots, ax.n, p, Uc[:, a], r[a]) for a, ax in enumerate(S.plan.axes)]
+        if w.dim == 1:
+            ref = rows[0] @ P
+        elif w.dim == 2:
+            ref = np.einsum("ia,ib,ab->i", rows[0], rows[1], P)
+        else:
+            ref = np.einsum("ia,ib,ic,abc->i", rows[0], rows[1], rows[2], P)
+        assert _rel(got, ref) < 1e-11, (der, _rel(got, ref))
+    f32 = enc.decode_points(ud, dtype=torch.float32).cpu().numpy()
+    f64 = enc.decode_points(ud).cpu().numpy()
+    assert f32.dtype == np.float32 and _rel(f32, f64) < 1e-6
+    with pytest.raises(_lib.MfaError):
+        enc.decode_points(ud, deriv=(p + 1,) * w.dim)
