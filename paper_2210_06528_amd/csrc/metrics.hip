@@ -247,7 +247,6 @@ __global__ void __launch_bounds__(256) k_jump_project_inner(const TG *__restrict
   if (l >= nlines) return;
   const int b = blockIdx.y;
   const TG *src = g + l * n2;
-  double *dst = U + l * (int64_t)(nif * p);
   const int row0 = b * p;
   const int c0 = Jcol[(int64_t)row0 * LJ];
   const int len = Jlen[row0];
@@ -262,7 +261,7 @@ __global__ void __launch_bounds__(256) k_jump_project_inner(const TG *__restrict
   }
 #pragma unroll
   for (int r = 0; r < kMaxP; ++r)
-    if (r < p) dst[row0 + r] = acc[r];
+    if (r < p) U[(int64_t)(row0 + r) * nlines + l] = acc[r];
 }
 
 // Interface projection along the contiguous axis: a workgroup stages LPB
@@ -295,7 +294,7 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
   }
   __syncthreads();
   for (int it = threadIdx.x; it < nl * nif; it += blockDim.x) {
-    const int li = it / nif, b = it - li * nif;
+    const int b = it / nl, li = it - b * nl;
     const int row0 = b * p;
     const int c0 = Jcol[(int64_t)row0 * LJ];
     const int len = Jlen[row0];
@@ -309,10 +308,11 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
       for (int r = 0; r < kMaxP; ++r)
         if (r < p) acc[r] += Jval[(int64_t)(row0 + r) * LJ + t] * v;
     }
-    double *dst = U + (l0 + li) * (int64_t)(nif * p) + row0;
+    // U[row][line]: the interface rows outermost (coalesced here and in the
+    // expansion, whose lanes run along the contiguous other axis)
 #pragma unroll
     for (int r = 0; r < kMaxP; ++r)
-      if (r < p) dst[r] = acc[r];
+      if (r < p) U[(int64_t)(row0 + r) * nlines + l0 + li] = acc[r];
   }
 }
 
@@ -517,7 +517,14 @@ hipError_t launch_jump_expand(Handle &h, int a, const double *U) {
   const int R = (X.B - 1) * h.p;
   int64_t d[3] = {h.ax[0].n, h.ax[1].n, h.ax[2].n};
   d[a] = R;
-  const int64_t st[3] = {d[1] * d[2], d[2], 1};
+  // U has axis a replaced by the R interface rows in place, except for the
+  // contiguous axis (a = 2), whose projection stores the rows outermost
+  int64_t st[3] = {d[1] * d[2], d[2], 1};
+  if (a == 2) {
+    st[2] = d[0] * d[1];
+    st[0] = d[1];
+    st[1] = 1;
+  }
   int oth[2], no = 0;
   for (int c = 0; c < 3; ++c)
     if (c != a && h.ax[c].active) oth[no++] = c;
