@@ -275,9 +275,11 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
                                                             const int *__restrict__ Jcol,
                                                             const int *__restrict__ Jlen,
                                                             const double *__restrict__ Jval, int LJ) {
-  extern __shared__ double sg[];   // [LPB][n2]
+  extern __shared__ double sg[];   // [LPB][n2], then the J rows [nif*p][LJ]
+  double *sJ = sg + (size_t)LPB * n2;
   const int64_t l0 = (int64_t)blockIdx.x * LPB;
   const int nl = (int)min((int64_t)LPB, nlines - l0);
+  for (int e = threadIdx.x; e < nif * p * LJ; e += blockDim.x) sJ[e] = Jval[e];
   const TG *src = g + l0 * n2;
   for (int e0 = 0; e0 < nl * n2; e0 += blockDim.x * kStageM) {
     double v[kStageM];
@@ -302,11 +304,12 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
     double acc[kMaxP];
 #pragma unroll
     for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
+    const double *jr = sJ + (size_t)row0 * LJ;
     for (int t = 0; t < len; ++t) {
       const double v = x[t];
 #pragma unroll
       for (int r = 0; r < kMaxP; ++r)
-        if (r < p) acc[r] += Jval[(int64_t)(row0 + r) * LJ + t] * v;
+        if (r < p) acc[r] += jr[r * LJ + t] * v;
     }
     // U[row][line]: the interface rows outermost (coalesced here and in the
     // expansion, whose lanes run along the contiguous other axis)
@@ -485,10 +488,11 @@ hipError_t launch_deriv_scale(Handle &h) {
 template <typename TG>
 hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U) {
   const Axis &X = h.ax[a];
-  if (a == 2 && (int64_t)X.n * 8 <= 32768) {
+  const size_t jbytes = sizeof(double) * (size_t)(X.B - 1) * h.p * X.J.L;
+  if (a == 2 && (int64_t)X.n * 8 <= 32768 && jbytes <= 16384) {
     const int64_t nlines = (int64_t)h.ax[0].n * h.ax[1].n;
     const int LPB = std::max(1, std::min(32, 32768 / (8 * X.n)));
-    k_jump_project_lines<TG><<<nblk(nlines, LPB), 256, sizeof(double) * LPB * X.n, h.stream>>>(
+    k_jump_project_lines<TG><<<nblk(nlines, LPB), 256, sizeof(double) * LPB * X.n + jbytes, h.stream>>>(
         g, U, nlines, X.n, X.B - 1, h.p, LPB, X.J.col, X.J.len, X.J.val, X.J.L);
     return hipGetLastError();
   }
