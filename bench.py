@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--check-every", type=int, default=0)
     ap.add_argument("--max-sweeps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=5,
+                    help="oracle sweeps timed for the CPU baseline (about 3 s each here)")
     ap.add_argument("--breakdown-steps", type=int, default=2,
                     help="extra untimed steps with every kernel class event-timed")
     ap.add_argument("--no-fp64-compare", action="store_true",
@@ -65,7 +66,7 @@ def get_workload(name, precision):
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, datasheet
 
 # HBM traffic of the residual stencil from two rocprofv3 --pmc passes
-# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the 28 launches of
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the 30 launches of
 # one 512x512x384 p=4 mixed-precision encode), scaled by what the same counters
 # read for a plain 1 GiB streaming copy (FETCH_SIZE 524303 KiB for 1048576 KiB
 # read: x2.0; WRITE_SIZE 1048576 KiB for 1048576 KiB written: x1.0).  Valid only
@@ -76,8 +77,8 @@ RESID_COUNTERS = {
     "precision": "mixed_bf16",
     "source": "paper_2210_06528_amd/csrc/sweep.hip",
     "source_sha256": "b6594f7f6893be15c141cdd25d50c37e89ae932e6f09e383925afe43addfef2d",
-    "fetch_kib": 206449.2, "write_kib": 49416.0,
-    "fetch_factor": 1048576.0 / 524302.9, "write_factor": 1.0,
+    "fetch_kib": 206553.4, "write_kib": 49416.0,
+    "fetch_factor": 1048576.0 / 524303.0, "write_factor": 1.0,
 }
 
 
