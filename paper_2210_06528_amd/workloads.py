@@ -226,8 +226,44 @@ def cfg_3d_mixed(precision="mixed_bf16"):
                     precision=precision, jump_tol=1e-8, dtype="f32", seed=0)
 
 
+def cfg_e1(overlap=4, m=10000, nsub=2, n_per=16):
+    """1-D asymmetric sinc sum of Section 3.1.1 on [-4, 4], p=3, two subdomains."""
+    w = Workload(f"e1-asym-sinc-{m}-o{overlap}", (m,), 3, [[n_per] * nsub], overlap,
+                 jump_tol=1e-8, dtype="f64")
+    w.extra["field"] = "e1"
+    return w
+
+
+def cfg_e2(nsub=5, overlap=1, m=10000, n=50):
+    """1-D symmetric sinc sum of Section 3.1.2 on [-4, 4], p=3, n control points in nsub blocks."""
+    w = Workload(f"e2-sym-sinc-{m}-N{nsub}-o{overlap}", (m,), 3, [even_sizes(n, nsub)], overlap,
+                 jump_tol=1e-8, dtype="f64")
+    w.extra["field"] = "e2"
+    return w
+
+
+def cfg_e5(dim=2, overlap=1):
+    """Radial sinc fields of Section 3.2.3 on [-4, 4]^d: 2-D with 5x5 subdomains,
+    3-D with 3x3x3, p=3, the minimum overlap (no augmented spans)."""
+    if dim == 2:
+        w = Workload("e5-radial-sinc-201sq", (201, 201), 3, [[12] * 5] * 2, overlap,
+                     jump_tol=1e-8, dtype="f64")
+    else:
+        w = Workload("e5-radial-sinc-81cube", (81, 81, 81), 3, [[12] * 3] * 3, overlap,
+                     jump_tol=1e-8, dtype="f64")
+    w.extra["field"] = "e5"
+    return w
+
+
 def make_field(w: Workload):
     """The input array of a named workload (float64 or float32)."""
+    kind = w.extra.get("field")
+    if kind == "e1":
+        return field_paper_1d_asymmetric(w.npts[0])
+    if kind == "e2":
+        return field_paper_1d_symmetric(w.npts[0])
+    if kind == "e5":
+        return field_paper_radial(w.npts)
     if w.dim == 1 and w.npts == (2000,):
         return field_sinc_1d(2000)
     if w.dim == 2 and w.npts == (1024, 1024) and w.name.startswith("2d-sinc"):
