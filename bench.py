@@ -67,8 +67,9 @@ def get_workload(name, precision):
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, datasheet
 
 # HBM traffic of the residual stencil from two rocprofv3 --pmc passes
-# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the 30 launches of
-# one 512x512x384 p=4 mixed-precision encode), scaled by what the same counters
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the 30 sweep
+# launches of one 512x512x384 p=4 mixed-precision encode, 384 workgroups in
+# x-chunks of 32 planes), scaled by what the same counters
 # read for a plain 1 GiB streaming copy (FETCH_SIZE 524303 KiB for 1048576 KiB
 # read: x2.0; WRITE_SIZE 1048576 KiB for 1048576 KiB written: x1.0).  Valid only
 # for the kernel source it was taken on: the bench reports null traffic once
@@ -77,8 +78,8 @@ RESID_COUNTERS = {
     "workload": "3d-spectral-512x512x384-p4-uneven",
     "precision": "mixed_bf16",
     "source": "paper_2210_06528_amd/csrc/sweep.hip",
-    "source_sha256": "b6594f7f6893be15c141cdd25d50c37e89ae932e6f09e383925afe43addfef2d",
-    "fetch_kib": 206553.4, "write_kib": 49416.0,
+    "source_sha256": "18c94cd6646bafb551585aea45eb59879d5e18007b70132e7514073177eb2743",
+    "fetch_kib": 166757.5, "write_kib": 49248.0,
     "fetch_factor": 1048576.0 / 524303.0, "write_factor": 1.0,
 }
 

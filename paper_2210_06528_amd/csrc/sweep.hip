@@ -11,6 +11,11 @@
 //             1/n_s combine of overlapping segments done in LDS.
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 #include "mfa_internal.hpp"
 
 namespace mfa {
@@ -433,19 +438,88 @@ __global__ void __launch_bounds__(1024) k_bsolve_seg(const TI *__restrict__ in, 
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// x-chunk of the residual stencil for a target number of workgroups (each
+// chunk re-reads 2p halo planes; more workgroups fill the chip better)
+inline int resid_xchunk(int n0, int byz, int target) {
+  int xchunk = n0;
+  if (byz < target) xchunk = std::max(4, (int)((int64_t)n0 * byz / target));
+  return std::min(xchunk, n0);
+}
+
+// Autotuned x-chunk per shape.  The residual is idempotent (it reads P and c
+// and writes g), and every output's arithmetic is the same whatever the
+// chunking, so on the first launch for a large shape each candidate runs on
+// the live arrays and is timed with events; the fastest is kept for the life
+// of the process.  Small shapes take the heuristic choice untimed.
+struct ResidKey {
+  int n0, n1, n2, p, tg;
+  bool operator<(const ResidKey &o) const {
+    return std::tie(n0, n1, n2, p, tg) < std::tie(o.n0, o.n1, o.n2, o.p, o.tg);
+  }
+};
+std::mutex g_resid_mu;
+std::map<ResidKey, int> g_resid_chunk;
+constexpr int64_t kTuneMinCtrl = 1 << 20;
+
 template <int P, typename TG>
 hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG *g, const double *A0,
                           const double *A1, const double *A2, int n0, int n1, int n2,
                           unsigned long long *slots) {
   const int byz = (int)(nblk(n2, kTZ) * nblk(n1, kTY));
-  // enough workgroups to fill the chip; the x halo (2p planes) is re-read
-  int xchunk = n0;
-  const int target = 1024;
-  if (byz * 1 < target) xchunk = std::max(4, (int)((int64_t)n0 * byz / target));
-  xchunk = std::min(xchunk, n0);
-  const dim3 grid(nblk(n2, kTZ), nblk(n1, kTY), nblk(n0, xchunk));
-  k_resid<P, TG><<<grid, kRT, 0, st>>>(Pc, c, g, A0, A1, A2, n0, n1, n2, xchunk, slots);
-  return hipGetLastError();
+  const ResidKey key{n0, n1, n2, P, (int)sizeof(TG)};
+  int xchunk = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_resid_mu);
+    auto it = g_resid_chunk.find(key);
+    if (it != g_resid_chunk.end()) xchunk = it->second;
+  }
+  auto launch = [&](int xc) {
+    const dim3 grid(nblk(n2, kTZ), nblk(n1, kTY), nblk(n0, xc));
+    k_resid<P, TG><<<grid, kRT, 0, st>>>(Pc, c, g, A0, A1, A2, n0, n1, n2, xc, slots);
+    return hipGetLastError();
+  };
+  if (xchunk == 0) {
+    // default: about 384 workgroups (1.5 per CU; the best of a sweep of
+    // targets on 256 x 256 x 192), 768 for small shapes
+    const int64_t nctrl = (int64_t)n0 * n1 * n2;
+    const int xdef = resid_xchunk(n0, byz, nctrl >= kTuneMinCtrl ? 384 : 768);
+    xchunk = xdef;
+    if (nctrl >= kTuneMinCtrl) {
+      std::vector<int> cand{xdef};
+      for (int target : {256, 512, 768, 1024, 1536}) {
+        const int xc = resid_xchunk(n0, byz, target);
+        if (std::find(cand.begin(), cand.end(), xc) == cand.end()) cand.push_back(xc);
+      }
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) != hipSuccess) return hipErrorOutOfMemory;
+      if (hipEventCreate(&e1) != hipSuccess) return hipErrorOutOfMemory;
+      // each candidate timed three times (fastest kept); the default stays
+      // unless a candidate is at least 10% faster, so that timing noise
+      // (or a profiler's overhead) cannot flip the choice
+      std::vector<float> tmin(cand.size(), 1e30f);
+      hipError_t err = launch(cand[0]);   // warm-up
+      for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+        for (size_t i = 0; i < cand.size() && err == hipSuccess; ++i) {
+          float ms = 0.f;
+          hipEventRecord(e0, st);
+          err = launch(cand[i]);
+          hipEventRecord(e1, st);
+          if (err == hipSuccess) err = hipEventSynchronize(e1);
+          if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+          if (err == hipSuccess) tmin[i] = std::min(tmin[i], ms);
+        }
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      if (err != hipSuccess) return err;
+      const size_t ib = std::min_element(tmin.begin(), tmin.end()) - tmin.begin();
+      const size_t id = std::find(cand.begin(), cand.end(), xdef) - cand.begin();
+      xchunk = tmin[ib] < 0.9f * tmin[id] ? cand[ib] : xdef;
+    }
+    std::lock_guard<std::mutex> lk(g_resid_mu);
+    g_resid_chunk[key] = xchunk;
+  }
+  return launch(xchunk);
 }
 
 }  // namespace
