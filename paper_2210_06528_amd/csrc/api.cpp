@@ -132,7 +132,8 @@ bool mfma_ok(const Handle &h) {
 
 bool fast_sweep_ok(const Handle &h, size_t elem) {
   for (int a = 0; a < 3; ++a)
-    if (h.ax[a].active && bsolve_lds(h.ax[a].Fmax, h.p, elem) > 64 * 1024) return false;
+    if (h.ax[a].active && !bsolve_seg_ok(h.ax[a]) && bsolve_lds(h.ax[a].Fmax, h.p, elem) > 64 * 1024)
+      return false;
   return true;
 }
 

@@ -217,6 +217,7 @@ hipError_t setup_mfma(Handle *h, int a, hipStream_t st);
 hipError_t launch_mfma_correct(Handle &h, int axis, const float *in, float *out, bool add);
 
 // LDS bytes the banded-solve kernel needs for segments of length fmax
+bool bsolve_seg_ok(const Axis &X);
 inline size_t bsolve_lds(int64_t fmax, int p, size_t elem) {
   return (size_t)2 * fmax * 65 * elem + sizeof(double) * (size_t)(p + 2) * fmax;
 }

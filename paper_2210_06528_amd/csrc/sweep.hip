@@ -348,7 +348,8 @@ __global__ void __launch_bounds__(64) k_bsolve(const TI *__restrict__ in, TO *__
 // [F0_b, F0_{b+1}), adding the left neighbour's tail on the shared part with
 // weight 1/n_s (AVG) or taking the owner's value (RAS).
 template <typename TI, typename TO, typename TC, int MODE, int MAXF>
-__global__ void __launch_bounds__(1024) k_bsolve_seg(const TI *__restrict__ in, TO *__restrict__ out,
+__global__ void __launch_bounds__(MAXF >= 64 ? 256 : 1024) k_bsolve_seg(const TI *__restrict__ in,
+                                                                          TO *__restrict__ out,
                                                      double *__restrict__ pc, LineGeom G,
                                                      int64_t nlines, int p, int B,
                                                      const int *__restrict__ blk,
@@ -563,13 +564,19 @@ hipError_t launch_bsolve_seg(hipStream_t st, const TI *in, TO *out, double *pc, 
   return hipGetLastError();
 }
 
+// segment-parallel banded solves (a wavefront per subdomain, segments held
+// in registers): up to 16 subdomains per axis with segments of at most 48
+// control points, up to 4 with segments of at most 64 (the wide variant runs
+// 256-thread workgroups so its segments fit the registers)
+bool bsolve_seg_ok(const Axis &X) { return (X.B <= 16 && X.Fmax <= 48) || (X.B <= 4 && X.Fmax <= 64); }
+
 template <typename TI, typename TO, typename TC>
 hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int axis, int n0, int n1,
                          int n2, int p, const Axis &X, int combine, unsigned long long *slots) {
   LineGeom G{axis, n0, n1, n2};
   const int64_t len = axis == 0 ? n0 : (axis == 1 ? n1 : n2);
   const int64_t nlines = (int64_t)n0 * n1 * n2 / len;
-  if (X.B <= 16 && X.Fmax <= 64) {
+  if (bsolve_seg_ok(X)) {
     int ov = 0;
     for (int b = 0; b + 1 < X.B; ++b) ov = std::max(ov, X.blk[b].F1 - X.blk[b + 1].F0);
     if (X.Fmax <= 16) return launch_bsolve_seg<TI, TO, TC, 16>(st, in, out, pc, G, nlines, p, X, combine, ov, slots);
