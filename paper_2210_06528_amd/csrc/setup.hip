@@ -135,9 +135,53 @@ __global__ void __launch_bounds__(64) k_gram(int64_t m, int n, int p, const int 
 
 // Batched banded Cholesky of every subdomain's local normal matrix
 // A[F0:F1, F0:F1] (a principal block of the axis' band; Section 2.3.1).
-// One wavefront per matrix: lane 0 forms the pivot of column j, lanes 1..p
-// the subdiagonal entries.  A non-positive pivot sets flag[0].
+// One wavefront per matrix, the factor built in LDS and written out once:
+// lane 0 forms the pivot of column j, lanes 1..p the subdiagonal entries.
+// A non-positive pivot sets flag[0].
 __global__ void __launch_bounds__(64) k_chol(int n, int p, const double *band, const int *blk,
+                                             double *chol, double *rdiag, int *flag) {
+  extern __shared__ double Ls[];   // Ls[t*F + j] = L(j+t, j)
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  int64_t off = 0, roff = 0;
+  for (int bb = 0; bb < b; ++bb) {
+    off += (int64_t)(p + 1) * (blk[8 * bb + 3] - blk[8 * bb + 2]);
+    roff += blk[8 * bb + 3] - blk[8 * bb + 2];
+  }
+  const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
+  for (int j = 0; j < F; ++j) {
+    if (lane == 0) {
+      const double ajj = band[F0 + j];
+      double s = ajj;
+      for (int k = max(0, j - p); k < j; ++k) {
+        const double l = Ls[(j - k) * F + k];
+        s -= l * l;
+      }
+      if (!(s > 1e-13 * ajj) || !(s > 0.0)) {
+        atomicOr(flag, 1);
+        s = 1.0;
+      }
+      Ls[j] = sqrt(s);
+    }
+    __syncthreads();
+    if (lane >= 1 && lane <= p) {
+      const int i = j + lane;
+      if (i < F) {
+        double s = band[(int64_t)lane * n + F0 + j];
+        for (int k = max(0, i - p); k < j; ++k) s -= Ls[(i - k) * F + k] * Ls[(j - k) * F + k];
+        Ls[lane * F + j] = s / Ls[j];
+      } else {
+        Ls[lane * F + j] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = lane; e < (p + 1) * F; e += 64) chol[off + e] = Ls[e];
+  for (int e = lane; e < F; e += 64) rdiag[roff + e] = 1.0 / Ls[e];
+}
+
+// The same with the factor in global memory (segments too long for LDS).
+__global__ void __launch_bounds__(64) k_chol_global(int n, int p, const double *band, const int *blk,
                                              double *chol, double *rdiag, int *flag) {
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
@@ -180,7 +224,7 @@ __global__ void __launch_bounds__(64) k_chol(int n, int p, const double *band, c
 
 // Dense inverse of every local normal matrix from its banded Cholesky factor:
 // column `col` solves L L^T z = e_col by forward and backward substitution.
-__global__ void k_inverse(int p, const int *blk, const double *chol, double *inv) {
+__global__ void k_inverse_global(int p, const int *blk, const double *chol, double *inv) {
   const int b = blockIdx.x;
   int64_t offc = 0, offi = 0;
   for (int bb = 0; bb < b; ++bb) {
@@ -204,6 +248,39 @@ __global__ void k_inverse(int p, const int *blk, const double *chol, double *inv
       Z[(int64_t)i * F + col] = s / L[i];
     }
   }
+}
+
+// The same with the factor and the inverse in LDS (F^2 + (p+1)F doubles),
+// written out coalesced at the end.
+__global__ void k_inverse(int p, const int *blk, const double *chol, double *inv) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x;
+  int64_t offc = 0, offi = 0;
+  for (int bb = 0; bb < b; ++bb) {
+    const int Fb = blk[8 * bb + 3] - blk[8 * bb + 2];
+    offc += (int64_t)(p + 1) * Fb;
+    offi += (int64_t)Fb * Fb;
+  }
+  const int F = blk[8 * b + 3] - blk[8 * b + 2];
+  double *L = sm;                       // [(p+1) * F]
+  double *Z = sm + (size_t)(p + 1) * F;  // [F * F]
+  for (int e = threadIdx.x; e < (p + 1) * F; e += blockDim.x) L[e] = chol[offc + e];
+  __syncthreads();
+  for (int col = threadIdx.x; col < F; col += blockDim.x) {
+    for (int i = 0; i < F; ++i) {
+      double s = (i == col) ? 1.0 : 0.0;
+      if (i > col)
+        for (int k = max(col, i - p); k < i; ++k) s -= L[(i - k) * F + k] * Z[k * F + col];
+      Z[i * F + col] = (i < col) ? 0.0 : s / L[i];
+    }
+    for (int i = F - 1; i >= 0; --i) {
+      double s = Z[i * F + col];
+      for (int k = i + 1; k <= min(F - 1, i + p); ++k) s -= L[(k - i) * F + i] * Z[k * F + col];
+      Z[i * F + col] = s / L[i];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < F * F; e += blockDim.x) inv[offi + e] = Z[e];
 }
 
 __device__ __forceinline__ int64_t inv_offset(const int *blk, int b) {
@@ -257,79 +334,94 @@ __global__ void k_tab_A(int n, int p, const double *band, Ell t) {
 // Weighted additive-Schwarz operator of one axis:
 // M[k][:] = sum over blocks b whose free set holds k of w_k Z_b[k - F0_b][:],
 // w_k = 1/n_s(k) (combine AVG) or the owner indicator (combine RAS).
-__global__ void k_tab_M(int n, int combine, const int *blk, const int *blo, const int *bhi,
-                        const int *owner, const int *ns, const double *inv, Ell t) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+__global__ void __launch_bounds__(64) k_tab_M(int n, int combine, const int *blk, const int *blo,
+                                              const int *bhi, const int *owner, const int *ns,
+                                              const double *inv, Ell t) {
+  // one wavefront per row, lanes over its columns (each entry written once)
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x;
   int b0 = blo[k], b1 = bhi[k];
   if (combine == MFA_COMBINE_RAS) b0 = b1 = owner[k];
   const int cfirst = blk[8 * b0 + 2], clast = blk[8 * b1 + 3];
   const double w = combine == MFA_COMBINE_RAS ? 1.0 : 1.0 / (double)ns[k];
   const int len = clast - cfirst;
-  for (int q = 0; q < len; ++q) {
-    t.col[(int64_t)k * t.L + q] = cfirst + q;
-    t.val[(int64_t)k * t.L + q] = 0.0;
+  for (int q = lane; q < t.L; q += 64) {
+    const int col = cfirst + q;
+    double v = 0.0;
+    if (q < len) {
+      for (int b = b0; b <= b1; ++b) {
+        const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
+        if (col >= F0 && col < F0 + F) v += w * inv[inv_offset(blk, b) + (int64_t)(k - F0) * F + (col - F0)];
+      }
+    }
+    t.col[(int64_t)k * t.L + q] = q < len ? col : (len > 0 ? clast - 1 : 0);
+    t.val[(int64_t)k * t.L + q] = v;
   }
-  for (int b = b0; b <= b1; ++b) {
-    const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
-    const double *Z = inv + inv_offset(blk, b);
-    for (int c = 0; c < F; ++c) t.val[(int64_t)k * t.L + (F0 + c - cfirst)] += w * Z[(int64_t)(k - F0) * F + c];
-  }
-  pad_row(t, k, len);
+  if (lane == 0) t.len[k] = len;
 }
 
 // Decode of a subdomain's local correction at its owned data points:
 // Om[i][:] = sum_q N_{s-p+q}(u_i) Z_b[s-p+q - F0_b][:] over the free set of the
 // block b that owns point i (basis functions outside F_b carry no correction).
-__global__ void k_tab_Om(int64_t m, int p, const int *blk, const int *pown, const int *span,
-                         Ell basis, const double *inv, Ell t) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+__global__ void __launch_bounds__(64) k_tab_Om(int64_t m, int p, const int *blk, const int *pown,
+                                               const int *span, Ell basis, const double *inv, Ell t) {
+  // one wavefront per data point, lanes over the free set of its owner
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
   const int b = pown[i];
   const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
   const double *Z = inv + inv_offset(blk, b);
   const int s = span[i];
-  for (int c = 0; c < F; ++c) {
+  for (int c = lane; c < t.L; c += 64) {
     double acc = 0.0;
-    for (int q = 0; q <= p; ++q) {
-      const int j = s - p + q - F0;
-      if (j >= 0 && j < F) acc += basis.val[i * basis.L + q] * Z[(int64_t)j * F + c];
+    if (c < F) {
+      for (int q = 0; q <= p; ++q) {
+        const int j = s - p + q - F0;
+        if (j >= 0 && j < F) acc += basis.val[i * basis.L + q] * Z[(int64_t)j * F + c];
+      }
     }
-    t.col[i * t.L + c] = F0 + c;
+    t.col[i * t.L + c] = c < F ? F0 + c : F0 + F - 1;
     t.val[i * t.L + c] = acc;
   }
-  pad_row(t, i, F);
+  if (lane == 0) t.len[i] = F;
 }
 
 // Interface jump functionals: row (b, r) maps a residual line to
 // d^r/du^r (L_b - L_{b+1})(u*_b) = dB_r(u*)^T (E_b Z_b R_b - E_{b+1} Z_{b+1} R_{b+1}).
-__global__ void k_tab_J(int nif, int p, const int *blk, const int *span_if, const double *dbas,
-                        const double *inv, Ell t, int *gid) {
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= nif * p) return;
+__global__ void __launch_bounds__(64) k_tab_J(int nif, int p, const int *blk, const int *span_if,
+                                              const double *dbas, const double *inv, Ell t, int *gid) {
+  // one wavefront per row (b, r), lanes over its columns
+  const int row = blockIdx.x;
+  const int lane = threadIdx.x;
   const int b = row / p, r = row % p;
   const int cfirst = blk[8 * b + 2], clast = blk[8 * (b + 1) + 3];
   const int len = clast - cfirst;
   const double *dv = dbas + (int64_t)row * (p + 1);
   const int s = span_if[b];
-  for (int q = 0; q < len; ++q) {
-    t.col[(int64_t)row * t.L + q] = cfirst + q;
-    t.val[(int64_t)row * t.L + q] = 0.0;
-  }
-  for (int side = 0; side < 2; ++side) {
-    const int bb = b + side;
-    const double sgn = side == 0 ? 1.0 : -1.0;
-    const int F0 = blk[8 * bb + 2], F = blk[8 * bb + 3] - F0;
-    const double *Z = inv + inv_offset(blk, bb);
-    for (int q = 0; q <= p; ++q) {
-      const int j = s - p + q - F0;
-      if (j < 0 || j >= F) continue;
-      for (int c = 0; c < F; ++c)
-        t.val[(int64_t)row * t.L + (F0 + c - cfirst)] += sgn * dv[q] * Z[(int64_t)j * F + c];
+  for (int q = lane; q < t.L; q += 64) {
+    const int col = cfirst + q;
+    double v = 0.0;
+    if (q < len) {
+      for (int side = 0; side < 2; ++side) {
+        const int bb = b + side;
+        const double sgn = side == 0 ? 1.0 : -1.0;
+        const int F0 = blk[8 * bb + 2], F = blk[8 * bb + 3] - F0;
+        if (col < F0 || col >= F0 + F) continue;
+        const double *Z = inv + inv_offset(blk, bb);
+        for (int qq = 0; qq <= p; ++qq) {
+          const int j = s - p + qq - F0;
+          if (j < 0 || j >= F) continue;
+          v += sgn * dv[qq] * Z[(int64_t)j * F + (col - F0)];
+        }
+      }
     }
+    t.col[(int64_t)row * t.L + q] = q < len ? col : (len > 0 ? clast - 1 : 0);
+    t.val[(int64_t)row * t.L + q] = v;
   }
-  pad_row(t, row, len);
-  gid[row] = r;
+  if (lane == 0) {
+    t.len[row] = len;
+    gid[row] = r;
+  }
 }
 
 // Derivative-coefficient operator: rows of D^r for r = 0..p-1 stacked; row k
@@ -645,18 +737,26 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
   }
   k_gram<<<n, 64, 0, st>>>(m, n, p, X.d_span, X.N[0], X.d_gram);
   MFA_TRY(hipGetLastError());
-  k_chol<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
+  const size_t chol_lds = sizeof(double) * (p + 1) * X.Fmax;
+  if (chol_lds <= 64 * 1024)
+    k_chol<<<B, 64, chol_lds, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
+  else
+    k_chol_global<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
   MFA_TRY(hipGetLastError());
-  k_inverse<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
+  const size_t inv_lds = sizeof(double) * ((size_t)(p + 1) * X.Fmax + (size_t)X.Fmax * X.Fmax);
+  if (inv_lds <= 64 * 1024)
+    k_inverse<<<B, 256, inv_lds, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
+  else
+    k_inverse_global<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
   MFA_TRY(hipGetLastError());
   k_tab_NT<<<nblk(n, 128), 128, 0, st>>>(m, n, p, X.d_span, X.N[0], X.NT);
   k_tab_A<<<nblk(n, 128), 128, 0, st>>>(n, p, X.d_gram, X.A);
-  k_tab_M<<<nblk(n, 64), 64, 0, st>>>(n, h->combine, X.d_blk, X.d_blo, X.d_bhi, X.d_owner, X.d_ns,
+  k_tab_M<<<n, 64, 0, st>>>(n, h->combine, X.d_blk, X.d_blo, X.d_bhi, X.d_owner, X.d_ns,
                                       X.d_inv, X.M);
-  k_tab_Om<<<nblk(m, 64), 64, 0, st>>>(m, p, X.d_blk, X.d_pown, X.d_span, X.N[0], X.d_inv, X.Om);
+  k_tab_Om<<<(unsigned)m, 64, 0, st>>>(m, p, X.d_blk, X.d_pown, X.d_span, X.N[0], X.d_inv, X.Om);
   k_transpose_vals<<<nblk(m * X.Om.L, 256), 256, 0, st>>>(X.Om.val, m, X.Om.L, X.d_omT);
   if (nif > 0)
-    k_tab_J<<<nblk((int64_t)nif * p, 64), 64, 0, st>>>(nif, p, X.d_blk, X.d_span_if, X.d_dbas_if,
+    k_tab_J<<<nif * p, 64, 0, st>>>(nif, p, X.d_blk, X.d_span_if, X.d_dbas_if,
                                                        X.d_inv, X.J, X.d_gidJ);
   k_tab_D<<<nblk(X.ND, 128), 128, 0, st>>>(n, p, X.D, X.d_gidD);
   MFA_TRY(hipGetLastError());
