@@ -156,13 +156,18 @@ __global__ void __launch_bounds__(256) k_jump_project(const TG *__restrict__ g, 
                                                       const int *__restrict__ Jcol,
                                                       const int *__restrict__ Jlen,
                                                       const double *__restrict__ Jval, int LJ) {
-  // output coordinates with axis a replaced by the interface index b
+  extern __shared__ double sJ[];   // the workgroup's interface rows [p][LJ]
+  // output coordinates with axis a replaced by the interface index b (uniform
+  // over the workgroup: grid.z for a = 0, grid.y for a = 1)
   int d[3] = {n0, n1, n2};
   d[a] = nif;
   const int x2 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x2 >= d[2]) return;
   int x[3] = {(int)blockIdx.z, (int)blockIdx.y, x2};
   const int b = x[a];
+  const int row0 = b * p;
+  for (int e = threadIdx.x; e < p * LJ; e += blockDim.x) sJ[e] = Jval[(int64_t)row0 * LJ + e];
+  __syncthreads();
+  if (x2 >= d[2]) return;
   const int64_t gs[3] = {(int64_t)n1 * n2, n2, 1};
   int R[3] = {n0, n1, n2};
   R[a] = nif * p;
@@ -170,17 +175,25 @@ __global__ void __launch_bounds__(256) k_jump_project(const TG *__restrict__ g, 
   x[a] = 0;
   const int64_t gbase = x[0] * gs[0] + x[1] * gs[1] + x[2] * gs[2];
   const int64_t ubase = x[0] * us[0] + x[1] * us[1] + x[2] * us[2];
-  const int row0 = b * p;
   const int c0 = Jcol[(int64_t)row0 * LJ];
   const int len = Jlen[row0];
+  const TG *src = g + gbase + (int64_t)c0 * gs[a];
   double acc[kMaxP];
 #pragma unroll
   for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
-  for (int t = 0; t < len; ++t) {
-    const double v = tod(g[gbase + (int64_t)(c0 + t) * gs[a]]);
+  // eight strided loads in flight per step
+  for (int t0 = 0; t0 < len; t0 += 8) {
+    double v[8];
 #pragma unroll
-    for (int r = 0; r < kMaxP; ++r)
-      if (r < p) acc[r] += Jval[(int64_t)(row0 + r) * LJ + t] * v;
+    for (int u = 0; u < 8; ++u) v[u] = t0 + u < len ? tod(src[(int64_t)(t0 + u) * gs[a]]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (t0 + u < len) {
+#pragma unroll
+        for (int r = 0; r < kMaxP; ++r)
+          if (r < p) acc[r] += sJ[r * LJ + t0 + u] * v[u];
+      }
+    }
   }
 #pragma unroll
   for (int r = 0; r < kMaxP; ++r)
@@ -507,7 +520,8 @@ hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U) {
   d[a] = X.B - 1;
   const int bs = d[2] >= 256 ? 256 : ((d[2] + 63) / 64) * 64;
   const dim3 grid(nblk(d[2], bs), d[1], d[0]);
-  k_jump_project<TG><<<grid, bs, 0, h.stream>>>(g, U, a, h.ax[0].n, h.ax[1].n, h.ax[2].n, X.B - 1,
+  k_jump_project<TG><<<grid, bs, sizeof(double) * h.p * X.J.L, h.stream>>>(g, U, a, h.ax[0].n, h.ax[1].n,
+                                                                            h.ax[2].n, X.B - 1,
                                                 h.p, X.J.col, X.J.len, X.J.val, X.J.L);
   return hipGetLastError();
 }
