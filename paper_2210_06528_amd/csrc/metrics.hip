@@ -318,11 +318,19 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
 #pragma unroll
     for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
     const double *jr = sJ + (size_t)row0 * LJ;
-    for (int t = 0; t < len; ++t) {
-      const double v = x[t];
+    // eight terms per step: their LDS reads are issued before the first use
+    for (int t0 = 0; t0 < len; t0 += 8) {
+      double v[8];
 #pragma unroll
-      for (int r = 0; r < kMaxP; ++r)
-        if (r < p) acc[r] += jr[r * LJ + t] * v;
+      for (int u = 0; u < 8; ++u) v[u] = t0 + u < len ? x[t0 + u] : 0.0;
+#pragma unroll
+      for (int r = 0; r < kMaxP; ++r) {
+        if (r < p) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (t0 + u < len) acc[r] += jr[r * LJ + t0 + u] * v[u];
+        }
+      }
     }
     // U[row][line]: the interface rows outermost (coalesced here and in the
     // expansion, whose lanes run along the contiguous other axis)
