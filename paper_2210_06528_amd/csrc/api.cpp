@@ -8,6 +8,8 @@
 
 #include <hip/hip_bf16.h>
 
+#include <cstdlib>
+
 #include "mfa_internal.hpp"
 
 using namespace mfa;
@@ -180,6 +182,17 @@ hipError_t sweep_normal(Handle &h) {
                               h.ax[2].d_acoef, n0, n1, n2, h.slots);
     }
     if (e != hipSuccess) return e;
+    if (h.fuse21 && h.ax[0].active && mfma_fused21_ok(h)) {
+      // axes 2 and 1 in one pass, then axis 0 adds into P
+      float *s1 = reinterpret_cast<float *>(h.s1);
+      {
+        TimeScope ts(h, MFA_K_CORRECT);
+        e = launch_mfma_fused21(h, gf, s1);
+      }
+      if (e != hipSuccess) return e;
+      TimeScope ts(h, MFA_K_CORRECT);
+      return launch_mfma_correct(h, 0, s1, nullptr, true);
+    }
     int act[3], na = 0;
     for (int a = 2; a >= 0; --a)
       if (h.ax[a].active) act[na++] = a;
@@ -424,6 +437,12 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
   }
   h.ws = (char *)workspace;
   h.ws_bytes = bytes;
+  // diagnostic: MFA_UNFUSED_CORRECTION=1 runs the split-BF16 correction as
+  // three separate passes (the same arithmetic) instead of the fused one
+  {
+    const char *env = getenv("MFA_UNFUSED_CORRECTION");
+    h.fuse21 = !(env && env[0] == '1');
+  }
   layout_workspace(&h, h.ws);
   h.stream = (hipStream_t)hip_stream;
   hipError_t e = hipGetDevice(&h.device);

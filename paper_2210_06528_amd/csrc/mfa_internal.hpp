@@ -113,6 +113,7 @@ struct Handle {
   int *flag = nullptr;                   // setup error flag
   double *hist = nullptr;                // max |correction| of recent sweeps (ring of kHist)
   size_t upload_bytes = 0;               // host-planned tables: workspace bytes [0, upload_bytes)
+  bool fuse21 = true;                    // fused axis-2/axis-1 correction when it applies
   bool have_rhs = false;
   const void *q = nullptr;  // data of the last encode / step (read every sweep in DATABOX mode)
   int q_dtype = 0;
@@ -214,6 +215,10 @@ hipError_t launch_project_grid(Handle &h, const void *q, bool f32);
 hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3]);
 bool mfma_fits(int npad);
 hipError_t setup_mfma(Handle *h, int a, hipStream_t st);
+// axes 2 and 1 of the split-BF16 correction in one pass (3-D problems)
+int fuse21_ldw(const Handle &h);
+bool mfma_fused21_ok(const Handle &h);
+hipError_t launch_mfma_fused21(Handle &h, const float *in, float *out);
 hipError_t launch_mfma_correct(Handle &h, int axis, const float *in, float *out, bool add);
 
 // LDS bytes the banded-solve kernel needs for segments of length fmax

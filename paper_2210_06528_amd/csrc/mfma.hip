@@ -12,6 +12,9 @@
 // the float64 residual.
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "mfa_internal.hpp"
 
 namespace mfa {
@@ -61,46 +64,21 @@ constexpr int kIT = 32;    // columns per workgroup on the strided axes
 constexpr int kStage = 16; // staging loads per thread issued before the first wait
 constexpr int kPre = 4;    // K chunks of a tile's M fragments requested up front
 
-// Strided axis: the array is [outer][n][inner] (FP32); workgroup = (one outer
-// index, kIT columns of inner), all n output rows.  IN[:, i0:i0+kIT] is staged
-// in LDS transposed and split (Thi/Tlo[i][j], j contiguous) so a B fragment is
-// one 16-byte LDS read.  Wave w computes row tiles w, w+4, ...; MODE 0 stores
-// FP32, MODE 1 adds into the float64 control points and reduces max |corr|.
+// Apply M_a (rows from global, split) to the kIT staged columns Thi/Tlo
+// ([kIT][ld], contraction index contiguous) of outer index o: OUT[o][k][i0+ii]
+// for every row k; MODE 0 stores FP32, MODE 1 adds into the float64 control
+// points and keeps max |correction| in dmax.  Waves take row tiles w, w+4, ...
 template <int MODE>
-__global__ void __launch_bounds__(256) k_mfma_strided(const float *__restrict__ in,
-                                                      float *__restrict__ out,
-                                                      double *__restrict__ pc, int n, int64_t inner,
-                                                      int npad, const __hip_bfloat16 *__restrict__ Mhi,
-                                                      const __hip_bfloat16 *__restrict__ Mlo,
-                                                      const int *__restrict__ klo,
-                                                      const int *__restrict__ knc,
-                                                      unsigned long long *slots) {
-  extern __shared__ __hip_bfloat16 T[];   // hi: [kIT][npad + 8], then lo
-  const int ld = npad + 8;
-  __hip_bfloat16 *Thi = T, *Tlo = T + kIT * ld;
-  const int64_t o = blockIdx.y;
-  const int64_t i0 = (int64_t)blockIdx.x * kIT;
-  // staging: kStage loads per thread in flight before the first wait
-  for (int e0 = 0; e0 < npad * kIT; e0 += 256 * kStage) {
-    float v[kStage];
-#pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = e0 + threadIdx.x + 256 * r;
-      const int j = e / kIT, ii = e - j * kIT;
-      v[r] = (e < npad * kIT && j < n && i0 + ii < inner) ? in[(o * n + j) * inner + i0 + ii] : 0.f;
-    }
-#pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = e0 + threadIdx.x + 256 * r;
-      const int j = e / kIT, ii = e - j * kIT;
-      if (e < npad * kIT) split_bf16(v[r], Thi[ii * ld + j], Tlo[ii * ld + j]);
-    }
-  }
-  __syncthreads();
+__device__ __forceinline__ void strided_apply(const __hip_bfloat16 *Thi, const __hip_bfloat16 *Tlo, int ld,
+                                              float *__restrict__ out, double *__restrict__ pc, int n,
+                                              int64_t inner, int npad, int64_t o, int64_t i0,
+                                              const __hip_bfloat16 *__restrict__ Mhi,
+                                              const __hip_bfloat16 *__restrict__ Mlo,
+                                              const int *__restrict__ klo, const int *__restrict__ knc,
+                                              double &dmax) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   const int ntiles = (n + 15) >> 4;
-  double dmax = 0.0;
   for (int t = w; t < ntiles; t += 4) {
     floatx4 acc[kIT / 16];
 #pragma unroll
@@ -155,6 +133,46 @@ __global__ void __launch_bounds__(256) k_mfma_strided(const float *__restrict__ 
       }
     }
   }
+}
+
+// Strided axis: the array is [outer][n][inner] (FP32); workgroup = (one outer
+// index, kIT columns of inner), all n output rows.  IN[:, i0:i0+kIT] is staged
+// in LDS transposed and split (Thi/Tlo[i][j], j contiguous) so a B fragment is
+// one 16-byte LDS read.  Wave w computes row tiles w, w+4, ...; MODE 0 stores
+// FP32, MODE 1 adds into the float64 control points and reduces max |corr|.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_mfma_strided(const float *__restrict__ in,
+                                                      float *__restrict__ out,
+                                                      double *__restrict__ pc, int n, int64_t inner,
+                                                      int npad, const __hip_bfloat16 *__restrict__ Mhi,
+                                                      const __hip_bfloat16 *__restrict__ Mlo,
+                                                      const int *__restrict__ klo,
+                                                      const int *__restrict__ knc,
+                                                      unsigned long long *slots) {
+  extern __shared__ __hip_bfloat16 T[];   // hi: [kIT][npad + 8], then lo
+  const int ld = npad + 8;
+  __hip_bfloat16 *Thi = T, *Tlo = T + kIT * ld;
+  const int64_t o = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * kIT;
+  // staging: kStage loads per thread in flight before the first wait
+  for (int e0 = 0; e0 < npad * kIT; e0 += 256 * kStage) {
+    float v[kStage];
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = e0 + threadIdx.x + 256 * r;
+      const int j = e / kIT, ii = e - j * kIT;
+      v[r] = (e < npad * kIT && j < n && i0 + ii < inner) ? in[(o * n + j) * inner + i0 + ii] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = e0 + threadIdx.x + 256 * r;
+      const int j = e / kIT, ii = e - j * kIT;
+      if (e < npad * kIT) split_bf16(v[r], Thi[ii * ld + j], Tlo[ii * ld + j]);
+    }
+  }
+  __syncthreads();
+  double dmax = 0.0;
+  strided_apply<MODE>(Thi, Tlo, ld, out, pc, n, inner, npad, o, i0, Mhi, Mlo, klo, knc, dmax);
   if (MODE == 1) slot_max_m(slots, kSlotMaxDP, dmax);
 }
 
@@ -240,6 +258,92 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
   if (MODE == 1) slot_max_m(slots, kSlotMaxDP, dmax);
 }
 
+// Axes 2 and 1 of the correction in one pass (mode 0): a workgroup takes one
+// x-plane o and a block of kIT outputs k2.  Phase 1 applies M_2 to the
+// plane's lines, 32 at a time (staged split in LDS, only the columns the two
+// output tiles need), and keeps the result split in LDS, transposed as the
+// strided pass stages its input; phase 2 is that strided pass along axis 1.
+// Every output takes the same MFMA sequence as the two separate passes, so
+// the result is the same; the intermediate never goes through HBM.
+__global__ void __launch_bounds__(256) k_mfma_fused21(const float *__restrict__ in, float *__restrict__ out,
+                                                      int n1, int n2, int npad1, int npad2,
+                                                      const __hip_bfloat16 *__restrict__ M1hi,
+                                                      const __hip_bfloat16 *__restrict__ M1lo,
+                                                      const int *__restrict__ klo1,
+                                                      const int *__restrict__ knc1,
+                                                      const __hip_bfloat16 *__restrict__ M2hi,
+                                                      const __hip_bfloat16 *__restrict__ M2lo,
+                                                      const int *__restrict__ klo2,
+                                                      const int *__restrict__ knc2, int ldw) {
+  extern __shared__ __hip_bfloat16 S[];
+  const int ld1 = npad1 + 8;
+  __hip_bfloat16 *Thi = S, *Tlo = S + kIT * ld1;       // [kIT][ld1]: phase-2 operand
+  __hip_bfloat16 *Lhi = S + 2 * kIT * ld1;             // [32 lines][ldw]: phase-1 staging
+  __hip_bfloat16 *Llo = Lhi + 32 * ldw;
+  const int64_t o = blockIdx.y;
+  const int K2a = blockIdx.x * kIT;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int ntiles2 = (n2 + 15) >> 4;
+  const int t2a = K2a >> 4;
+  const int nt2 = min(2, ntiles2 - t2a);
+  int jlo = klo2[t2a], jhi = klo2[t2a] + 32 * knc2[t2a];
+  if (nt2 > 1) {
+    jlo = min(jlo, klo2[t2a + 1]);
+    jhi = max(jhi, klo2[t2a + 1] + 32 * knc2[t2a + 1]);
+  }
+  const int jw = jhi - jlo;
+  // rows j1 in [n1, npad1) of the phase-2 operand are zero
+  for (int e = threadIdx.x; e < kIT * (npad1 - n1); e += 256) {
+    const int ii = e / (npad1 - n1), j = n1 + e % (npad1 - n1);
+    Thi[ii * ld1 + j] = __float2bfloat16(0.0f);
+    Tlo[ii * ld1 + j] = __float2bfloat16(0.0f);
+  }
+  const float *plane = in + o * (int64_t)n1 * n2;
+  for (int l0 = 0; l0 < n1; l0 += 32) {
+    __syncthreads();   // the previous chunk's staging is consumed
+    for (int e0 = 0; e0 < 32 * jw; e0 += 256 * kStage) {
+      float v[kStage];
+#pragma unroll
+      for (int r = 0; r < kStage; ++r) {
+        const int e = e0 + threadIdx.x + 256 * r;
+        const int li = e / jw, jj = e - li * jw;
+        const int j = jlo + jj;
+        v[r] = (e < 32 * jw && l0 + li < n1 && j < n2) ? plane[(int64_t)(l0 + li) * n2 + j] : 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < kStage; ++r) {
+        const int e = e0 + threadIdx.x + 256 * r;
+        const int li = e / jw, jj = e - li * jw;
+        if (e < 32 * jw) split_bf16(v[r], Lhi[li * ldw + jj], Llo[li * ldw + jj]);
+      }
+    }
+    __syncthreads();
+    // wave w: output tile t2a + (w & 1), lines 16*(w >> 1) .. +15 of the chunk
+    if ((w & 1) < nt2) {
+      const int t = t2a + (w & 1), lb = w >> 1;
+      floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+      const int lo = klo2[t], nc = knc2[t];
+      const int64_t moff = (int64_t)(16 * t + r16) * npad2 + 8 * kq;
+      const int aoff = (16 * lb + r16) * ldw + 8 * kq - jlo;
+      for (int c = 0; c < nc; ++c) {
+        const int j0 = lo + 32 * c;
+        acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), load8(M2hi + moff + j0),
+                    load8(M2lo + moff + j0), acc);
+      }
+      const int ii = 16 * (w & 1) + r16;   // output k2 - K2a
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j1 = l0 + 16 * lb + 4 * kq + v;
+        if (j1 < n1) split_bf16(acc[v], Thi[ii * ld1 + j1], Tlo[ii * ld1 + j1]);
+      }
+    }
+  }
+  __syncthreads();
+  double dmax = 0.0;
+  strided_apply<0>(Thi, Tlo, ld1, out, nullptr, n1, n2, npad1, o, K2a, M1hi, M1lo, klo1, knc1, dmax);
+}
+
 // dense split-BF16 copy of M_a (rows padded to a multiple of 16 with zeros,
 // columns to npad) from its float64 row table
 __global__ void k_tab_Mbf16(int n, int nrows, int npad, Ell M, __hip_bfloat16 *Mhi,
@@ -301,6 +405,64 @@ hipError_t setup_mfma(Handle *h, int ia, hipStream_t st) {
   __hip_bfloat16 *Mlo = Mhi + (int64_t)nrows * X.npad;
   k_tab_Mbf16<<<nrows, 128, 0, st>>>(X.n, nrows, X.npad, X.M, Mhi, Mlo);
   k_tab_ktiles<<<nblk((X.n + 15) / 16, 64), 64, 0, st>>>(X.n, X.M, X.d_klo, X.d_knc);
+  return hipGetLastError();
+}
+
+// Widest column range phase 1 of the fused pass stages for one block of kIT
+// outputs along axis 2 (two 16-row tiles of M_2), plus 8 of padding: the
+// host copy of the tile ranges k_tab_ktiles builds on the device (row k of
+// M spans the free sets of the blocks holding k: blo..bhi, or its owner).
+int fuse21_ldw(const Handle &h) {
+  const Axis &X = h.ax[2];
+  const int n = X.n, ntiles = (n + 15) / 16;
+  std::vector<int> lo(ntiles), hi(ntiles);
+  for (int t = 0; t < ntiles; ++t) {
+    int l = 1 << 30, u = 0;
+    for (int k = 16 * t; k < std::min(n, 16 * t + 16); ++k) {
+      int b0 = X.blo[k], b1 = X.bhi[k];
+      if (h.combine == MFA_COMBINE_RAS) b0 = b1 = X.owner[k];
+      l = std::min(l, X.blk[b0].F0);
+      u = std::max(u, X.blk[b1].F1);
+    }
+    l &= ~7;
+    lo[t] = l;
+    hi[t] = l + 32 * ((u - l + 31) / 32);
+  }
+  int w = 0;
+  for (int t = 0; t < ntiles; t += kIT / 16) {
+    int l = lo[t], u = hi[t];
+    if (t + 1 < ntiles) {
+      l = std::min(l, lo[t + 1]);
+      u = std::max(u, hi[t + 1]);
+    }
+    w = std::max(w, u - l);
+  }
+  return w > 0 ? w + 8 : 0;
+}
+
+// workgroup LDS of the fused axis-2/axis-1 pass and the widest staged column
+// range of phase 1 (two output tiles of M_2)
+static size_t fused21_lds(const Axis &X1, int ldw) {
+  return sizeof(__hip_bfloat16) * 2 * ((size_t)kIT * (X1.npad + 8) + 32 * (size_t)ldw);
+}
+
+bool mfma_fused21_ok(const Handle &h) {
+  return h.ax[1].active && h.ax[2].active && h.ax[2].n >= 16 && fuse21_ldw(h) > 0 &&
+         fused21_lds(h.ax[1], fuse21_ldw(h)) <= 64 * 1024;
+}
+
+hipError_t launch_mfma_fused21(Handle &h, const float *in, float *out) {
+  const Axis &X1 = h.ax[1], &X2 = h.ax[2];
+  const int nr1 = (X1.n + 15) / 16 * 16, nr2 = (X2.n + 15) / 16 * 16;
+  const __hip_bfloat16 *M1hi = reinterpret_cast<const __hip_bfloat16 *>(X1.d_Mb);
+  const __hip_bfloat16 *M1lo = M1hi + (int64_t)nr1 * X1.npad;
+  const __hip_bfloat16 *M2hi = reinterpret_cast<const __hip_bfloat16 *>(X2.d_Mb);
+  const __hip_bfloat16 *M2lo = M2hi + (int64_t)nr2 * X2.npad;
+  const int ldw = fuse21_ldw(h);
+  const dim3 grid(nblk(X2.n, kIT), (unsigned)h.ax[0].n);
+  k_mfma_fused21<<<grid, 256, fused21_lds(X1, ldw), h.stream>>>(
+      in, out, X1.n, X2.n, X1.npad, X2.npad, M1hi, M1lo, X1.d_klo, X1.d_knc, M2hi, M2lo, X2.d_klo,
+      X2.d_knc, ldw);
   return hipGetLastError();
 }
 

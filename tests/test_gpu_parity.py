@@ -289,3 +289,27 @@ def test_decode_points_match_oracle(name):
     assert f32.dtype == np.float32 and _rel(f32, f64) < 1e-6
     with pytest.raises(_lib.MfaError):
         enc.decode_points(ud, deriv=(p + 1,) * w.dim)
+
+
+@pytest.mark.parametrize("which", ["ragged", "full"])
+def test_fused_correction_equals_separate_passes(which, monkeypatch):
+    """The fused axis-2/axis-1 split-BF16 correction performs each output's
+    MFMA sequence and BF16 split exactly as the separate passes do, so sweeps
+    agree bitwise (a ragged shape with a partial last output block, and the
+    512x512x384 p=4 workload)."""
+    if which == "ragged":
+        w = W.small_3d(npts=(40, 48, 70), sizes=((8, 9), (10, 10), (17, 18)), p=4, overlap=2)
+        Q = _field(w)
+    else:
+        w = W.cfg_3d_mixed()
+        Q = W.make_field(w)
+    q = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    out = {}
+    for mode in ("fused", "separate"):
+        monkeypatch.setenv("MFA_UNFUSED_CORRECTION", "1" if mode == "separate" else "0")
+        enc = _enc(w, precision="mixed_bf16")
+        for k in range(3):
+            enc.step(q if k == 0 else None)
+        out[mode] = enc.get_ctrl().cpu().numpy()
+        enc.close()
+    assert np.array_equal(out["fused"], out["separate"])
