@@ -94,6 +94,20 @@ __device__ __forceinline__ void strided_apply(const __hip_bfloat16 *Thi, const _
         alo[c] = load8(Mlo + moff + lo + 32 * c);
       }
     }
+    // MODE 1: the control points this tile updates are requested before the
+    // products too
+    double pold[kIT / 16][4];
+    if (MODE == 1) {
+#pragma unroll
+      for (int s = 0; s < kIT / 16; ++s) {
+        const int64_t i = i0 + 16 * s + r16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = 16 * t + 4 * kq + v;
+          pold[s][v] = (k < n && i < inner) ? pc[(o * n + k) * inner + i] : 0.0;
+        }
+      }
+    }
 #pragma unroll
     for (int c = 0; c < kPre; ++c) {
       if (c < nc) {
@@ -126,7 +140,7 @@ __device__ __forceinline__ void strided_apply(const __hip_bfloat16 *Thi, const _
             out[idx] = acc[s][v];
           } else {
             const double d = (double)acc[s][v];
-            pc[idx] += d;
+            pc[idx] = pold[s][v] + d;
             dmax = fmax(dmax, fabs(d));
           }
         }
@@ -265,6 +279,11 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
 // strided pass stages its input; phase 2 is that strided pass along axis 1.
 // Every output takes the same MFMA sequence as the two separate passes, so
 // the result is the same; the intermediate never goes through HBM.
+// The grid is one-dimensional, nb2 blocks per plane: workgroups are dealt to
+// the 8 XCDs round-robin, and the renumbering gives each XCD a contiguous run
+// of planes, so the blocks of one plane (whose column ranges overlap) share an
+// L2.  The M_2 fragments of a wave's tile are loaded once; the next chunk of
+// lines is loaded into registers while the current one is multiplied.
 __global__ void __launch_bounds__(256) k_mfma_fused21(const float *__restrict__ in, float *__restrict__ out,
                                                       int n1, int n2, int npad1, int npad2,
                                                       const __hip_bfloat16 *__restrict__ M1hi,
@@ -274,14 +293,16 @@ __global__ void __launch_bounds__(256) k_mfma_fused21(const float *__restrict__ 
                                                       const __hip_bfloat16 *__restrict__ M2hi,
                                                       const __hip_bfloat16 *__restrict__ M2lo,
                                                       const int *__restrict__ klo2,
-                                                      const int *__restrict__ knc2, int ldw) {
+                                                      const int *__restrict__ knc2, int ldw, int nb2) {
   extern __shared__ __hip_bfloat16 S[];
   const int ld1 = npad1 + 8;
   __hip_bfloat16 *Thi = S, *Tlo = S + kIT * ld1;       // [kIT][ld1]: phase-2 operand
   __hip_bfloat16 *Lhi = S + 2 * kIT * ld1;             // [32 lines][ldw]: phase-1 staging
   __hip_bfloat16 *Llo = Lhi + 32 * ldw;
-  const int64_t o = blockIdx.y;
-  const int K2a = blockIdx.x * kIT;
+  const unsigned G = gridDim.x, xcd = blockIdx.x % 8, per = G / 8, rem = G % 8;
+  const unsigned lb = xcd * per + min(xcd, rem) + blockIdx.x / 8;
+  const int64_t o = lb / nb2;
+  const int K2a = (int)(lb % nb2) * kIT;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   const int ntiles2 = (n2 + 15) >> 4;
@@ -292,7 +313,20 @@ __global__ void __launch_bounds__(256) k_mfma_fused21(const float *__restrict__ 
     jlo = min(jlo, klo2[t2a + 1]);
     jhi = max(jhi, klo2[t2a + 1] + 32 * knc2[t2a + 1]);
   }
-  const int jw = jhi - jlo;
+  const int jw = jhi - jlo;   // 32 * jw <= 256 * kStage (checked on the host)
+  // wave w: output tile t2a + (w & 1), lines 16*(w >> 1) .. +15 of each chunk
+  const bool mine = (w & 1) < nt2;
+  const int t = t2a + (w & 1), lbk = w >> 1;
+  const int lo2 = mine ? klo2[t] : 0, nc2 = mine ? knc2[t] : 0;
+  const int64_t moff = (int64_t)(16 * t + r16) * npad2 + 8 * kq;
+  bf16x8 bhi[kPre], blo[kPre];
+#pragma unroll
+  for (int c = 0; c < kPre; ++c) {
+    if (c < nc2) {
+      bhi[c] = load8(M2hi + moff + lo2 + 32 * c);
+      blo[c] = load8(M2lo + moff + lo2 + 32 * c);
+    }
+  }
   // rows j1 in [n1, npad1) of the phase-2 operand are zero
   for (int e = threadIdx.x; e < kIT * (npad1 - n1); e += 256) {
     const int ii = e / (npad1 - n1), j = n1 + e % (npad1 - n1);
@@ -300,42 +334,46 @@ __global__ void __launch_bounds__(256) k_mfma_fused21(const float *__restrict__ 
     Tlo[ii * ld1 + j] = __float2bfloat16(0.0f);
   }
   const float *plane = in + o * (int64_t)n1 * n2;
+  float v[kStage];
+  auto fetch = [&](int l0) {
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = threadIdx.x + 256 * r;
+      const int li = e / jw, j = jlo + (e - li * jw);
+      v[r] = (e < 32 * jw && l0 + li < n1 && j < n2) ? plane[(int64_t)(l0 + li) * n2 + j] : 0.f;
+    }
+  };
+  fetch(0);
   for (int l0 = 0; l0 < n1; l0 += 32) {
     __syncthreads();   // the previous chunk's staging is consumed
-    for (int e0 = 0; e0 < 32 * jw; e0 += 256 * kStage) {
-      float v[kStage];
 #pragma unroll
-      for (int r = 0; r < kStage; ++r) {
-        const int e = e0 + threadIdx.x + 256 * r;
-        const int li = e / jw, jj = e - li * jw;
-        const int j = jlo + jj;
-        v[r] = (e < 32 * jw && l0 + li < n1 && j < n2) ? plane[(int64_t)(l0 + li) * n2 + j] : 0.f;
-      }
-#pragma unroll
-      for (int r = 0; r < kStage; ++r) {
-        const int e = e0 + threadIdx.x + 256 * r;
-        const int li = e / jw, jj = e - li * jw;
-        if (e < 32 * jw) split_bf16(v[r], Lhi[li * ldw + jj], Llo[li * ldw + jj]);
-      }
+    for (int r = 0; r < kStage; ++r) {
+      const int e = threadIdx.x + 256 * r;
+      const int li = e / jw, jj = e - li * jw;
+      if (e < 32 * jw) split_bf16(v[r], Lhi[li * ldw + jj], Llo[li * ldw + jj]);
     }
     __syncthreads();
-    // wave w: output tile t2a + (w & 1), lines 16*(w >> 1) .. +15 of the chunk
-    if ((w & 1) < nt2) {
-      const int t = t2a + (w & 1), lb = w >> 1;
+    if (l0 + 32 < n1) fetch(l0 + 32);
+    if (mine) {
       floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-      const int lo = klo2[t], nc = knc2[t];
-      const int64_t moff = (int64_t)(16 * t + r16) * npad2 + 8 * kq;
-      const int aoff = (16 * lb + r16) * ldw + 8 * kq - jlo;
-      for (int c = 0; c < nc; ++c) {
-        const int j0 = lo + 32 * c;
+      const int aoff = (16 * lbk + r16) * ldw + 8 * kq - jlo;
+#pragma unroll
+      for (int c = 0; c < kPre; ++c) {
+        if (c < nc2) {
+          const int j0 = lo2 + 32 * c;
+          acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), bhi[c], blo[c], acc);
+        }
+      }
+      for (int c = kPre; c < nc2; ++c) {
+        const int j0 = lo2 + 32 * c;
         acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), load8(M2hi + moff + j0),
                     load8(M2lo + moff + j0), acc);
       }
       const int ii = 16 * (w & 1) + r16;   // output k2 - K2a
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j1 = l0 + 16 * lb + 4 * kq + v;
-        if (j1 < n1) split_bf16(acc[v], Thi[ii * ld1 + j1], Tlo[ii * ld1 + j1]);
+      for (int q = 0; q < 4; ++q) {
+        const int j1 = l0 + 16 * lbk + 4 * kq + q;
+        if (j1 < n1) split_bf16(acc[q], Thi[ii * ld1 + j1], Tlo[ii * ld1 + j1]);
       }
     }
   }
@@ -447,8 +485,10 @@ static size_t fused21_lds(const Axis &X1, int ldw) {
 }
 
 bool mfma_fused21_ok(const Handle &h) {
-  return h.ax[1].active && h.ax[2].active && h.ax[2].n >= 16 && fuse21_ldw(h) > 0 &&
-         fused21_lds(h.ax[1], fuse21_ldw(h)) <= 64 * 1024;
+  const int ldw = fuse21_ldw(h);
+  return h.ax[1].active && h.ax[2].active && h.ax[2].n >= 16 && ldw > 0 &&
+         32 * (ldw - 8) <= 256 * kStage && fused21_lds(h.ax[1], ldw) <= 64 * 1024 &&
+         (int64_t)h.ax[0].n * nblk(h.ax[2].n, kIT) < (1ll << 31);
 }
 
 hipError_t launch_mfma_fused21(Handle &h, const float *in, float *out) {
@@ -459,10 +499,10 @@ hipError_t launch_mfma_fused21(Handle &h, const float *in, float *out) {
   const __hip_bfloat16 *M2hi = reinterpret_cast<const __hip_bfloat16 *>(X2.d_Mb);
   const __hip_bfloat16 *M2lo = M2hi + (int64_t)nr2 * X2.npad;
   const int ldw = fuse21_ldw(h);
-  const dim3 grid(nblk(X2.n, kIT), (unsigned)h.ax[0].n);
-  k_mfma_fused21<<<grid, 256, fused21_lds(X1, ldw), h.stream>>>(
+  const unsigned nb2 = nblk(X2.n, kIT);
+  k_mfma_fused21<<<nb2 * (unsigned)h.ax[0].n, 256, fused21_lds(X1, ldw), h.stream>>>(
       in, out, X1.n, X2.n, X1.npad, X2.npad, M1hi, M1lo, X1.d_klo, X1.d_knc, M2hi, M2lo, X2.d_klo,
-      X2.d_knc, ldw);
+      X2.d_knc, ldw, (int)nb2);
   return hipGetLastError();
 }
 
