@@ -83,33 +83,56 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
 #pragma unroll
     for (int r = 0; r < kRY; ++r) ring[t][r] = 0.0;
   double nres = 0.0;
+  // Plane-invariant gathers: every thread's tile elements and right-hand-side
+  // entries as 32-bit offsets within a plane (clamped to 0 where outside the
+  // array, the value then replaced by 0), so a plane's loads are one address
+  // add each and carry no branches.
+  constexpr int NE = (LY * LZ + kRT - 1) / kRT;
+  const int64_t plane = (int64_t)n1 * n2;
+  int toff[NE];
+  unsigned tmask = 0;
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int e = threadIdx.x + kRT * i;
+    const int yy = e / LZ, zz = e - yy * LZ;
+    const int gy = y0 - P + yy, gzz = z0 - P + zz;
+    const bool ok = e < LY * LZ && gy >= 0 && gy < n1 && gzz >= 0 && gzz < n2;
+    toff[i] = ok ? gy * n2 + gzz : 0;
+    tmask |= (unsigned)ok << i;
+  }
+  int coff[kRY];
+  unsigned cmask = 0;
+#pragma unroll
+  for (int r = 0; r < kRY; ++r) {
+    const int gy = y0 + ty * kRY + r;
+    const bool ok = gy < n1 && gz < n2;
+    coff[r] = ok ? gy * n2 + gz : 0;
+    cmask |= (unsigned)ok << r;
+  }
   // the tile of the next plane is loaded into registers while the current
   // plane is computed (software pipelining of the global loads)
-  constexpr int NE = (LY * LZ + kRT - 1) / kRT;
+  // The loads are unconditional (in-bounds addresses) and the zero fill of
+  // out-of-range entries happens where the values are used, so no load is
+  // followed by an early wait.
   double pre[NE];
+  bool pre_in = false;   // the plane held in pre[] lies inside the array
   auto gload = [&](int xi) {
-    const bool xin = xi >= 0 && xi < n0;
+    pre_in = xi >= 0 && xi < n0;
+    const double *base = Pc + (pre_in ? xi : 0) * plane;
 #pragma unroll
-    for (int i = 0; i < NE; ++i) {
-      const int e = threadIdx.x + kRT * i;
-      const int yy = e / LZ, zz = e - yy * LZ;
-      const int gy = y0 - P + yy, gzz = z0 - P + zz;
-      double v = 0.0;
-      if (e < LY * LZ && xin && gy >= 0 && gy < n1 && gzz >= 0 && gzz < n2)
-        v = Pc[((int64_t)xi * n1 + gy) * n2 + gzz];
-      pre[i] = v;
-    }
+    for (int i = 0; i < NE; ++i) pre[i] = base[toff[i]];
   };
   gload(x0 - P);
   for (int xi = x0 - P; xi < x1 + P; ++xi) {
     const int xo = xi - P;
     const bool out_plane = xo >= x0 && xo < x1;
-    // the right-hand side of the plane completed in this iteration
-    double cv[kRY];
+    // axis-0 stencil row of the output plane (scalar loads, covered by the
+    // barrier's wait)
+    double axv[W];
+    {
+      const double *ax = A0 + (int64_t)(out_plane ? xo : 0) * W;
 #pragma unroll
-    for (int r = 0; r < kRY; ++r) {
-      const int gy = y0 + ty * kRY + r;
-      cv[r] = (out_plane && gy < n1 && gz < n2) ? c[((int64_t)xo * n1 + gy) * n2 + gz] : 0.0;
+      for (int t = 0; t < W; ++t) axv[t] = ax[t];
     }
     __syncthreads();
 #pragma unroll
@@ -117,11 +140,22 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
       const int e = threadIdx.x + kRT * i;
       if (e < LY * LZ) {
         const int yy = e / LZ, zz = e - yy * LZ;
-        tile[yy][zz] = pre[i];
+        tile[yy][zz] = (pre_in && ((tmask >> i) & 1)) ? pre[i] : 0.0;
       }
     }
+    // the right-hand side of the plane completed in this iteration, requested
+    // after the wait for the tile (loads return in order) and before the next
+    // plane's tile, so that neither wait covers the other
+    double cv[kRY];
+    {
+      const double *cb = c + (out_plane ? xo : 0) * plane;
+#pragma unroll
+      for (int r = 0; r < kRY; ++r) cv[r] = cb[coff[r]];
+    }
     __syncthreads();
-    if (xi + 1 < x1 + P) gload(xi + 1);
+    // unconditional (past the last plane it reads in-bounds data it never
+    // uses): a branch here would make the wait for cv[] cover these loads
+    gload(xi + 1);
     for (int yy = ty; yy < LY; yy += kRT / 64) {
       double s = 0.0;
 #pragma unroll
@@ -141,15 +175,13 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
       ring[W - 1][r] = s;
     }
     if (out_plane) {
-      const double *ax = A0 + (int64_t)xo * W;
 #pragma unroll
       for (int r = 0; r < kRY; ++r) {
-        const int gy = y0 + ty * kRY + r;
-        if (gy < n1 && gz < n2) {
+        if ((cmask >> r) & 1) {
           double s = 0.0;
 #pragma unroll
-          for (int t = 0; t < W; ++t) s += ax[t] * ring[t][r];
-          const int64_t idx = ((int64_t)xo * n1 + gy) * n2 + gz;
+          for (int t = 0; t < W; ++t) s += axv[t] * ring[t][r];
+          const int64_t idx = xo * plane + coff[r];
           const double gv = cv[r] - s;
           g[idx] = from_d<TG>(gv);
           nres = fmax(nres, fabs(gv));
@@ -466,6 +498,8 @@ template <int P, typename TG>
 hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG *g, const double *A0,
                           const double *A1, const double *A2, int n0, int n1, int n2,
                           unsigned long long *slots) {
+  // the kernel addresses within a plane with 32-bit offsets
+  if ((int64_t)n1 * n2 > INT32_MAX) return hipErrorInvalidValue;
   const int byz = (int)(nblk(n2, kTZ) * nblk(n1, kTY));
   const ResidKey key{n0, n1, n2, P, (int)sizeof(TG)};
   int xchunk = 0;
