@@ -109,21 +109,22 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
     coff[r] = ok ? gy * n2 + gz : 0;
     cmask |= (unsigned)ok << r;
   }
-  // the tile of the next plane is loaded into registers while the current
-  // plane is computed (software pipelining of the global loads)
-  // The loads are unconditional (in-bounds addresses) and the zero fill of
-  // out-of-range entries happens where the values are used, so no load is
-  // followed by an early wait.
-  double pre[NE];
-  bool pre_in = false;   // the plane held in pre[] lies inside the array
-  auto gload = [&](int xi) {
-    pre_in = xi >= 0 && xi < n0;
-    const double *base = Pc + (pre_in ? xi : 0) * plane;
+  // The tiles of the next two planes are in flight in registers while the
+  // current plane is computed (software pipelining of the global loads, two
+  // buffers, the loop unrolled by two).  The loads are unconditional
+  // (in-bounds addresses) and the zero fill of out-of-range entries happens
+  // where the values are used, so no load is followed by an early wait; the
+  // plane count is rounded up to even so that no branch separates a load from
+  // its wait (the extra plane writes nothing).
+  double preA[NE], preB[NE];
+  bool inA = false, inB = false;   // the plane held in the buffer lies inside the array
+  auto gload = [&](double (&buf)[NE], bool &bin, int xi) {
+    bin = xi >= 0 && xi < n0;
+    const double *base = Pc + (bin ? xi : 0) * plane;
 #pragma unroll
-    for (int i = 0; i < NE; ++i) pre[i] = base[toff[i]];
+    for (int i = 0; i < NE; ++i) buf[i] = base[toff[i]];
   };
-  gload(x0 - P);
-  for (int xi = x0 - P; xi < x1 + P; ++xi) {
+  auto step = [&](double (&buf)[NE], bool &bin, int xi) {
     const int xo = xi - P;
     const bool out_plane = xo >= x0 && xo < x1;
     // axis-0 stencil row of the output plane (scalar loads, covered by the
@@ -140,12 +141,12 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
       const int e = threadIdx.x + kRT * i;
       if (e < LY * LZ) {
         const int yy = e / LZ, zz = e - yy * LZ;
-        tile[yy][zz] = (pre_in && ((tmask >> i) & 1)) ? pre[i] : 0.0;
+        tile[yy][zz] = (bin && ((tmask >> i) & 1)) ? buf[i] : 0.0;
       }
     }
-    // the right-hand side of the plane completed in this iteration, requested
-    // after the wait for the tile (loads return in order) and before the next
-    // plane's tile, so that neither wait covers the other
+    // the right-hand side of the plane completed in this step, requested
+    // after the wait for the tile (loads return in order) and before the
+    // tile two planes ahead, so that neither wait covers the other
     double cv[kRY];
     {
       const double *cb = c + (out_plane ? xo : 0) * plane;
@@ -153,9 +154,7 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
       for (int r = 0; r < kRY; ++r) cv[r] = cb[coff[r]];
     }
     __syncthreads();
-    // unconditional (past the last plane it reads in-bounds data it never
-    // uses): a branch here would make the wait for cv[] cover these loads
-    gload(xi + 1);
+    gload(buf, bin, xi + 2);
     for (int yy = ty; yy < LY; yy += kRT / 64) {
       double s = 0.0;
 #pragma unroll
@@ -188,6 +187,15 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
         }
       }
     }
+  };
+  const int xs = x0 - P, npl = (x1 + P - xs + 1) & ~1;
+  gload(preA, inA, xs);
+  // keep A's loads ahead of B's: the waits count loads in issue order
+  asm volatile("" ::: "memory");
+  gload(preB, inB, xs + 1);
+  for (int xi = xs; xi < xs + npl; xi += 2) {
+    step(preA, inA, xi);
+    step(preB, inB, xi + 1);
   }
   slot_max_c(slots, kSlotNres, nres);
 }
