@@ -54,7 +54,6 @@ struct OmTab {
 // point ic of axis c evaluates sum_kc Om_c[ic][kc] V_i[kc] for all i of the
 // group (one read of the Om_c row serves jb outputs); max |.| goes to slot
 // (a, row % p).  Om rows are contiguous column ranges.
-constexpr int kJB = 16;
 template <int JB>
 __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ U, int R,
                                                      int64_t sr, int64_t sb, int64_t sc, OmTab Ob,
@@ -347,17 +346,33 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
 // points' last p values along axis 0 in registers for the axis-0
 // coefficients, which lag p-1 planes behind (the planes past the chunk are
 // read as halo, those past the grid as zeros that no coefficient uses).
+// The next two planes are in flight in registers while one is processed (two
+// buffers, the plane loop unrolled by two and its count rounded up to even;
+// unconditional in-bounds loads, zero fill where the values are used).  The
+// axis-1 coefficient rows of the tile sit in LDS.
 template <int PP>
 __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restrict__ P, int n0, int n1,
                                                            int n2, int K0C, DTab d0, DTab d1, DTab d2,
                                                            int act0, int act1, int act2,
                                                            unsigned long long *slots) {
   constexpr int TX = 64, TY = 16, RY = 4, H = PP - 1;
-  __shared__ double tile[TY + H][TX + H + 1];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  constexpr int LYY = TY + H, LXX = TX + H;
+  constexpr int NT = (LYY * LXX + 255) / 256;
+  __shared__ double tile[LYY][LXX + 1];
+  __shared__ double sd1[TY][PP][PP];   // axis-1 rows: sd1[k1 - k1a][r][q]
+  const int tx = threadIdx.x & 63;
+  const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int k2a = blockIdx.x * TX, k1a = blockIdx.y * TY;
   const int k0a = blockIdx.z * K0C, k0b = min(n0, k0a + K0C);
   const int k2 = k2a + tx;
+  const int64_t plane = (int64_t)n1 * n2;
+  for (int e = threadIdx.x; e < TY * PP * PP; e += 256) {
+    const int yl = e / (PP * PP), r = (e / PP) % PP, q = e % PP;
+    const int k1 = k1a + yl;
+    int rowoff = 0;
+    for (int rr = 0; rr < r; ++rr) rowoff += n1 - rr;
+    sd1[yl][r][q] = (act1 && q <= r && k1 <= n1 - 1 - r) ? d1.val[(int64_t)(rowoff + k1) * d1.L + q] : 0.0;
+  }
   // this thread's axis-2 coefficient rows (fixed k2)
   double dv2[PP][PP];
   {
@@ -370,6 +385,18 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
       rowoff += n2 - r;
     }
   }
+  // plane-invariant tile gathers: offsets within a plane and validity
+  int toff[NT];
+  unsigned tmask = 0;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int r = e / LXX, c = e - r * LXX;
+    const int k1 = k1a + r, kk2 = k2a + c;
+    const bool ok = e < LYY * LXX && k1 < n1 && kk2 < n2;
+    toff[u] = ok ? k1 * n2 + kk2 : 0;
+    tmask |= (unsigned)ok << u;
+  }
   double win[RY][PP];
   double mx[3][PP];
 #pragma unroll
@@ -381,30 +408,40 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
 #pragma unroll
     for (int r = 0; r < PP; ++r) mx[a][r] = 0.0;
 
-  for (int k0 = k0a; k0 < k0b + H; ++k0) {
-    __syncthreads();
+  double bufA[NT], bufB[NT];
+  bool inA = false, inB = false;
+  auto gload = [&](double (&buf)[NT], bool &bin, int k0) {
+    bin = k0 < n0;
+    const double *base = P + (bin ? k0 : 0) * plane;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) buf[u] = base[toff[u]];
+  };
+  auto step = [&](double (&buf)[NT], bool &bin, int k0) {
+    // axis-0 rows of the plane whose window completes here (uniform)
+    const int idx = k0 - H;
+    const bool do0 = act0 && idx >= k0a && idx < k0b;
+    double dv0[PP][PP];
     {
-      constexpr int NT = ((TY + H) * (TX + H) + 255) / 256;
-      double v[NT];
+      int rowoff = 0;
 #pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        const int e = threadIdx.x + 256 * u;
-        const int r = e / (TX + H), c = e - r * (TX + H);
-        const int k1 = k1a + r, kk2 = k2a + c;
-        v[u] = (e < (TY + H) * (TX + H) && k0 < n0 && k1 < n1 && kk2 < n2)
-                   ? P[((int64_t)k0 * n1 + k1) * n2 + kk2]
-                   : 0.0;
-      }
+      for (int r = 0; r < PP; ++r) {
+        const bool okr = do0 && idx <= n0 - 1 - r;
+        const double *dv = d0.val + (int64_t)(rowoff + (okr ? idx : 0)) * d0.L;
 #pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        const int e = threadIdx.x + 256 * u;
-        const int r = e / (TX + H), c = e - r * (TX + H);
-        if (e < (TY + H) * (TX + H)) tile[r][c] = v[u];
+        for (int q = 0; q <= r; ++q) dv0[r][q] = okr ? dv[q] : 0.0;
+        rowoff += n0 - r;
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int r = e / LXX, c = e - r * LXX;
+      if (e < LYY * LXX) tile[r][c] = (bin && ((tmask >> u) & 1)) ? buf[u] : 0.0;
+    }
+    __syncthreads();
+    gload(buf, bin, k0 + 2);
     const bool own = k0 < k0b;
-    const int idx = k0 - H;   // axis-0 index whose window is complete
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       const int ly = ty + 4 * j, k1 = k1a + ly;
@@ -425,34 +462,37 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
         }
       }
       if (own && act1) {
-        int rowoff = 0;
 #pragma unroll
         for (int r = 0; r < PP; ++r) {
           if (k1 <= n1 - 1 - r) {
-            const double *dv = d1.val + (int64_t)(rowoff + k1) * d1.L;
             double sum = 0.0;
 #pragma unroll
-            for (int q = 0; q <= r; ++q) sum += dv[q] * tile[ly + q][tx];
+            for (int q = 0; q <= r; ++q) sum += sd1[ly][r][q] * tile[ly + q][tx];
             mx[1][r] = fmax(mx[1][r], fabs(sum));
           }
-          rowoff += n1 - r;
         }
       }
-      if (act0 && idx >= k0a && idx < k0b) {
-        int rowoff = 0;
+      if (do0) {
 #pragma unroll
         for (int r = 0; r < PP; ++r) {
           if (idx <= n0 - 1 - r) {
-            const double *dv = d0.val + (int64_t)(rowoff + idx) * d0.L;
             double sum = 0.0;
 #pragma unroll
-            for (int q = 0; q <= r; ++q) sum += dv[q] * win[j][q];
+            for (int q = 0; q <= r; ++q) sum += dv0[r][q] * win[j][q];
             mx[0][r] = fmax(mx[0][r], fabs(sum));
           }
-          rowoff += n0 - r;
         }
       }
     }
+  };
+  const int npl = (k0b + H - k0a + 1) & ~1;
+  gload(bufA, inA, k0a);
+  // keep A's loads ahead of B's: the waits count loads in issue order
+  asm volatile("" ::: "memory");
+  gload(bufB, inB, k0a + 1);
+  for (int k0 = k0a; k0 < k0a + npl; k0 += 2) {
+    step(bufA, inA, k0);
+    step(bufB, inB, k0 + 1);
   }
   const int act[3] = {act0, act1, act2};
 #pragma unroll
@@ -570,15 +610,16 @@ hipError_t launch_jump_expand(Handle &h, int a, const double *U) {
     has_c = 1;
     nc = h.ax[oth[1]].n;
   }
-  const int jb = nc <= 384 ? 16 : (nc <= 768 ? 8 : (nc <= 1536 ? 4 : 1));
+  // data points per workgroup: 8 (of 4, 8, 16 the fastest on a 256 x 256 x
+  // 192 grid: more workgroups, all resident at once), fewer for long rows
+  const int jb = nc <= 768 ? 8 : (nc <= 1536 ? 4 : 1);
   const unsigned grid = (unsigned)((int64_t)R * ((Ob.m + jb - 1) / jb));
   const size_t lds = sizeof(double) * jb * (nc + Ob.L) + sizeof(int) * 2 * jb;
   if (lds > 64 * 1024) return hipErrorInvalidValue;
 #define MFA_JE(JB)                                                                                  \
   k_jump_expand<JB><<<grid, 256, lds, h.stream>>>(U, R, st[a], st[oth[0]], sc, Ob, Oc, has_c, h.p, \
                                                  kSlotJ + a * kMaxP, h.slots)
-  if (jb == 16) MFA_JE(16);
-  else if (jb == 8) MFA_JE(8);
+  if (jb == 8) MFA_JE(8);
   else if (jb == 4) MFA_JE(4);
   else MFA_JE(1);
 #undef MFA_JE

@@ -283,8 +283,10 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
 // the 8 XCDs round-robin, and the renumbering gives each XCD a contiguous run
 // of planes, so the blocks of one plane (whose column ranges overlap) share an
 // L2.  The M_2 fragments of a wave's tile are loaded once; the next chunk of
-// lines is loaded into registers while the current one is multiplied.
-__global__ void __launch_bounds__(256) k_mfma_fused21(const float *__restrict__ in, float *__restrict__ out,
+// lines is loaded into registers while the current one is multiplied.  At
+// most 168 registers per lane (three waves per SIMD, as many workgroups per CU
+// as the LDS holds).
+__global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict__ in, float *__restrict__ out,
                                                       int n1, int n2, int npad1, int npad2,
                                                       const __hip_bfloat16 *__restrict__ M1hi,
                                                       const __hip_bfloat16 *__restrict__ M1lo,
