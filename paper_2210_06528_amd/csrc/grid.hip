@@ -24,6 +24,7 @@ namespace {
 
 __device__ __forceinline__ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+
 // span(i) = min(n-1, p + floor(i (n-p) / (m-1))): the first point whose span
 // is >= s, and the last point whose span is <= s.
 __device__ __forceinline__ int64_t first_span_ge(int s, int64_t m, int n, int p) {
@@ -52,7 +53,7 @@ struct Rows {
 // staged in LDS; each thread contracts them along axis 2 for its k2 with its
 // N_2^T row held in registers (NTR values at most), then folds the result
 // into the p+1 open k1 rows.
-template <typename TQ, int P, int RI, int NTR>
+template <typename TQ, int P, int RI, int NTR, int NCW>
 __global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, double *__restrict__ out,
                                                     int64_t m1, int64_t m2, int n1, int n2, int K1C,
                                                     Rows r1, const int *__restrict__ nt2col,
@@ -101,13 +102,31 @@ __global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, do
   int cur = ss[0];
   double *dst = out + (i0 * n1) * (int64_t)n2 + k2;
 
+  // The next group of RI rows (W <= NCW * BS columns) is loaded into
+  // registers while the current one is contracted; the loads use clamped
+  // in-bounds indices and carry no branches (rows past the group and columns
+  // past W are never stored or read).
+  TQ pre[RI][NCW];
+  auto fetch = [&](int64_t g) {
+    const int nr = (int)min((int64_t)RI, r_hi - g);
+    const TQ *src = Q + (i0 * m1 + g) * m2 + c_lo;
+#pragma unroll
+    for (int rr = 0; rr < RI; ++rr)
+#pragma unroll
+      for (int cw = 0; cw < NCW; ++cw)
+        pre[rr][cw] = src[(int64_t)min(rr, nr - 1) * m2 + min(tid + cw * BS, W - 1)];
+  };
+  fetch(r_lo);
   for (int64_t g = r_lo; g < r_hi; g += RI) {
     const int nr = (int)min((int64_t)RI, r_hi - g);
     __syncthreads();   // the previous group's rows have been consumed
-    const TQ *src = Q + (i0 * m1 + g) * m2 + c_lo;
-    for (int rr = 0; rr < nr; ++rr)
-      for (int c = tid; c < W; c += BS) rows[rr * W + c] = src[(int64_t)rr * m2 + c];
+#pragma unroll
+    for (int rr = 0; rr < RI; ++rr)
+#pragma unroll
+      for (int cw = 0; cw < NCW; ++cw)
+        if (rr < nr && tid + cw * BS < W) rows[rr * W + tid + cw * BS] = pre[rr][cw];
     __syncthreads();
+    fetch(min(g + RI, r_hi - 1));
     for (int rr = 0; rr < nr; ++rr) {
       const int64_t i1 = g + rr;
       double v = 0.0;
@@ -282,21 +301,27 @@ __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in
   int cur = ss[0];
   double win[P + 1];
 #pragma unroll
-  for (int q = 0; q <= P; ++q) win[q] = actk ? slab[(int64_t)(cur - P + q) * n2] : 0.0;
-  double nxt = (actk && cur + 1 < n1) ? slab[(int64_t)(cur + 1) * n2] : 0.0;
+  for (int q = 0; q <= P; ++q) win[q] = slab[(int64_t)(cur - P + q) * n2];
   TO *dst = out + i0 * m1 * m2;
 
   for (int64_t g = I1a; g < I1b; g += RI) {
     const int nr = (int)min((int64_t)RI, I1b - g);
+    // the group's rows advance the span at most nr <= RI times: control rows
+    // cur+1 .. cur+RI of this column (clamped to the grid, the excess never
+    // used) are requested together, one wait per group
+    double nx[RI];
+#pragma unroll
+    for (int u = 0; u < RI; ++u) nx[u] = slab[(int64_t)min(cur + 1 + u, n1 - 1) * n2];
     for (int rr = 0; rr < nr; ++rr) {
       const int64_t i1 = g + rr;
       const int s = ss[i1 - I1a];
       if (s != cur) {
 #pragma unroll
         for (int q = 0; q < P; ++q) win[q] = win[q + 1];
-        win[P] = nxt;
+        win[P] = nx[0];
+#pragma unroll
+        for (int u = 0; u + 1 < RI; ++u) nx[u] = nx[u + 1];
         cur = s;
-        nxt = (actk && cur + 1 < n1) ? slab[(int64_t)(cur + 1) * n2] : 0.0;
       }
       const double *w = sw + (i1 - I1a) * (P + 1);
       double v = 0.0;
@@ -382,22 +407,32 @@ hipError_t project_p(Handle &h, const void *q, bool f32) {
   const Rows r1 = rows_of(X1, 0);
   const dim3 g1(nk1c * nk2c, (unsigned)m0);
   const int LT2 = X2.NT.L;
-#define MFA_PI(TQ, NTR)                                                                            \
-  k_proj_inner<TQ, P, kProjRI, NTR><<<g1, BS, lds, h.stream>>>(                                     \
+  // column slices per thread of a staged row (the register prefetch holds
+  // kProjRI x NCW values)
+  const int ncw = (int)((W + BS - 1) / BS);
+  if (ncw > 4) return hipErrorNotSupported;
+#define MFA_PI(TQ, NTR, NCW)                                                                       \
+  k_proj_inner<TQ, P, kProjRI, NTR, NCW><<<g1, BS, lds, h.stream>>>(                                \
       reinterpret_cast<const TQ *>(q), T, m1, m2, n1, n2, K1C, r1, X2.NT.col, X2.NT.len, X2.NT.val, \
       LT2, maxrows1)
+#define MFA_PI2(NTR)                                   \
+  if (ncw <= 2) {                                      \
+    if (f32) MFA_PI(float, NTR, 2);                    \
+    else MFA_PI(double, NTR, 2);                       \
+  } else {                                             \
+    if (f32) MFA_PI(float, NTR, 4);                    \
+    else MFA_PI(double, NTR, 4);                       \
+  }
   if (LT2 <= 12) {
-    if (f32) MFA_PI(float, 12);
-    else MFA_PI(double, 12);
+    MFA_PI2(12)
   } else if (LT2 <= 24) {
-    if (f32) MFA_PI(float, 24);
-    else MFA_PI(double, 24);
+    MFA_PI2(24)
   } else if (LT2 <= 48) {
-    if (f32) MFA_PI(float, 48);
-    else MFA_PI(double, 48);
+    MFA_PI2(48)
   } else {
     return hipErrorNotSupported;
   }
+#undef MFA_PI2
 #undef MFA_PI
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !outer) return e;
