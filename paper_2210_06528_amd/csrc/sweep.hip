@@ -154,7 +154,9 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
       for (int r = 0; r < kRY; ++r) cv[r] = cb[coff[r]];
     }
     __syncthreads();
-    gload(buf, bin, xi + 2);
+    // past the chunk's last plane the prefetch re-reads that plane (cache
+    // hits, never used) instead of the next chunk's planes
+    gload(buf, bin, min(xi + 2, x1 + P - 1));
     for (int yy = ty; yy < LY; yy += kRT / 64) {
       double s = 0.0;
 #pragma unroll
