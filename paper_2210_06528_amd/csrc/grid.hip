@@ -306,12 +306,13 @@ __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in
 
   for (int64_t g = I1a; g < I1b; g += RI) {
     const int nr = (int)min((int64_t)RI, I1b - g);
-    // the group's rows advance the span at most nr <= RI times: control rows
-    // cur+1 .. cur+RI of this column (clamped to the grid, the excess never
-    // used) are requested together, one wait per group
+    // the group's rows advance the span adv <= nr <= RI times: control rows
+    // cur+1 .. cur+adv of this column are requested together, one wait per
+    // group (the remaining registers re-read the last of them, a cache hit)
+    const int adv = ss[g + nr - 1 - I1a] - cur;
     double nx[RI];
 #pragma unroll
-    for (int u = 0; u < RI; ++u) nx[u] = slab[(int64_t)min(cur + 1 + u, n1 - 1) * n2];
+    for (int u = 0; u < RI; ++u) nx[u] = slab[(int64_t)(cur + min(u + 1, adv)) * n2];
     for (int rr = 0; rr < nr; ++rr) {
       const int64_t i1 = g + rr;
       const int s = ss[i1 - I1a];
