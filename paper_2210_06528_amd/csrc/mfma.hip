@@ -190,6 +190,114 @@ __global__ void __launch_bounds__(256) k_mfma_strided(const float *__restrict__ 
   if (MODE == 1) slot_max_m(slots, kSlotMaxDP, dmax);
 }
 
+// Axis-0 pass that adds into the control points (outer = 1), for n <= 64 *
+// kPT: every wave's control points (kPT row tiles) are requested at the
+// start, with the staging loads, instead of one HBM round trip per tile after
+// the products (they hold 64 registers: two waves per SIMD, still faster).
+// Loads use clamped in-bounds indices; the same MFMA sequence as
+// k_mfma_strided<1>.
+constexpr int kPT = 4;
+__global__ void __launch_bounds__(256) k_mfma_axis0_add(const float *__restrict__ in,
+                                                        double *__restrict__ pc, int n, int64_t inner,
+                                                        int npad, const __hip_bfloat16 *__restrict__ Mhi,
+                                                        const __hip_bfloat16 *__restrict__ Mlo,
+                                                        const int *__restrict__ klo,
+                                                        const int *__restrict__ knc,
+                                                        unsigned long long *slots) {
+  extern __shared__ __hip_bfloat16 T[];   // hi: [kIT][npad + 8], then lo
+  const int ld = npad + 8;
+  __hip_bfloat16 *Thi = T, *Tlo = T + kIT * ld;
+  const int64_t i0 = (int64_t)blockIdx.x * kIT;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int ntiles = (n + 15) >> 4;
+  double pold[kPT][kIT / 16][4];
+#pragma unroll
+  for (int j = 0; j < kPT; ++j) {
+    const int t = w + 4 * j;
+#pragma unroll
+    for (int s = 0; s < kIT / 16; ++s) {
+      const int64_t i = min(i0 + 16 * s + r16, inner - 1);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = min(16 * t + 4 * kq + v, n - 1);
+        pold[j][s][v] = pc[(int64_t)k * inner + i];
+      }
+    }
+  }
+  for (int e0 = 0; e0 < npad * kIT; e0 += 256 * kStage) {
+    float v[kStage];
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = e0 + threadIdx.x + 256 * r;
+      const int j = e / kIT, ii = e - j * kIT;
+      v[r] = (e < npad * kIT && j < n && i0 + ii < inner) ? in[(int64_t)j * inner + i0 + ii] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = e0 + threadIdx.x + 256 * r;
+      const int j = e / kIT, ii = e - j * kIT;
+      if (e < npad * kIT) split_bf16(v[r], Thi[ii * ld + j], Tlo[ii * ld + j]);
+    }
+  }
+  __syncthreads();
+  double dmax = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPT; ++j) {
+    const int t = w + 4 * j;
+    if (t < ntiles) {
+      floatx4 acc[kIT / 16];
+#pragma unroll
+      for (int s = 0; s < kIT / 16; ++s) acc[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const int lo = klo[t], nc = knc[t];
+      const int64_t moff = (int64_t)(16 * t + r16) * npad + 8 * kq;
+      bf16x8 ahi[kPre], alo[kPre];
+#pragma unroll
+      for (int c = 0; c < kPre; ++c) {
+        if (c < nc) {
+          ahi[c] = load8(Mhi + moff + lo + 32 * c);
+          alo[c] = load8(Mlo + moff + lo + 32 * c);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kPre; ++c) {
+        if (c < nc) {
+          const int j0 = lo + 32 * c;
+#pragma unroll
+          for (int s = 0; s < kIT / 16; ++s) {
+            const int toff = (16 * s + r16) * ld + j0 + 8 * kq;
+            acc[s] = mfma3(ahi[c], alo[c], load8(Thi + toff), load8(Tlo + toff), acc[s]);
+          }
+        }
+      }
+      for (int c = kPre; c < nc; ++c) {
+        const int j0 = lo + 32 * c;
+        const bf16x8 bh = load8(Mhi + moff + j0), bl = load8(Mlo + moff + j0);
+#pragma unroll
+        for (int s = 0; s < kIT / 16; ++s) {
+          const int toff = (16 * s + r16) * ld + j0 + 8 * kq;
+          acc[s] = mfma3(bh, bl, load8(Thi + toff), load8(Tlo + toff), acc[s]);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < kIT / 16; ++s) {
+        const int64_t i = i0 + 16 * s + r16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = 16 * t + 4 * kq + v;
+          if (k < n && i < inner) {
+            const double d = (double)acc[s][v];
+            pc[(int64_t)k * inner + i] = pold[j][s][v] + d;
+            dmax = fmax(dmax, fabs(d));
+          }
+        }
+      }
+    }
+  }
+  slot_max_m(slots, kSlotMaxDP, dmax);
+}
+
 // Contiguous axis: the array is [nlines][n] (FP32); workgroup = 16*nw lines
 // staged in LDS (split), wave w holds lines 16w..16w+15 and computes every
 // row tile of M_a for them.
@@ -531,7 +639,10 @@ hipError_t launch_mfma_correct(Handle &h, int axis, const float *in, float *out,
     const int64_t inner = axis == 0 ? (int64_t)h.ax[1].n * h.ax[2].n : h.ax[2].n;
     const dim3 grid(nblk(inner, kIT), (unsigned)outer);
     const size_t lds = mfma_lds(X.npad);
-    if (add)
+    if (add && axis == 0 && n <= 64 * kPT) {
+      k_mfma_axis0_add<<<grid, 256, lds, h.stream>>>(in, h.P, n, inner, X.npad, Mhi, Mlo, X.d_klo,
+                                                     X.d_knc, h.slots);
+    } else if (add)
       k_mfma_strided<1><<<grid, 256, lds, h.stream>>>(in, out, h.P, n, inner, X.npad, Mhi, Mlo,
                                                       X.d_klo, X.d_knc, h.slots);
     else
