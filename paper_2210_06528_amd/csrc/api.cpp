@@ -318,22 +318,90 @@ hipError_t sweep_databox(Handle &h, bool metrics) {
   return hipSuccess;
 }
 
+// Two auxiliary streams (default priority) and fork/join events per host
+// thread and device, created on first use and kept for the life of the
+// process: concurrent handles on different threads never share them.
+struct AuxStreams {
+  hipStream_t s[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+};
+
+static AuxStreams *aux_streams(int device) {
+  static thread_local AuxStreams per_dev[16];
+  if (device < 0 || device >= 16) return nullptr;
+  AuxStreams &a = per_dev[device];
+  if (!a.fork) {
+    for (int i = 0; i < 2; ++i) {
+      if (hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking) != hipSuccess) return nullptr;
+      if (hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming) != hipSuccess) return nullptr;
+    }
+    if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+  }
+  return &a;
+}
+
+// Runs a launch helper on another stream: the helpers launch on h.stream.
+struct StreamSwap {
+  Handle &h;
+  hipStream_t saved;
+  StreamSwap(Handle &hh, hipStream_t s) : h(hh), saved(hh.stream) { h.stream = s; }
+  ~StreamSwap() { h.stream = saved; }
+};
+
+// Jump of the interfaces along axis a: the interface functionals applied to
+// the residual into U, then expanded over the other axes.
+static hipError_t jump_axis(Handle &h, int a, double *U) {
+  hipError_t e =
+      h.g_type == 1   ? launch_jump_project<float>(h, a, reinterpret_cast<const float *>(h.g), U)
+      : h.g_type == 2 ? launch_jump_project<__hip_bfloat16>(
+                            h, a, reinterpret_cast<const __hip_bfloat16 *>(h.g), U)
+                      : launch_jump_project<double>(h, a, h.g, U);
+  if (e != hipSuccess) return e;
+  return launch_jump_expand(h, a, U);
+}
+
 // Jump and scale reductions of the sweep just done (g still holds the
-// residual the sweep used; P holds the new consensus).
+// residual the sweep used; P holds the new consensus).  The per-axis jump
+// chains and the derivative scales are independent latency-bound kernels
+// whose maxima go to separate slots: axis 0 and the scales run on the
+// caller's stream, axes 1 and 2 on the two auxiliary streams (forked from it
+// and joined back), each axis with its own part of the scratch array s1.
 hipError_t sweep_metrics(Handle &h) {
   TimeScope ts(h, MFA_K_METRICS);
+  int64_t off[3] = {0, 0, 0}, tot = 0;
+  bool jumps[3] = {false, false, false};
   for (int a = 0; a < 3; ++a) {
     if (!h.ax[a].active || h.ax[a].B < 2) continue;
-    hipError_t e =
-        h.g_type == 1   ? launch_jump_project<float>(h, a, reinterpret_cast<const float *>(h.g), h.s1)
-        : h.g_type == 2 ? launch_jump_project<__hip_bfloat16>(
-                              h, a, reinterpret_cast<const __hip_bfloat16 *>(h.g), h.s1)
-                        : launch_jump_project<double>(h, a, h.g, h.s1);
-    if (e != hipSuccess) return e;
-    e = launch_jump_expand(h, a, h.s1);
-    if (e != hipSuccess) return e;
+    jumps[a] = true;
+    off[a] = tot;
+    tot += (int64_t)(h.ax[a].B - 1) * h.p * (h.nctrl_total / h.ax[a].n);
   }
-  return launch_deriv_scale(h);
+  AuxStreams *aux = tot <= h.s1n ? aux_streams(h.device) : nullptr;
+  if (!aux) {
+    for (int a = 0; a < 3; ++a) {
+      if (!jumps[a]) continue;
+      hipError_t e = jump_axis(h, a, h.s1);
+      if (e != hipSuccess) return e;
+    }
+    return launch_deriv_scale(h);
+  }
+  hipError_t e = hipEventRecord(aux->fork, h.stream);
+  if (e != hipSuccess) return e;
+  for (int a = 1; a < 3; ++a) {
+    if (!jumps[a]) continue;
+    hipStream_t st = aux->s[a - 1];
+    if ((e = hipStreamWaitEvent(st, aux->fork, 0)) != hipSuccess) return e;
+    {
+      StreamSwap sw(h, st);
+      if ((e = jump_axis(h, a, h.s1 + off[a])) != hipSuccess) return e;
+    }
+    if ((e = hipEventRecord(aux->join[a - 1], st)) != hipSuccess) return e;
+  }
+  if (jumps[0] && (e = jump_axis(h, 0, h.s1 + off[0])) != hipSuccess) return e;
+  if ((e = launch_deriv_scale(h)) != hipSuccess) return e;
+  for (int a = 1; a < 3; ++a)
+    if (jumps[a] && (e = hipStreamWaitEvent(h.stream, aux->join[a - 1], 0)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 mfa_status read_stats(Handle &h, mfa_step_stats *out, double jump_tol, bool *finite) {
@@ -392,28 +460,6 @@ mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes) {
   if (!msg.empty()) return fail(MFA_EINVAL, msg);
   *bytes = layout_workspace(&tmp, nullptr);
   return MFA_OK;
-}
-
-// Two auxiliary streams (default priority) and fork/join events per host
-// thread and device, created on first use and kept for the life of the
-// process: concurrent handles on different threads never share them.
-struct AuxStreams {
-  hipStream_t s[2] = {nullptr, nullptr};
-  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
-};
-
-static AuxStreams *aux_streams(int device) {
-  static thread_local AuxStreams per_dev[16];
-  if (device < 0 || device >= 16) return nullptr;
-  AuxStreams &a = per_dev[device];
-  if (!a.fork) {
-    for (int i = 0; i < 2; ++i) {
-      if (hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking) != hipSuccess) return nullptr;
-      if (hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming) != hipSuccess) return nullptr;
-    }
-    if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
-  }
-  return &a;
 }
 
 mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, void *hip_stream,
