@@ -189,13 +189,22 @@ def cpu_baseline(w, Q, nsweeps_gpu, nsample):
     schwarz.decode(S, P)
     t_dec = time.perf_counter() - t0
     total = t_setup + t_sweep * nsweeps_gpu + t_dec
+    # second figure: the oracle's single-domain direct solve, the fixed point
+    # the iteration converges to (not the method the GPU runs)
+    t0 = time.perf_counter()
+    schwarz.global_direct(S, Q64)
+    t_direct = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return {"value": w.npoints / total, "unit": "points/s", "cores": int(threads),
             "kind": "oracle",
             "sample": (f"{nsample} literal per-subdomain oracle sweeps of the full {w.name} input "
                        f"({t_sweep:.2f} s/sweep) + setup + one decode, extrapolated to the "
                        f"{nsweeps_gpu} sweeps the GPU needed"),
-            "seconds_measured": round(t_setup + t_sweep * nsample + t_dec, 2)}
+            "seconds_measured": round(t_setup + t_sweep * nsample + t_dec, 2),
+            "global_direct": {"value": w.npoints / t_direct, "unit": "points/s",
+                              "seconds": round(t_direct, 2),
+                              "what": "oracle single-domain separable least-squares fit of the "
+                                      "same input (the iteration's fixed point), same threads"}}
 
 
 def run_copy(args):
