@@ -169,7 +169,7 @@ hipError_t correct_bsolve(Handle &h, const T *g) {
 //                                     subdomains at once)
 //   P += (M_0 x M_1 x M_2) g         (local solves with lagged ghosts and the
 //                                     1/n_s combine, Section 2.3.2)
-hipError_t sweep_normal(Handle &h) {
+hipError_t sweep_normal(Handle &h, const SlotTurn &turn) {
   const int n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
   if (h.precision == MFA_PREC_MIXED_BF16 && mfma_ok(h)) {
     // residual in float64, rounded to FP32; correction on the matrix cores
@@ -179,7 +179,7 @@ hipError_t sweep_normal(Handle &h) {
     {
       TimeScope ts(h, MFA_K_RESID);
       e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                              h.ax[2].d_acoef, n0, n1, n2, h.slots);
+                              h.ax[2].d_acoef, n0, n1, n2, h.slots, turn);
     }
     if (e != hipSuccess) return e;
     if (h.fuse21 && h.ax[0].active && mfma_fused21_ok(h)) {
@@ -217,7 +217,7 @@ hipError_t sweep_normal(Handle &h) {
       {
         TimeScope ts(h, MFA_K_RESID);
         e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                                h.ax[2].d_acoef, n0, n1, n2, h.slots);
+                                h.ax[2].d_acoef, n0, n1, n2, h.slots, turn);
       }
       if (e != hipSuccess) return e;
       return correct_bsolve<float>(h, gf);
@@ -226,7 +226,7 @@ hipError_t sweep_normal(Handle &h) {
     {
       TimeScope ts(h, MFA_K_RESID);
       e = launch_resid<double>(h.stream, h.p, h.P, h.c, h.g, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                               h.ax[2].d_acoef, n0, n1, n2, h.slots);
+                               h.ax[2].d_acoef, n0, n1, n2, h.slots, turn);
     }
     if (e != hipSuccess) return e;
     return correct_bsolve<double>(h, h.g);
@@ -592,11 +592,38 @@ static mfa_status load_q(Handle &h, const void *q, mfa_dtype dt) {
   return MFA_OK;
 }
 
+// Whether a NORMAL-mode sweep starts with the residual stencil kernel (the
+// conditions of sweep_normal's first two branches).
+static bool sweep_uses_resid_kernel(const Handle &h) {
+  if (h.rhs == MFA_RHS_DATABOX) return false;
+  if (h.precision == MFA_PREC_MIXED_BF16 && mfma_ok(h)) return true;
+  return fast_sweep_ok(h, h.precision != MFA_PREC_FP64 ? sizeof(float) : sizeof(double));
+}
+
 static mfa_status do_sweep(Handle &h, bool metrics) {
-  // record the previous sweep's max |correction| (sweep h.sweep, 1-based)
-  hipError_t e = launch_zero_slots(h.stream, h.slots, kNumSlots * kSlotCopies,
-                                   h.sweep >= 1 ? h.hist : nullptr, (h.sweep - 1 + kHist) % kHist);
-  if (e != hipSuccess) return hip_fail(e, "zero slots");
+  // Reduction slots: sweep k (0-based h.sweep) writes set k % 2, which is
+  // zero when it starts.  The residual kernel of sweep k records the max
+  // |correction| of sweep k-1 (set (k+1) % 2) into the history and clears
+  // that set for sweep k+1; the host reads a sweep's set only right after it
+  // (stream-synchronised), before the next sweep is queued.  Sweeps without
+  // the residual kernel clear their own set with one small launch.
+  const int64_t nset = (int64_t)kNumSlots * kSlotCopies;
+  unsigned long long *cur = h.slot_base + (h.sweep & 1) * nset;
+  unsigned long long *prev = h.slot_base + ((h.sweep + 1) & 1) * nset;
+  h.slots = cur;
+  double *hist = h.sweep >= 1 ? h.hist : nullptr;
+  const int hidx = (h.sweep - 1 + kHist) % kHist;
+  SlotTurn turn;
+  hipError_t e = hipSuccess;
+  if (sweep_uses_resid_kernel(h)) {
+    // the first sweep also clears its own set (both sets start cleared)
+    if (h.sweep == 0 && (e = launch_zero_slots(h.stream, h.slot_base, 2 * (int)nset)) != hipSuccess)
+      return hip_fail(e, "zero slots");
+    turn = SlotTurn{prev, hist, hidx};
+  } else {
+    e = launch_zero_slots(h.stream, cur, (int)nset, hist, hidx, prev);
+    if (e != hipSuccess) return hip_fail(e, "zero slots");
+  }
   if (h.rhs == MFA_RHS_DATABOX) {
     e = sweep_databox(h, metrics);
     if (e != hipSuccess) return hip_fail(e, "sweep");
@@ -606,7 +633,7 @@ static mfa_status do_sweep(Handle &h, bool metrics) {
       if (e != hipSuccess) return hip_fail(e, "metrics");
     }
   } else {
-    e = sweep_normal(h);
+    e = sweep_normal(h, turn);
     if (e != hipSuccess) return hip_fail(e, "sweep");
     if (metrics) {
       e = sweep_metrics(h);

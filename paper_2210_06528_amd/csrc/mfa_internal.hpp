@@ -109,7 +109,10 @@ struct Handle {
   // DATABOX scratch
   double *b1 = nullptr, *b2 = nullptr;
   int64_t b1n = 0, b2n = 0;
-  unsigned long long *slots = nullptr;   // reductions, see kSlot*
+  // reductions, see kSlot*: two sets of kNumSlots * kSlotCopies, used by
+  // alternate sweeps (slots points to the current sweep's set)
+  unsigned long long *slot_base = nullptr;
+  unsigned long long *slots = nullptr;
   int *flag = nullptr;                   // setup error flag
   double *hist = nullptr;                // max |correction| of recent sweeps (ring of kHist)
   size_t upload_bytes = 0;               // host-planned tables: workspace bytes [0, upload_bytes)
@@ -173,11 +176,20 @@ hipError_t launch_fill(hipStream_t st, double *x, int64_t n, double v);
 template <typename TQ>
 hipError_t launch_box_resid(hipStream_t st, const TQ *q, Dims qd, double *r, Dims rd,
                             const int *qm0, const int *qm1, const int *qm2);
-// zero the reduction slots; first record the previous sweep's max |correction|
-// (slot kSlotMaxDP) into hist[idx] when hist is given
+// zero n reduction slots; first record the max |correction| held in the set
+// `from` (slot kSlotMaxDP, the previous sweep's) into hist[idx] when hist is
+// given
 constexpr int kHist = 64;
 hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n, double *hist = nullptr,
-                             int idx = 0);
+                             int idx = 0, const unsigned long long *from = nullptr);
+// Slot bookkeeping a sweep's residual kernel does in its first workgroup:
+// record the previous sweep's max |correction| (set `prev`) into hist[idx]
+// (hist may be null), then clear `prev`, the set the next sweep uses.
+struct SlotTurn {
+  unsigned long long *prev = nullptr;
+  double *hist = nullptr;
+  int idx = 0;
+};
 hipError_t launch_maxabs(hipStream_t st, const double *x, int64_t n, unsigned long long *slot);
 
 // setup kernels (one axis at a time)
@@ -195,7 +207,7 @@ hipError_t setup_acoef(Handle *h, int a, hipStream_t st);
 template <typename TG>
 hipError_t launch_resid(hipStream_t st, int p, const double *Pc, const double *c, TG *g,
                         const double *A0, const double *A1, const double *A2, int n0, int n1, int n2,
-                        unsigned long long *slots);
+                        unsigned long long *slots, const SlotTurn &turn = SlotTurn{});
 template <typename TI, typename TO, typename TC>
 hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int axis, int n0, int n1,
                          int n2, int p, const Axis &X, int combine, unsigned long long *slots);

@@ -93,12 +93,13 @@ __global__ void k_fill(double *x, int64_t n, double v) {
   if (i < n) x[i] = v;
 }
 
-// One wavefront per block; block 0 covers the kSlotCopies copies of slot
-// kSlotMaxDP and reads them (max over the copies) before clearing.
-__global__ void k_zero_slots(unsigned long long *s, int n, double *hist, int idx) {
+// One wavefront per block; block 0 reads the kSlotCopies copies of slot
+// kSlotMaxDP of `from` (max over the copies) before any clearing.
+__global__ void k_zero_slots(unsigned long long *s, int n, double *hist, int idx,
+                             const unsigned long long *from) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (hist && blockIdx.x == 0) {
-    unsigned long long v = threadIdx.x < kSlotCopies ? s[kSlotMaxDP * kSlotCopies + threadIdx.x] : 0ull;
+    unsigned long long v = threadIdx.x < kSlotCopies ? from[kSlotMaxDP * kSlotCopies + threadIdx.x] : 0ull;
     for (int off = 32; off > 0; off >>= 1) {
       const unsigned long long o = __shfl_xor(v, off, 64);
       v = o > v ? o : v;
@@ -192,9 +193,10 @@ hipError_t launch_fill(hipStream_t st, double *x, int64_t n, double v) {
   return hipGetLastError();
 }
 
-hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n, double *hist, int idx) {
-  static_assert(kSlotMaxDP == 0 && kSlotCopies == 64, "block 0 must hold the max-correction slot");
-  k_zero_slots<<<nblk(n, 64), 64, 0, st>>>(slots, n, hist, idx);
+hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n, double *hist, int idx,
+                             const unsigned long long *from) {
+  static_assert(kSlotMaxDP == 0 && kSlotCopies == 64, "one wavefront reads the max-correction slot");
+  k_zero_slots<<<nblk(n, 64), 64, 0, st>>>(slots, n, hist, idx, from ? from : slots);
   return hipGetLastError();
 }
 

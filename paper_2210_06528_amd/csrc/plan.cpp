@@ -383,7 +383,8 @@ size_t layout_workspace(Handle *h, char *base) {
     h->b2 = bp.take<double>(big);
     h->b1n = h->b2n = big;
   }
-  h->slots = bp.take<unsigned long long>((int64_t)kNumSlots * kSlotCopies);
+  h->slot_base = bp.take<unsigned long long>(2 * (int64_t)kNumSlots * kSlotCopies);
+  h->slots = h->slot_base;
   h->flag = bp.take<int>(4);
   h->hist = bp.take<double>(kHist);
   return bp.off + 256;

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
                                                const double *__restrict__ A0,
                                                const double *__restrict__ A1,
                                                const double *__restrict__ A2, int n0, int n1, int n2,
-                                               int xchunk, unsigned long long *slots) {
+                                               int xchunk, unsigned long long *slots, SlotTurn turn) {
   constexpr int W = 2 * P + 1;
   constexpr int LY = kTY + 2 * P;
   constexpr int LZ = kTZ + 2 * P;
@@ -72,6 +72,22 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wavefront index 0..7
   const int z0 = blockIdx.x * kTZ, y0 = blockIdx.y * kTY, x0 = blockIdx.z * xchunk;
   const int x1 = min(n0, x0 + xchunk);
+  // slot bookkeeping (first workgroup): the previous sweep's max |correction|
+  // into the history, then its slot set cleared for the next sweep; no other
+  // kernel of this sweep touches that set
+  if (turn.prev && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+    unsigned long long v = 0ull;
+    if (threadIdx.x < kSlotCopies) v = turn.prev[kSlotMaxDP * kSlotCopies + threadIdx.x];
+    if (turn.hist && threadIdx.x < 64) {
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+      }
+      if (threadIdx.x == 0) turn.hist[turn.idx] = __longlong_as_double((long long)v);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kNumSlots * kSlotCopies; e += kRT) turn.prev[e] = 0ull;
+  }
   const int gz = z0 + tx;
   for (int e = threadIdx.x; e < W * kTZ; e += kRT) {
     const int t = e / kTZ, zl = e - t * kTZ;
@@ -507,7 +523,7 @@ constexpr int64_t kTuneMinCtrl = 1 << 20;
 template <int P, typename TG>
 hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG *g, const double *A0,
                           const double *A1, const double *A2, int n0, int n1, int n2,
-                          unsigned long long *slots) {
+                          unsigned long long *slots, const SlotTurn &turn) {
   // the kernel addresses within a plane with 32-bit offsets
   if ((int64_t)n1 * n2 > INT32_MAX) return hipErrorInvalidValue;
   const int byz = (int)(nblk(n2, kTZ) * nblk(n1, kTY));
@@ -518,9 +534,11 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
     auto it = g_resid_chunk.find(key);
     if (it != g_resid_chunk.end()) xchunk = it->second;
   }
-  auto launch = [&](int xc) {
+  // the tuner's timing launches skip the slot bookkeeping (recording the
+  // history is not idempotent); the sweep's own launch does it
+  auto launch = [&](int xc, const SlotTurn &tn) {
     const dim3 grid(nblk(n2, kTZ), nblk(n1, kTY), nblk(n0, xc));
-    k_resid<P, TG><<<grid, kRT, 0, st>>>(Pc, c, g, A0, A1, A2, n0, n1, n2, xc, slots);
+    k_resid<P, TG><<<grid, kRT, 0, st>>>(Pc, c, g, A0, A1, A2, n0, n1, n2, xc, slots, tn);
     return hipGetLastError();
   };
   if (xchunk == 0) {
@@ -542,12 +560,12 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
       // unless a candidate is at least 10% faster, so that timing noise
       // (or a profiler's overhead) cannot flip the choice
       std::vector<float> tmin(cand.size(), 1e30f);
-      hipError_t err = launch(cand[0]);   // warm-up
+      hipError_t err = launch(cand[0], SlotTurn{});   // warm-up
       for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
         for (size_t i = 0; i < cand.size() && err == hipSuccess; ++i) {
           float ms = 0.f;
           hipEventRecord(e0, st);
-          err = launch(cand[i]);
+          err = launch(cand[i], SlotTurn{});
           hipEventRecord(e1, st);
           if (err == hipSuccess) err = hipEventSynchronize(e1);
           if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
@@ -564,7 +582,7 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
     std::lock_guard<std::mutex> lk(g_resid_mu);
     g_resid_chunk[key] = xchunk;
   }
-  return launch(xchunk);
+  return launch(xchunk, turn);
 }
 
 }  // namespace
@@ -572,11 +590,11 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
 template <typename TG>
 hipError_t launch_resid(hipStream_t st, int p, const double *Pc, const double *c, TG *g,
                         const double *A0, const double *A1, const double *A2, int n0, int n1, int n2,
-                        unsigned long long *slots) {
+                        unsigned long long *slots, const SlotTurn &turn) {
   switch (p) {
 #define MFA_RESID_CASE(PP) \
   case PP:                 \
-    return launch_resid_p<PP, TG>(st, Pc, c, g, A0, A1, A2, n0, n1, n2, slots);
+    return launch_resid_p<PP, TG>(st, Pc, c, g, A0, A1, A2, n0, n1, n2, slots, turn);
     MFA_RESID_CASE(1)
     MFA_RESID_CASE(2)
     MFA_RESID_CASE(3)
@@ -661,13 +679,14 @@ hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int 
 
 template hipError_t launch_resid<double>(hipStream_t, int, const double *, const double *, double *,
                                          const double *, const double *, const double *, int, int, int,
-                                         unsigned long long *);
+                                         unsigned long long *, const SlotTurn &);
 template hipError_t launch_resid<float>(hipStream_t, int, const double *, const double *, float *,
                                         const double *, const double *, const double *, int, int, int,
-                                        unsigned long long *);
+                                        unsigned long long *, const SlotTurn &);
 template hipError_t launch_resid<__hip_bfloat16>(hipStream_t, int, const double *, const double *,
                                                  __hip_bfloat16 *, const double *, const double *,
-                                                 const double *, int, int, int, unsigned long long *);
+                                                 const double *, int, int, int, unsigned long long *,
+                                                 const SlotTurn &);
 template hipError_t launch_bsolve<double, double, double>(hipStream_t, const double *, double *,
                                                           double *, int, int, int, int, int,
                                                           const Axis &, int, unsigned long long *);
