@@ -71,7 +71,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, datasheet
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the 30 sweep
 # launches of one 512x512x384 p=4 mixed-precision encode, 384 workgroups in
 # x-chunks of 32 planes), scaled by what the same counters
-# read for a plain 1 GiB streaming copy (FETCH_SIZE 524305.5 KiB for 1048576 KiB
+# read for a plain 1 GiB streaming copy (FETCH_SIZE 524305.6 KiB for 1048576 KiB
 # read: x2.0; WRITE_SIZE 1048576 KiB for 1048576 KiB written: x1.0).  Valid only
 # for the kernel source it was taken on: the bench reports null traffic once
 # the residual kernel or its launcher has changed (digest of their source).
@@ -79,9 +79,9 @@ RESID_COUNTERS = {
     "workload": "3d-spectral-512x512x384-p4-uneven",
     "precision": "mixed_bf16",
     "source": "paper_2210_06528_amd/csrc/sweep.hip",
-    "source_sha256": "2580c05a5aeee1e353bddec25578208553f56327c075d35b5ac2e46d4ddae7fc",
-    "fetch_kib": 167309.1, "write_kib": 49248.0,
-    "fetch_factor": 1048576.0 / 524305.5, "write_factor": 1.0,
+    "source_sha256": "37fc46425d64bb00a67ef975d62556cee84ebe6a00d8b2b0b6b85b8d9e6fc5a2",
+    "fetch_kib": 167314.3, "write_kib": 49276.0,
+    "fetch_factor": 1048576.0 / 524305.6, "write_factor": 1.0,
 }
 
 
