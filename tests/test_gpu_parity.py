@@ -235,17 +235,20 @@ def test_bf16_sweep_is_a_perturbed_fp64_sweep():
     assert 0 < _rel(pb, pa) < 5e-2
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed_bf16"])
-def test_predicted_check_schedule_stops_at_or_just_after_the_crossing(precision):
+@pytest.mark.parametrize("precision,rhs", [("fp64", "normal"), ("mixed_bf16", "normal"),
+                                           ("fp64", "databox")])
+def test_predicted_check_schedule_stops_at_or_just_after_the_crossing(precision, rhs):
     """With the predicted schedule (check_every = 0) the encode may only stop
     at a sweep whose jumps are below the tolerance, so never before the first
     such sweep of the every-sweep oracle run, and the prediction lands within
-    a few sweeps after it."""
+    a few sweeps after it.  The three cases cover both ways the correction
+    history is recorded: by the residual stencil (mixed_bf16) and by the
+    per-sweep slot clearing (the generic passes and the data-box form)."""
     w = W.cfg_2d()
     S = _oracle(w)
     Q = W.make_field(w)
     _, hist = schwarz.encode(S, Q, 40, jump_tol=w.jump_tol)
-    enc = _enc(w, precision=precision)
+    enc = _enc(w, precision=precision, rhs=rhs)
     st = enc.encode(torch.from_numpy(Q).cuda(), 40, w.jump_tol, 0)
     assert st["converged"] and max(st["jump"]) < w.jump_tol
     assert len(hist) <= st["sweep"] <= len(hist) + 3, (st["sweep"], len(hist))
