@@ -226,19 +226,40 @@ __global__ void __launch_bounds__(256) k_mfma_axis0_add(const float *__restrict_
       }
     }
   }
-  for (int e0 = 0; e0 < npad * kIT; e0 += 256 * kStage) {
-    float v[kStage];
+  // staging: a thread takes column ii and blocks of 8 consecutive rows j (the
+  // loads coalesce across the kIT columns); each block's 8 values are split
+  // and stored as one 16-byte write per half (rows ld = npad + 8 elements
+  // apart put 16 lanes' 16-byte groups in distinct banks)
+  {
+    constexpr int BPP = 256 / kIT;   // row blocks per pass of the workgroup
+    const int ii = threadIdx.x % kIT;
+    const int nb8 = npad / 8;
+    const bool colok = i0 + ii < inner;
+    for (int b0 = threadIdx.x / kIT; b0 < nb8; b0 += 2 * BPP) {
+      float v[2][8];
 #pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = e0 + threadIdx.x + 256 * r;
-      const int j = e / kIT, ii = e - j * kIT;
-      v[r] = (e < npad * kIT && j < n && i0 + ii < inner) ? in[(int64_t)j * inner + i0 + ii] : 0.f;
-    }
+      for (int hh = 0; hh < 2; ++hh) {
+        const int jb = b0 + hh * BPP;
 #pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = e0 + threadIdx.x + 256 * r;
-      const int j = e / kIT, ii = e - j * kIT;
-      if (e < npad * kIT) split_bf16(v[r], Thi[ii * ld + j], Tlo[ii * ld + j]);
+        for (int q = 0; q < 8; ++q) {
+          const int j = 8 * jb + q;
+          v[hh][q] = (jb < nb8 && j < n && colok) ? in[(int64_t)j * inner + i0 + ii] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int jb = b0 + hh * BPP;
+        if (jb < nb8) {
+          __hip_bfloat16 hb[8], lb[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) split_bf16(v[hh][q], hb[q], lb[q]);
+          bf16x8 hv, lv;
+          __builtin_memcpy(&hv, hb, sizeof(hv));
+          __builtin_memcpy(&lv, lb, sizeof(lv));
+          *reinterpret_cast<bf16x8 *>(Thi + ii * ld + 8 * jb) = hv;
+          *reinterpret_cast<bf16x8 *>(Tlo + ii * ld + 8 * jb) = lv;
+        }
+      }
     }
   }
   __syncthreads();
