@@ -415,6 +415,7 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
 // lines is loaded into registers while the current one is multiplied.  At
 // most 168 registers per lane (three waves per SIMD, as many workgroups per CU
 // as the LDS holds).
+template <bool VEC>
 __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict__ in, float *__restrict__ out,
                                                       int n1, int n2, int npad1, int npad2,
                                                       const __hip_bfloat16 *__restrict__ M1hi,
@@ -444,7 +445,7 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
     jlo = min(jlo, klo2[t2a + 1]);
     jhi = max(jhi, klo2[t2a + 1] + 32 * knc2[t2a + 1]);
   }
-  const int jw = jhi - jlo;   // 32 * jw <= 256 * kStage (checked on the host)
+  const int jw = jhi - jlo;   // a multiple of 8; 32 * jw / 8 <= 512 (checked on the host)
   // wave w: output tile t2a + (w & 1), lines 16*(w >> 1) .. +15 of each chunk
   const bool mine = (w & 1) < nt2;
   const int t = t2a + (w & 1), lbk = w >> 1;
@@ -465,23 +466,51 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
     Tlo[ii * ld1 + j] = __float2bfloat16(0.0f);
   }
   const float *plane = in + o * (int64_t)n1 * n2;
-  float v[kStage];
+  // Phase-1 staging in blocks of 8 consecutive columns of one line (jw is a
+  // multiple of 8; at most 2 blocks per thread): read with 16-byte loads when
+  // rows are 16-byte aligned (VEC), columns past n2 read as zeros, and each
+  // block stored split as one 16-byte write per half.
+  const int nbw = jw / 8, nblk32 = 32 * nbw;
+  float v[2][8];
   auto fetch = [&](int l0) {
 #pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = threadIdx.x + 256 * r;
-      const int li = e / jw, j = jlo + (e - li * jw);
-      v[r] = (e < 32 * jw && l0 + li < n1 && j < n2) ? plane[(int64_t)(l0 + li) * n2 + j] : 0.f;
+    for (int hh = 0; hh < 2; ++hh) {
+      const int bi = threadIdx.x + 256 * hh;
+      const int li = bi / nbw, j0 = jlo + 8 * (bi - li * nbw);
+      const bool ok = bi < nblk32 && l0 + li < n1;
+      const float *src = plane + (int64_t)(ok ? l0 + li : 0) * n2 + (ok ? j0 : 0);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (VEC && ok && j0 + 4 * u + 3 < n2) {
+          const float4 f = *reinterpret_cast<const float4 *>(src + 4 * u);
+          v[hh][4 * u] = f.x;
+          v[hh][4 * u + 1] = f.y;
+          v[hh][4 * u + 2] = f.z;
+          v[hh][4 * u + 3] = f.w;
+        } else {
+#pragma unroll
+          for (int q = 4 * u; q < 4 * u + 4; ++q) v[hh][q] = (ok && j0 + q < n2) ? src[q] : 0.f;
+        }
+      }
     }
   };
   fetch(0);
   for (int l0 = 0; l0 < n1; l0 += 32) {
     __syncthreads();   // the previous chunk's staging is consumed
 #pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = threadIdx.x + 256 * r;
-      const int li = e / jw, jj = e - li * jw;
-      if (e < 32 * jw) split_bf16(v[r], Lhi[li * ldw + jj], Llo[li * ldw + jj]);
+    for (int hh = 0; hh < 2; ++hh) {
+      const int bi = threadIdx.x + 256 * hh;
+      if (bi < nblk32) {
+        const int li = bi / nbw, bj = bi - li * nbw;
+        __hip_bfloat16 hb[8], lb[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) split_bf16(v[hh][q], hb[q], lb[q]);
+        bf16x8 hv, lv;
+        __builtin_memcpy(&hv, hb, sizeof(hv));
+        __builtin_memcpy(&lv, lb, sizeof(lv));
+        *reinterpret_cast<bf16x8 *>(Lhi + li * ldw + 8 * bj) = hv;
+        *reinterpret_cast<bf16x8 *>(Llo + li * ldw + 8 * bj) = lv;
+      }
     }
     __syncthreads();
     if (l0 + 32 < n1) fetch(l0 + 32);
@@ -501,10 +530,20 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
                     load8(M2lo + moff + j0), acc);
       }
       const int ii = 16 * (w & 1) + r16;   // output k2 - K2a
+      const int j1 = l0 + 16 * lbk + 4 * kq;
+      if (j1 + 3 < n1) {   // four consecutive rows: one 8-byte write per half
+        __hip_bfloat16 hb[4], lb[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j1 = l0 + 16 * lbk + 4 * kq + q;
-        if (j1 < n1) split_bf16(acc[q], Thi[ii * ld1 + j1], Tlo[ii * ld1 + j1]);
+        for (int q = 0; q < 4; ++q) split_bf16(acc[q], hb[q], lb[q]);
+        uint2 hv, lv;
+        __builtin_memcpy(&hv, hb, sizeof(hv));
+        __builtin_memcpy(&lv, lb, sizeof(lv));
+        *reinterpret_cast<uint2 *>(Thi + ii * ld1 + j1) = hv;
+        *reinterpret_cast<uint2 *>(Tlo + ii * ld1 + j1) = lv;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (j1 + q < n1) split_bf16(acc[q], Thi[ii * ld1 + j1 + q], Tlo[ii * ld1 + j1 + q]);
       }
     }
   }
@@ -618,7 +657,7 @@ static size_t fused21_lds(const Axis &X1, int ldw) {
 bool mfma_fused21_ok(const Handle &h) {
   const int ldw = fuse21_ldw(h);
   return h.ax[1].active && h.ax[2].active && h.ax[2].n >= 16 && ldw > 0 &&
-         32 * (ldw - 8) <= 256 * kStage && fused21_lds(h.ax[1], ldw) <= 64 * 1024 &&
+         32 * ((ldw - 8) / 8) <= 512 && fused21_lds(h.ax[1], ldw) <= 64 * 1024 &&
          (int64_t)h.ax[0].n * nblk(h.ax[2].n, kIT) < (1ll << 31);
 }
 
@@ -631,9 +670,15 @@ hipError_t launch_mfma_fused21(Handle &h, const float *in, float *out) {
   const __hip_bfloat16 *M2lo = M2hi + (int64_t)nr2 * X2.npad;
   const int ldw = fuse21_ldw(h);
   const unsigned nb2 = nblk(X2.n, kIT);
-  k_mfma_fused21<<<nb2 * (unsigned)h.ax[0].n, 256, fused21_lds(X1, ldw), h.stream>>>(
-      in, out, X1.n, X2.n, X1.npad, X2.npad, M1hi, M1lo, X1.d_klo, X1.d_knc, M2hi, M2lo, X2.d_klo,
-      X2.d_knc, ldw, (int)nb2);
+  // 16-byte row loads need rows (and the array) 16-byte aligned
+  if (X2.n % 4 == 0)
+    k_mfma_fused21<true><<<nb2 * (unsigned)h.ax[0].n, 256, fused21_lds(X1, ldw), h.stream>>>(
+        in, out, X1.n, X2.n, X1.npad, X2.npad, M1hi, M1lo, X1.d_klo, X1.d_knc, M2hi, M2lo, X2.d_klo,
+        X2.d_knc, ldw, (int)nb2);
+  else
+    k_mfma_fused21<false><<<nb2 * (unsigned)h.ax[0].n, 256, fused21_lds(X1, ldw), h.stream>>>(
+        in, out, X1.n, X2.n, X1.npad, X2.npad, M1hi, M1lo, X1.d_klo, X1.d_knc, M2hi, M2lo, X2.d_klo,
+        X2.d_knc, ldw, (int)nb2);
   return hipGetLastError();
 }
 
