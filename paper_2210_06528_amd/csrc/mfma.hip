@@ -61,8 +61,94 @@ __device__ __forceinline__ floatx4 mfma3(const bf16x8 &ahi, const bf16x8 &alo, c
 }
 
 constexpr int kIT = 32;    // columns per workgroup on the strided axes
-constexpr int kStage = 16; // staging loads per thread issued before the first wait
 constexpr int kPre = 4;    // K chunks of a tile's M fragments requested up front
+
+// Split 8 values into BF16 hi/lo and store each half as one 16-byte LDS write.
+__device__ __forceinline__ void store_split8(const float (&v)[8], __hip_bfloat16 *hi,
+                                             __hip_bfloat16 *lo) {
+  __hip_bfloat16 hb[8], lb[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) split_bf16(v[q], hb[q], lb[q]);
+  bf16x8 hv, lv;
+  __builtin_memcpy(&hv, hb, sizeof(hv));
+  __builtin_memcpy(&lv, lb, sizeof(lv));
+  *reinterpret_cast<bf16x8 *>(hi) = hv;
+  *reinterpret_cast<bf16x8 *>(lo) = lv;
+}
+
+// Stage in[j * inner + i0 + ii] (rows j < n, zeros up to npad; columns
+// ii < kIT, zeros past inner) transposed and split: Thi/Tlo[ii * ld + j].  A
+// thread takes column ii and blocks of 8 rows (the loads coalesce across the
+// kIT columns, two blocks in flight); each block is one 16-byte write per
+// half (rows ld = npad + 8 elements apart put 16 lanes' groups in distinct
+// banks).  256 threads.
+__device__ __forceinline__ void stage_transposed(const float *__restrict__ in, int64_t inner, int n,
+                                                 int npad, int64_t i0, __hip_bfloat16 *Thi,
+                                                 __hip_bfloat16 *Tlo, int ld) {
+  constexpr int BPP = 256 / kIT;   // row blocks per pass of the workgroup
+  const int ii = threadIdx.x % kIT;
+  const int nb8 = npad / 8;
+  const bool colok = i0 + ii < inner;
+  for (int b0 = threadIdx.x / kIT; b0 < nb8; b0 += 2 * BPP) {
+    float v[2][8];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int jb = b0 + hh * BPP;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = 8 * jb + q;
+        v[hh][q] = (jb < nb8 && j < n && colok) ? in[(int64_t)j * inner + i0 + ii] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int jb = b0 + hh * BPP;
+      if (jb < nb8) store_split8(v[hh], Thi + ii * ld + 8 * jb, Tlo + ii * ld + 8 * jb);
+    }
+  }
+}
+
+// Stage nl lines of in (line li at in + li * n; columns j < n, zeros up to
+// npad; lines past nl zero) split row-wise: Lhi/Llo[li * ld + j], in blocks of
+// 8 columns, two per thread in flight, 16-byte loads when VEC (rows 16-byte
+// aligned).  nt threads.
+template <bool VEC>
+__device__ __forceinline__ void stage_rows(const float *__restrict__ in, int n, int npad, int lines,
+                                           int nl, __hip_bfloat16 *Lhi, __hip_bfloat16 *Llo, int ld,
+                                           int nt) {
+  const int nbw = npad / 8, nblk = lines * nbw;
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += 2 * nt) {
+    float v[2][8];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int bi = b0 + hh * nt;
+      const int li = bi / nbw, j0 = 8 * (bi - li * nbw);
+      const bool ok = bi < nblk && li < nl;
+      const float *src = in + (int64_t)(ok ? li : 0) * n + (ok ? j0 : 0);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (VEC && ok && j0 + 4 * u + 3 < n) {
+          const float4 f = *reinterpret_cast<const float4 *>(src + 4 * u);
+          v[hh][4 * u] = f.x;
+          v[hh][4 * u + 1] = f.y;
+          v[hh][4 * u + 2] = f.z;
+          v[hh][4 * u + 3] = f.w;
+        } else {
+#pragma unroll
+          for (int q = 4 * u; q < 4 * u + 4; ++q) v[hh][q] = (ok && j0 + q < n) ? src[q] : 0.f;
+        }
+      }
+    }
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int bi = b0 + hh * nt;
+      if (bi < nblk) {
+        const int li = bi / nbw, j0 = 8 * (bi - li * nbw);
+        store_split8(v[hh], Lhi + li * ld + j0, Llo + li * ld + j0);
+      }
+    }
+  }
+}
 
 // Apply M_a (rows from global, split) to the kIT staged columns Thi/Tlo
 // ([kIT][ld], contraction index contiguous) of outer index o: OUT[o][k][i0+ii]
@@ -168,22 +254,7 @@ __global__ void __launch_bounds__(256) k_mfma_strided(const float *__restrict__ 
   __hip_bfloat16 *Thi = T, *Tlo = T + kIT * ld;
   const int64_t o = blockIdx.y;
   const int64_t i0 = (int64_t)blockIdx.x * kIT;
-  // staging: kStage loads per thread in flight before the first wait
-  for (int e0 = 0; e0 < npad * kIT; e0 += 256 * kStage) {
-    float v[kStage];
-#pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = e0 + threadIdx.x + 256 * r;
-      const int j = e / kIT, ii = e - j * kIT;
-      v[r] = (e < npad * kIT && j < n && i0 + ii < inner) ? in[(o * n + j) * inner + i0 + ii] : 0.f;
-    }
-#pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = e0 + threadIdx.x + 256 * r;
-      const int j = e / kIT, ii = e - j * kIT;
-      if (e < npad * kIT) split_bf16(v[r], Thi[ii * ld + j], Tlo[ii * ld + j]);
-    }
-  }
+  stage_transposed(in + o * n * inner, inner, n, npad, i0, Thi, Tlo, ld);
   __syncthreads();
   double dmax = 0.0;
   strided_apply<MODE>(Thi, Tlo, ld, out, pc, n, inner, npad, o, i0, Mhi, Mlo, klo, knc, dmax);
@@ -226,42 +297,7 @@ __global__ void __launch_bounds__(256) k_mfma_axis0_add(const float *__restrict_
       }
     }
   }
-  // staging: a thread takes column ii and blocks of 8 consecutive rows j (the
-  // loads coalesce across the kIT columns); each block's 8 values are split
-  // and stored as one 16-byte write per half (rows ld = npad + 8 elements
-  // apart put 16 lanes' 16-byte groups in distinct banks)
-  {
-    constexpr int BPP = 256 / kIT;   // row blocks per pass of the workgroup
-    const int ii = threadIdx.x % kIT;
-    const int nb8 = npad / 8;
-    const bool colok = i0 + ii < inner;
-    for (int b0 = threadIdx.x / kIT; b0 < nb8; b0 += 2 * BPP) {
-      float v[2][8];
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const int jb = b0 + hh * BPP;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int j = 8 * jb + q;
-          v[hh][q] = (jb < nb8 && j < n && colok) ? in[(int64_t)j * inner + i0 + ii] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const int jb = b0 + hh * BPP;
-        if (jb < nb8) {
-          __hip_bfloat16 hb[8], lb[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) split_bf16(v[hh][q], hb[q], lb[q]);
-          bf16x8 hv, lv;
-          __builtin_memcpy(&hv, hb, sizeof(hv));
-          __builtin_memcpy(&lv, lb, sizeof(lv));
-          *reinterpret_cast<bf16x8 *>(Thi + ii * ld + 8 * jb) = hv;
-          *reinterpret_cast<bf16x8 *>(Tlo + ii * ld + 8 * jb) = lv;
-        }
-      }
-    }
-  }
+  stage_transposed(in, inner, n, npad, i0, Thi, Tlo, ld);
   __syncthreads();
   double dmax = 0.0;
 #pragma unroll
@@ -322,7 +358,7 @@ __global__ void __launch_bounds__(256) k_mfma_axis0_add(const float *__restrict_
 // Contiguous axis: the array is [nlines][n] (FP32); workgroup = 16*nw lines
 // staged in LDS (split), wave w holds lines 16w..16w+15 and computes every
 // row tile of M_a for them.
-template <int MODE>
+template <int MODE, bool VEC>
 __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ in,
                                                      float *__restrict__ out,
                                                      double *__restrict__ pc, int n, int64_t nlines,
@@ -337,21 +373,7 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
   __hip_bfloat16 *Lhi = Ls, *Llo = Ls + lpw * ld;
   const int64_t l0 = (int64_t)blockIdx.x * lpw;
   const int nt = blockDim.x;
-  for (int e0 = 0; e0 < npad * lpw; e0 += nt * kStage) {
-    float v[kStage];
-#pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = e0 + threadIdx.x + nt * r;
-      const int li = e / npad, j = e - li * npad;
-      v[r] = (e < npad * lpw && j < n && l0 + li < nlines) ? in[(l0 + li) * n + j] : 0.f;
-    }
-#pragma unroll
-    for (int r = 0; r < kStage; ++r) {
-      const int e = e0 + threadIdx.x + nt * r;
-      const int li = e / npad, j = e - li * npad;
-      if (e < npad * lpw) split_bf16(v[r], Lhi[li * ld + j], Llo[li * ld + j]);
-    }
-  }
+  stage_rows<VEC>(in + l0 * n, n, npad, lpw, (int)min((int64_t)lpw, nlines - l0), Lhi, Llo, ld, nt);
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
@@ -694,12 +716,19 @@ hipError_t launch_mfma_correct(Handle &h, int axis, const float *in, float *out,
     const size_t lds = sizeof(__hip_bfloat16) * 2 * (size_t)lpw * (X.npad + 8);
     const unsigned grid = nblk(nlines, lpw);
     const int threads = 4 * lpw;
-    if (add)
-      k_mfma_contig<1><<<grid, threads, lds, h.stream>>>(in, out, h.P, n, nlines, X.npad, Mhi, Mlo,
-                                                         X.d_klo, X.d_knc, h.slots);
-    else
-      k_mfma_contig<0><<<grid, threads, lds, h.stream>>>(in, out, h.P, n, nlines, X.npad, Mhi, Mlo,
-                                                         X.d_klo, X.d_knc, h.slots);
+    // 16-byte row loads need rows 16-byte aligned
+#define MFA_MC(M, V)                                                                             \
+  k_mfma_contig<M, V><<<grid, threads, lds, h.stream>>>(in, out, h.P, n, nlines, X.npad, Mhi, Mlo, \
+                                                        X.d_klo, X.d_knc, h.slots)
+    const bool vec = n % 4 == 0;
+    if (add) {
+      if (vec) MFA_MC(1, true);
+      else MFA_MC(1, false);
+    } else {
+      if (vec) MFA_MC(0, true);
+      else MFA_MC(0, false);
+    }
+#undef MFA_MC
   } else {
     const int64_t outer = axis == 0 ? 1 : h.ax[0].n;
     const int64_t inner = axis == 0 ? (int64_t)h.ax[1].n * h.ax[2].n : h.ax[2].n;
