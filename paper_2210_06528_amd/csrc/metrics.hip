@@ -9,6 +9,8 @@
 //                  axes (Omega_b, Omega_c) and reduce max |.| per order.
 #include <hip/hip_bf16.h>
 
+#include <type_traits>
+
 #include "mfa_internal.hpp"
 
 namespace mfa {
@@ -27,7 +29,6 @@ __device__ __forceinline__ double tod(double v) { return v; }
 __device__ __forceinline__ double tod(float v) { return (double)v; }
 __device__ __forceinline__ double tod(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
 
-constexpr int kStageM = 8;   // staging loads per thread issued before the first wait
 
 struct DTab {
   const int *len;
@@ -279,29 +280,32 @@ __global__ void __launch_bounds__(256) k_jump_project_inner(const TG *__restrict
 // Interface projection along the contiguous axis: a workgroup stages LPB
 // whole grid lines of g in LDS (one coalesced read) and computes every
 // (line, interface) pair, all orders from one pass over the interface's
-// support.
-template <typename TG>
+// support.  The lines are staged in SG, float for a float or BF16 residual
+// (its values exactly) and double otherwise.
+template <typename TG, typename SG>
 __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict__ g,
                                                             double *__restrict__ U, int64_t nlines,
                                                             int n2, int nif, int p, int LPB,
                                                             const int *__restrict__ Jcol,
                                                             const int *__restrict__ Jlen,
                                                             const double *__restrict__ Jval, int LJ) {
-  extern __shared__ double sg[];   // [LPB][n2], then the J rows [nif*p][LJ]
-  double *sJ = sg + (size_t)LPB * n2;
+  extern __shared__ double smem_j[];
+  double *sJ = smem_j;                                  // the J rows [nif*p][LJ]
+  SG *sg = reinterpret_cast<SG *>(sJ + (size_t)nif * p * LJ);   // [LPB][n2]
   const int64_t l0 = (int64_t)blockIdx.x * LPB;
   const int nl = (int)min((int64_t)LPB, nlines - l0);
   for (int e = threadIdx.x; e < nif * p * LJ; e += blockDim.x) sJ[e] = Jval[e];
   const TG *src = g + l0 * n2;
-  for (int e0 = 0; e0 < nl * n2; e0 += blockDim.x * kStageM) {
-    double v[kStageM];
+  // 16 loads per thread in flight before the first store
+  for (int e0 = 0; e0 < nl * n2; e0 += blockDim.x * 16) {
+    SG v[16];
 #pragma unroll
-    for (int u = 0; u < kStageM; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int e = e0 + threadIdx.x + blockDim.x * u;
-      v[u] = e < nl * n2 ? tod(src[e]) : 0.0;
+      v[u] = e < nl * n2 ? (SG)tod(src[e]) : SG(0);
     }
 #pragma unroll
-    for (int u = 0; u < kStageM; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int e = e0 + threadIdx.x + blockDim.x * u;
       if (e < nl * n2) sg[e] = v[u];
     }
@@ -312,7 +316,7 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
     const int row0 = b * p;
     const int c0 = Jcol[(int64_t)row0 * LJ];
     const int len = Jlen[row0];
-    const double *x = sg + li * n2 + c0;
+    const SG *x = sg + li * n2 + c0;
     double acc[kMaxP];
 #pragma unroll
     for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
@@ -552,8 +556,11 @@ hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U) {
   const size_t jbytes = sizeof(double) * (size_t)(X.B - 1) * h.p * X.J.L;
   if (a == 2 && (int64_t)X.n * 8 <= 32768 && jbytes <= 16384) {
     const int64_t nlines = (int64_t)h.ax[0].n * h.ax[1].n;
-    const int LPB = std::max(1, std::min(32, 32768 / (8 * X.n)));
-    k_jump_project_lines<TG><<<nblk(nlines, LPB), 256, sizeof(double) * LPB * X.n + jbytes, h.stream>>>(
+    // staged lines: float for a float or BF16 residual (exact), else double;
+    // up to 32 KB of them per workgroup
+    using SG = typename std::conditional<sizeof(TG) <= 4, float, double>::type;
+    const int LPB = std::max(1, std::min(64, 32768 / ((int)sizeof(SG) * X.n)));
+    k_jump_project_lines<TG, SG><<<nblk(nlines, LPB), 256, sizeof(SG) * LPB * X.n + jbytes, h.stream>>>(
         g, U, nlines, X.n, X.B - 1, h.p, LPB, X.J.col, X.J.len, X.J.val, X.J.L);
     return hipGetLastError();
   }
