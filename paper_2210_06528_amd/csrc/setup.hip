@@ -74,11 +74,18 @@ __device__ void basis_deriv(double u, int s, int n, int p, int r, double *out) {
   for (int q = 0; q <= p; ++q) out[q] = v[q];
 }
 
-// One thread per data point: span and r-th derivative basis row, written as
-// the ELL decode table (columns span-p..span).
-__global__ void k_basis(int64_t m, int n, int p, int r, int *span_out, Ell tab) {
+// One thread per data point and derivative order r = blockIdx.y (0..p):
+// span and r-th derivative basis row, written as the ELL decode table of
+// that order (columns span-p..span); order 0 also writes the span.
+struct EllSet {
+  Ell t[kMaxP + 1];
+};
+__global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
+  const int r = blockIdx.y;
+  const Ell &tab = tabs.t[r];
+  if (r != 0) span_out = nullptr;
   int64_t s = p + (i * (n - p)) / (m - 1);
   if (s > n - 1) s = n - 1;
   const double u = (double)i / (double)(m - 1);
@@ -725,9 +732,12 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
   const int p = h->p, n = X.n, B = X.B, nif = B - 1;
   const int64_t m = X.m;
 
-  // basis values and derivative tables at the data points
-  for (int r = 0; r <= p; ++r) {
-    k_basis<<<nblk(m, 256), 256, 0, st>>>(m, n, p, r, r == 0 ? X.d_span : nullptr, X.N[r]);
+  // basis values and derivative tables at the data points, all orders in one
+  // launch
+  {
+    EllSet tabs;
+    for (int r = 0; r <= p; ++r) tabs.t[r] = X.N[r];
+    k_basis<<<dim3(nblk(m, 256), p + 1), 256, 0, st>>>(m, n, p, X.d_span, tabs);
     MFA_TRY(hipGetLastError());
   }
   X.d_bas = X.N[0].val;
