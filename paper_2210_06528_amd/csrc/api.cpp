@@ -520,7 +520,6 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
       if ((e = hipStreamWaitEvent(st, aux->fork, 0)) != hipSuccess) return bail(e, "fork");
     }
     if ((e = setup_axis(&h, a, st)) != hipSuccess) return bail(e, "setup");
-    if ((e = setup_acoef(&h, a, st)) != hipSuccess) return bail(e, "setup");
     if (h.precision == MFA_PREC_MIXED_BF16 && (e = setup_mfma(&h, a, st)) != hipSuccess)
       return bail(e, "setup");
     if (used > 0) {

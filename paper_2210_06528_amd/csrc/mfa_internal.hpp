@@ -200,8 +200,6 @@ hipError_t upload_plan(Handle *h);
 hipError_t launch_decode_points(Handle &h, const double *u, int64_t npts, void *out, bool f32,
                                 const int r[3]);
 hipError_t setup_axis(Handle *h, int a, hipStream_t st);
-// stencil rows of A for the residual kernel (identity row for inactive axes)
-hipError_t setup_acoef(Handle *h, int a, hipStream_t st);
 
 // sweep kernels
 template <typename TG>

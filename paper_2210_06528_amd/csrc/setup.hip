@@ -311,7 +311,7 @@ __device__ __forceinline__ void pad_row(Ell &t, int64_t r, int len) {
 }
 
 // N^T: row k lists the data points whose span lies in [k, k+p].
-__global__ void k_tab_NT(int64_t m, int n, int p, const int *span, Ell basis, Ell t) {
+__device__ __forceinline__ void tab_NT(int64_t m, int n, int p, const int *span, Ell basis, Ell t) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int64_t lo = d_first_with_span_ge(max(k, p), m, n, p);
@@ -326,7 +326,7 @@ __global__ void k_tab_NT(int64_t m, int n, int p, const int *span, Ell basis, El
 }
 
 // A = N^T N as rows: columns k-p..k+p from the band.
-__global__ void k_tab_A(int n, int p, const double *band, Ell t) {
+__device__ __forceinline__ void tab_A(int n, int p, const double *band, Ell t) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int len = 0;
@@ -341,7 +341,7 @@ __global__ void k_tab_A(int n, int p, const double *band, Ell t) {
 // Weighted additive-Schwarz operator of one axis:
 // M[k][:] = sum over blocks b whose free set holds k of w_k Z_b[k - F0_b][:],
 // w_k = 1/n_s(k) (combine AVG) or the owner indicator (combine RAS).
-__global__ void __launch_bounds__(64) k_tab_M(int n, int combine, const int *blk, const int *blo,
+__device__ __forceinline__ void tab_M(int n, int combine, const int *blk, const int *blo,
                                               const int *bhi, const int *owner, const int *ns,
                                               const double *inv, Ell t) {
   // one wavefront per row, lanes over its columns (each entry written once)
@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(64) k_tab_M(int n, int combine, const int *blk
 // Decode of a subdomain's local correction at its owned data points:
 // Om[i][:] = sum_q N_{s-p+q}(u_i) Z_b[s-p+q - F0_b][:] over the free set of the
 // block b that owns point i (basis functions outside F_b carry no correction).
-__global__ void __launch_bounds__(64) k_tab_Om(int64_t m, int p, const int *blk, const int *pown,
+__device__ __forceinline__ void tab_Om(int64_t m, int p, const int *blk, const int *pown,
                                                const int *span, Ell basis, const double *inv, Ell t) {
   // one wavefront per data point, lanes over the free set of its owner
   const int64_t i = blockIdx.x;
@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(64) k_tab_Om(int64_t m, int p, const int *blk,
 
 // Interface jump functionals: row (b, r) maps a residual line to
 // d^r/du^r (L_b - L_{b+1})(u*_b) = dB_r(u*)^T (E_b Z_b R_b - E_{b+1} Z_{b+1} R_{b+1}).
-__global__ void __launch_bounds__(64) k_tab_J(int nif, int p, const int *blk, const int *span_if,
+__device__ __forceinline__ void tab_J(int nif, int p, const int *blk, const int *span_if,
                                               const double *dbas, const double *inv, Ell t, int *gid) {
   // one wavefront per row (b, r), lanes over its columns
   const int row = blockIdx.x;
@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(64) k_tab_J(int nif, int p, const int *blk, co
 // Derivative-coefficient operator: rows of D^r for r = 0..p-1 stacked; row k
 // of D^r gives the r-th derivative control coefficient
 //   D^r_k = (p-r+1)/(t_{k+p+1} - t_{k+r}) (D^{r-1}_{k+1} - D^{r-1}_k),  D^0 = P.
-__global__ void k_tab_D(int n, int p, Ell t, int *gid) {
+__device__ __forceinline__ void tab_D(int n, int p, Ell t, int *gid) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   int r = 0, base = 0;
   while (r < p && row >= base + (n - r)) {
@@ -611,7 +611,7 @@ __global__ void k_transpose_vals(const double *val, int64_t rows, int L, double 
 }
 
 // stencil rows: acoef[k*(2p+1) + t] = A[k][k-p+t], zero outside the matrix
-__global__ void k_acoef(int n, int p, const double *band, double *acoef) {
+__device__ __forceinline__ void tab_acoef(int n, int p, const double *band, double *acoef) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   for (int t = 0; t <= 2 * p; ++t) {
@@ -619,6 +619,41 @@ __global__ void k_acoef(int n, int p, const double *band, double *acoef) {
     double v = 0.0;
     if (c >= 0 && c < n) v = band[(int64_t)abs(k - c) * n + min(k, c)];
     acoef[(int64_t)k * (2 * p + 1) + t] = v;
+  }
+}
+
+// The row tables that need only the basis rows and the normal-matrix band,
+// in one launch (a thread per row, blockIdx.y the table): N^T, A, the
+// derivative operators D and the residual stencil rows.
+__global__ void k_tab_rows(int64_t m, int n, int p, const int *span, Ell basis, Ell NT,
+                           const double *band, Ell A, Ell D, int *gidD, double *acoef) {
+  switch (blockIdx.y) {
+    case 0: tab_NT(m, n, p, span, basis, NT); break;
+    case 1: tab_A(n, p, band, A); break;
+    case 2: tab_D(n, p, D, gidD); break;
+    default: tab_acoef(n, p, band, acoef); break;
+  }
+}
+
+// The operators built from the local inverses, in one launch (a wavefront
+// per row, blockIdx.y the table): M (n rows), Om (m data points) and the
+// interface functionals J (nif * p rows, none with one block).
+__global__ void __launch_bounds__(64) k_tab_ops(int64_t m, int n, int p, int combine, int nif,
+                                                const int *blk, const int *blo, const int *bhi,
+                                                const int *owner, const int *ns, const int *pown,
+                                                const int *span, Ell basis, const double *inv,
+                                                const int *span_if, const double *dbas_if, Ell M,
+                                                Ell Om, Ell J, int *gidJ) {
+  switch (blockIdx.y) {
+    case 0:
+      if (blockIdx.x < (unsigned)n) tab_M(n, combine, blk, blo, bhi, owner, ns, inv, M);
+      break;
+    case 1:
+      if (blockIdx.x < (uint64_t)m) tab_Om(m, p, blk, pown, span, basis, inv, Om);
+      break;
+    default:
+      if (blockIdx.x < (unsigned)(nif * p)) tab_J(nif, p, blk, span_if, dbas_if, inv, J, gidJ);
+      break;
   }
 }
 
@@ -672,12 +707,6 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 
 }  // namespace
 
-hipError_t setup_acoef(Handle *h, int ia, hipStream_t st) {
-  Axis &X = h->ax[ia];
-  if (!X.active) return hipSuccess;   // identity row, uploaded with the plan
-  k_acoef<<<nblk(X.n, 128), 128, 0, st>>>(X.n, h->p, X.d_gram, X.d_acoef);
-  return hipGetLastError();
-}
 
 #define MFA_TRY(x)                       \
   do {                                   \
@@ -747,6 +776,10 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
   }
   k_gram<<<n, 64, 0, st>>>(m, n, p, X.d_span, X.N[0], X.d_gram);
   MFA_TRY(hipGetLastError());
+  // N^T, A, D and the stencil rows (they need the basis rows and the band)
+  k_tab_rows<<<dim3(nblk(std::max<int64_t>(n, X.ND), 128), 4), 128, 0, st>>>(
+      m, n, p, X.d_span, X.N[0], X.NT, X.d_gram, X.A, X.D, X.d_gidD, X.d_acoef);
+  MFA_TRY(hipGetLastError());
   const size_t chol_lds = sizeof(double) * (p + 1) * X.Fmax;
   if (chol_lds <= 64 * 1024)
     k_chol<<<B, 64, chol_lds, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
@@ -759,16 +792,15 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
   else
     k_inverse_global<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
   MFA_TRY(hipGetLastError());
-  k_tab_NT<<<nblk(n, 128), 128, 0, st>>>(m, n, p, X.d_span, X.N[0], X.NT);
-  k_tab_A<<<nblk(n, 128), 128, 0, st>>>(n, p, X.d_gram, X.A);
-  k_tab_M<<<n, 64, 0, st>>>(n, h->combine, X.d_blk, X.d_blo, X.d_bhi, X.d_owner, X.d_ns,
-                                      X.d_inv, X.M);
-  k_tab_Om<<<(unsigned)m, 64, 0, st>>>(m, p, X.d_blk, X.d_pown, X.d_span, X.N[0], X.d_inv, X.Om);
+  // M, Om and J (they need the local inverses)
+  {
+    const int64_t gx = std::max<int64_t>(std::max<int64_t>(n, m), (int64_t)nif * p);
+    k_tab_ops<<<dim3((unsigned)gx, nif > 0 ? 3 : 2), 64, 0, st>>>(
+        m, n, p, h->combine, nif, X.d_blk, X.d_blo, X.d_bhi, X.d_owner, X.d_ns, X.d_pown, X.d_span,
+        X.N[0], X.d_inv, X.d_span_if, X.d_dbas_if, X.M, X.Om, X.J, X.d_gidJ);
+    MFA_TRY(hipGetLastError());
+  }
   k_transpose_vals<<<nblk(m * X.Om.L, 256), 256, 0, st>>>(X.Om.val, m, X.Om.L, X.d_omT);
-  if (nif > 0)
-    k_tab_J<<<nif * p, 64, 0, st>>>(nif, p, X.d_blk, X.d_span_if, X.d_dbas_if,
-                                                       X.d_inv, X.J, X.d_gidJ);
-  k_tab_D<<<nblk(X.ND, 128), 128, 0, st>>>(n, p, X.D, X.d_gidD);
   MFA_TRY(hipGetLastError());
   if (h->rhs == MFA_RHS_DATABOX) {
     k_tab_Nseg<<<nblk(X.SD, 128), 128, 0, st>>>(p, B, X.d_blk, nullptr, X.N[0], X.Nseg, X.d_qmap);
