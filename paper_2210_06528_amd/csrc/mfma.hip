@@ -575,9 +575,9 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
 }
 
 // dense split-BF16 copy of M_a (rows padded to a multiple of 16 with zeros,
-// columns to npad) from its float64 row table
-__global__ void k_tab_Mbf16(int n, int nrows, int npad, Ell M, __hip_bfloat16 *Mhi,
-                            __hip_bfloat16 *Mlo) {
+// columns to npad) from its float64 row table; one workgroup per row
+__device__ __forceinline__ void tab_Mbf16(int n, int nrows, int npad, Ell M, __hip_bfloat16 *Mhi,
+                                          __hip_bfloat16 *Mlo) {
   const int k = blockIdx.x;
   if (k >= nrows) return;
   for (int j = threadIdx.x; j < npad; j += blockDim.x) {
@@ -597,8 +597,8 @@ __global__ void k_tab_Mbf16(int n, int nrows, int npad, Ell M, __hip_bfloat16 *M
 }
 
 // K range of every 16-row tile: [lo, lo + 32*nc) covers the band of its rows,
-// lo a multiple of 8 (16-byte aligned fragments)
-__global__ void k_tab_ktiles(int n, Ell M, int *klo, int *knc) {
+// lo a multiple of 8 (16-byte aligned fragments); one thread per tile
+__device__ __forceinline__ void tab_ktiles(int n, Ell M, int *klo, int *knc) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (n + 15) / 16) return;
   int lo = 1 << 30, hi = 0;
@@ -610,6 +610,15 @@ __global__ void k_tab_ktiles(int n, Ell M, int *klo, int *knc) {
   lo &= ~7;
   klo[t] = lo;
   knc[t] = (hi - lo + 31) / 32;
+}
+
+// both tables in one launch (blockIdx.y: the BF16 rows, the tile K ranges)
+__global__ void k_tab_mfma(int n, int nrows, int npad, Ell M, __hip_bfloat16 *Mhi, __hip_bfloat16 *Mlo,
+                           int *klo, int *knc) {
+  if (blockIdx.y == 0)
+    tab_Mbf16(n, nrows, npad, M, Mhi, Mlo);
+  else
+    tab_ktiles(n, M, klo, knc);
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -633,8 +642,8 @@ hipError_t setup_mfma(Handle *h, int ia, hipStream_t st) {
   const int nrows = (X.n + 15) / 16 * 16;
   __hip_bfloat16 *Mhi = reinterpret_cast<__hip_bfloat16 *>(X.d_Mb);
   __hip_bfloat16 *Mlo = Mhi + (int64_t)nrows * X.npad;
-  k_tab_Mbf16<<<nrows, 128, 0, st>>>(X.n, nrows, X.npad, X.M, Mhi, Mlo);
-  k_tab_ktiles<<<nblk((X.n + 15) / 16, 64), 64, 0, st>>>(X.n, X.M, X.d_klo, X.d_knc);
+  k_tab_mfma<<<dim3(std::max<unsigned>(nrows, nblk((X.n + 15) / 16, 128)), 2), 128, 0, st>>>(
+      X.n, nrows, X.npad, X.M, Mhi, Mlo, X.d_klo, X.d_knc);
   return hipGetLastError();
 }
 

@@ -76,12 +76,22 @@ __device__ void basis_deriv(double u, int s, int n, int p, int r, double *out) {
 
 // One thread per data point and derivative order r = blockIdx.y (0..p):
 // span and r-th derivative basis row, written as the ELL decode table of
-// that order (columns span-p..span); order 0 also writes the span.
+// that order (columns span-p..span); order 0 also writes the span.  The
+// slice blockIdx.y = p + 1 evaluates the derivatives of orders 0..p-1 at the
+// interface parameters u*_b (nif * p threads).
 struct EllSet {
   Ell t[kMaxP + 1];
 };
-__global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs) {
+__global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs, int nif,
+                        const double *ustar, const int *span_if, double *dbas_if) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int)blockIdx.y == p + 1) {
+    if (i < (int64_t)nif * p) {
+      const int b = (int)(i / p), r = (int)(i % p);
+      basis_deriv(ustar[b], span_if[b], n, p, r, dbas_if + i * (p + 1));
+    }
+    return;
+  }
   if (i >= m) return;
   const int r = blockIdx.y;
   const Ell &tab = tabs.t[r];
@@ -99,14 +109,6 @@ __global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs) {
   }
 }
 
-// Derivatives of orders 0..p-1 at each interface parameter u*_b.
-__global__ void k_basis_if(int nif, int n, int p, const double *ustar, const int *span_if,
-                           double *out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nif * p) return;
-  const int b = t / p, r = t % p;
-  basis_deriv(ustar[b], span_if[b], n, p, r, out + (int64_t)t * (p + 1));
-}
 
 // Banded normal matrix A = N^T N of one axis, lower band storage
 // band[t*n + k] = A[k+t][k].  One wavefront per row k: the lanes stride over
@@ -371,7 +373,8 @@ __device__ __forceinline__ void tab_M(int n, int combine, const int *blk, const 
 // Om[i][:] = sum_q N_{s-p+q}(u_i) Z_b[s-p+q - F0_b][:] over the free set of the
 // block b that owns point i (basis functions outside F_b carry no correction).
 __device__ __forceinline__ void tab_Om(int64_t m, int p, const int *blk, const int *pown,
-                                               const int *span, Ell basis, const double *inv, Ell t) {
+                                               const int *span, Ell basis, const double *inv, Ell t,
+                                               double *valT) {
   // one wavefront per data point, lanes over the free set of its owner
   const int64_t i = blockIdx.x;
   const int lane = threadIdx.x;
@@ -389,6 +392,7 @@ __device__ __forceinline__ void tab_Om(int64_t m, int p, const int *blk, const i
     }
     t.col[i * t.L + c] = c < F ? F0 + c : F0 + F - 1;
     t.val[i * t.L + c] = acc;
+    valT[(int64_t)c * m + i] = acc;   // the values transposed: valT[c*m + i]
   }
   if (lane == 0) t.len[i] = F;
 }
@@ -603,12 +607,6 @@ __global__ void k_tab_Comb(int n, int combine, const int *blk, const int *blo, c
   pad_row(t, k, len);
 }
 
-__global__ void k_transpose_vals(const double *val, int64_t rows, int L, double *valT) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows * L) return;
-  const int64_t r = i / L, t = i - r * L;
-  valT[t * rows + r] = val[i];
-}
 
 // stencil rows: acoef[k*(2p+1) + t] = A[k][k-p+t], zero outside the matrix
 __device__ __forceinline__ void tab_acoef(int n, int p, const double *band, double *acoef) {
@@ -636,20 +634,21 @@ __global__ void k_tab_rows(int64_t m, int n, int p, const int *span, Ell basis, 
 }
 
 // The operators built from the local inverses, in one launch (a wavefront
-// per row, blockIdx.y the table): M (n rows), Om (m data points) and the
-// interface functionals J (nif * p rows, none with one block).
+// per row, blockIdx.y the table): M (n rows), Om (m data points, with its
+// values also written transposed) and the interface functionals J (nif * p
+// rows, none with one block).
 __global__ void __launch_bounds__(64) k_tab_ops(int64_t m, int n, int p, int combine, int nif,
                                                 const int *blk, const int *blo, const int *bhi,
                                                 const int *owner, const int *ns, const int *pown,
                                                 const int *span, Ell basis, const double *inv,
                                                 const int *span_if, const double *dbas_if, Ell M,
-                                                Ell Om, Ell J, int *gidJ) {
+                                                Ell Om, double *omT, Ell J, int *gidJ) {
   switch (blockIdx.y) {
     case 0:
       if (blockIdx.x < (unsigned)n) tab_M(n, combine, blk, blo, bhi, owner, ns, inv, M);
       break;
     case 1:
-      if (blockIdx.x < (uint64_t)m) tab_Om(m, p, blk, pown, span, basis, inv, Om);
+      if (blockIdx.x < (uint64_t)m) tab_Om(m, p, blk, pown, span, basis, inv, Om, omT);
       break;
     default:
       if (blockIdx.x < (unsigned)(nif * p)) tab_J(nif, p, blk, span_if, dbas_if, inv, J, gidJ);
@@ -766,14 +765,12 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
   {
     EllSet tabs;
     for (int r = 0; r <= p; ++r) tabs.t[r] = X.N[r];
-    k_basis<<<dim3(nblk(m, 256), p + 1), 256, 0, st>>>(m, n, p, X.d_span, tabs);
+    const unsigned gx = nblk(std::max<int64_t>(m, (int64_t)nif * p), 256);
+    k_basis<<<dim3(gx, nif > 0 ? p + 2 : p + 1), 256, 0, st>>>(m, n, p, X.d_span, tabs, nif, X.d_ustar,
+                                                                 X.d_span_if, X.d_dbas_if);
     MFA_TRY(hipGetLastError());
   }
   X.d_bas = X.N[0].val;
-  if (nif > 0) {
-    k_basis_if<<<nblk((int64_t)nif * p, 64), 64, 0, st>>>(nif, n, p, X.d_ustar, X.d_span_if, X.d_dbas_if);
-    MFA_TRY(hipGetLastError());
-  }
   k_gram<<<n, 64, 0, st>>>(m, n, p, X.d_span, X.N[0], X.d_gram);
   MFA_TRY(hipGetLastError());
   // N^T, A, D and the stencil rows (they need the basis rows and the band)
@@ -797,11 +794,9 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
     const int64_t gx = std::max<int64_t>(std::max<int64_t>(n, m), (int64_t)nif * p);
     k_tab_ops<<<dim3((unsigned)gx, nif > 0 ? 3 : 2), 64, 0, st>>>(
         m, n, p, h->combine, nif, X.d_blk, X.d_blo, X.d_bhi, X.d_owner, X.d_ns, X.d_pown, X.d_span,
-        X.N[0], X.d_inv, X.d_span_if, X.d_dbas_if, X.M, X.Om, X.J, X.d_gidJ);
+        X.N[0], X.d_inv, X.d_span_if, X.d_dbas_if, X.M, X.Om, X.d_omT, X.J, X.d_gidJ);
     MFA_TRY(hipGetLastError());
   }
-  k_transpose_vals<<<nblk(m * X.Om.L, 256), 256, 0, st>>>(X.Om.val, m, X.Om.L, X.d_omT);
-  MFA_TRY(hipGetLastError());
   if (h->rhs == MFA_RHS_DATABOX) {
     k_tab_Nseg<<<nblk(X.SD, 128), 128, 0, st>>>(p, B, X.d_blk, nullptr, X.N[0], X.Nseg, X.d_qmap);
     k_tab_NsegT<<<nblk(X.SF, 128), 128, 0, st>>>(m, n, p, B, X.d_blk, X.d_span, X.N[0], X.NsegT);
