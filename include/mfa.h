@@ -19,10 +19,14 @@
  *    nctrl[0] x ... x nctrl[dim-1].
  *  - Pointers named *_dev are HIP device pointers on the device that was
  *    current when mfa_create ran; pointers named *_host are host memory.
- *  - All work is enqueued on the HIP stream given to mfa_create.  Calls return
- *    when the work is enqueued unless stated otherwise; mfa_create,
- *    mfa_encode (to read the convergence metrics) and mfa_schwarz_step (to
- *    fill its statistics) synchronise the stream before returning.
+ *  - All work is ordered on the HIP stream given to mfa_create.  Independent
+ *    parts of the setup and of a convergence check run on two auxiliary
+ *    streams the library keeps per host thread and device (default priority),
+ *    forked from that stream with an event and joined back to it before any
+ *    later work on it.  Calls return when the work is enqueued unless stated
+ *    otherwise; mfa_create, mfa_encode (to read the convergence metrics) and
+ *    mfa_schwarz_step (to fill its statistics) synchronise the stream before
+ *    returning.
  *  - The caller owns every buffer passed in, including the workspace; the
  *    library never allocates device memory.  It must outlive the handle.
  *  - Errors: every entry point returns an mfa_status; on failure
@@ -120,8 +124,9 @@ mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes);
  * data point (Section 2.1), assemble the banded per-axis normal matrices
  * N_a^T N_a with wavefront reductions, factor every subdomain's local normal
  * matrix with a batched banded Cholesky (Section 2.3.1) and build the
- * per-axis Schwarz operators; everything runs on `hip_stream` (a hipStream_t,
- * or NULL for the default stream).  `workspace` is a device buffer of at
+ * per-axis Schwarz operators; everything is ordered on `hip_stream` (a
+ * hipStream_t, or NULL for the default stream; the three axes' setup runs
+ * concurrently on it and two auxiliary streams).  `workspace` is a device buffer of at
  * least mfa_workspace_size bytes, 256-byte aligned.  Synchronises the stream.
  * Returns MFA_ESINGULAR when a local normal matrix is not positive definite.
  * On success *out owns no memory but the small host-side handle.           */
