@@ -10,6 +10,12 @@
 // its band.  The residual feeding these passes is the float64 residual of the
 // normal equations rounded to FP32, so the sweep is an iterative refinement on
 // the float64 residual.
+//
+// In 3-D the axis-2 and axis-1 passes run as one kernel (k_mfma_fused21)
+// whose intermediate stays in LDS; the axis-0 pass adds into the control
+// points.  Every pass stages its input in LDS split into BF16 halves, eight
+// values per 16-byte store (a 2-byte store per value made the staging
+// LDS-bank-bound), so that an MFMA operand fragment is one 16-byte read.
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
