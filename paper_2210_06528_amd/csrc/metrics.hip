@@ -444,7 +444,9 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
       if (e < LYY * LXX) tile[r][c] = (bin && ((tmask >> u) & 1)) ? buf[u] : 0.0;
     }
     __syncthreads();
-    gload(buf, bin, k0 + 2);
+    // past the chunk's last plane the prefetch re-reads that plane (cache hits,
+    // never used) instead of the next chunk's planes
+    gload(buf, bin, min(k0 + 2, k0b + H - 1));
     const bool own = k0 < k0b;
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
