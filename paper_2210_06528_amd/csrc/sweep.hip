@@ -497,12 +497,15 @@ __global__ void __launch_bounds__(MAXF >= 64 ? 256 : 1024) k_bsolve_seg(const TI
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// x-chunk of the residual stencil for a target number of workgroups (each
-// chunk re-reads 2p halo planes; more workgroups fill the chip better)
+// x-chunk of the residual stencil for at most `target` workgroups: the
+// number of chunks is chosen first (the most that keeps byz x chunks within
+// the target, each chunk at least 4 planes) and the planes are then spread
+// evenly over them.  Each chunk re-reads 2p halo planes; a target of twice
+// the CU count lets two workgroups share every CU without a third one
+// lengthening some CU's queue.
 inline int resid_xchunk(int n0, int byz, int target) {
-  int xchunk = n0;
-  if (byz < target) xchunk = std::max(4, (int)((int64_t)n0 * byz / target));
-  return std::min(xchunk, n0);
+  const int nch = std::max(1, std::min(target / byz, n0 / 4));
+  return (n0 + nch - 1) / nch;
 }
 
 // Autotuned x-chunk per shape.  The residual is idempotent (it reads P and c
@@ -542,15 +545,17 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
     return hipGetLastError();
   };
   if (xchunk == 0) {
-    // default: about 256 workgroups (one per CU, x-chunks of 48 planes on
-    // 256 x 256 x 192: 4.5% faster than 384 in an alternating A/B, fewer
-    // halo planes re-read), 768 for small shapes
+    // default: at most 512 workgroups, two per CU (on 256 x 256 x 192
+    // control points: 10 chunks of 26 planes, 480 workgroups, 8% less
+    // time than 5 chunks of 48 planes plus one of 16, and 25% less than 6
+    // even chunks of 43 planes, which put two long chunks on 32 CUs), 768
+    // for small shapes
     const int64_t nctrl = (int64_t)n0 * n1 * n2;
-    const int xdef = resid_xchunk(n0, byz, nctrl >= kTuneMinCtrl ? 256 : 768);
+    const int xdef = resid_xchunk(n0, byz, nctrl >= kTuneMinCtrl ? 512 : 768);
     xchunk = xdef;
     if (nctrl >= kTuneMinCtrl) {
       std::vector<int> cand{xdef};
-      for (int target : {384, 512, 768, 1024, 1536}) {
+      for (int target : {256, 384, 768, 1024, 1536}) {
         const int xc = resid_xchunk(n0, byz, target);
         if (std::find(cand.begin(), cand.end(), xc) == cand.end()) cand.push_back(xc);
       }
