@@ -143,50 +143,78 @@ __global__ void __launch_bounds__(64) k_gram(int64_t m, int n, int p, const int 
 }
 
 // Batched banded Cholesky of every subdomain's local normal matrix
-// A[F0:F1, F0:F1] (a principal block of the axis' band; Section 2.3.1).
-// One wavefront per matrix, the factor built in LDS and written out once:
-// lane 0 forms the pivot of column j, lanes 1..p the subdiagonal entries.
-// A non-positive pivot sets flag[0].
-__global__ void __launch_bounds__(64) k_chol(int n, int p, const double *band, const int *blk,
+// A[F0:F1, F0:F1] (a principal block of the axis' band; Section 2.3.1), for
+// degree PP.  A wavefront per matrix stages the block's band in LDS (entries
+// past the block read as zero); one lane then forms the columns in order,
+// keeping the last PP columns of L in registers, so a column costs a square
+// root, a division and O(PP^2) register products with no LDS round trip on
+// its chain.  A non-positive pivot sets flag[0].
+template <int PP>
+__global__ void __launch_bounds__(64) k_chol(int n, const double *band, const int *blk,
                                              double *chol, double *rdiag, int *flag) {
-  extern __shared__ double Ls[];   // Ls[t*F + j] = L(j+t, j)
+  extern __shared__ double As[];   // As[t*F + j] = A(j+t, j)
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
   int64_t off = 0, roff = 0;
   for (int bb = 0; bb < b; ++bb) {
-    off += (int64_t)(p + 1) * (blk[8 * bb + 3] - blk[8 * bb + 2]);
+    off += (int64_t)(PP + 1) * (blk[8 * bb + 3] - blk[8 * bb + 2]);
     roff += blk[8 * bb + 3] - blk[8 * bb + 2];
   }
   const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
-  for (int j = 0; j < F; ++j) {
-    if (lane == 0) {
-      const double ajj = band[F0 + j];
-      double s = ajj;
-      for (int k = max(0, j - p); k < j; ++k) {
-        const double l = Ls[(j - k) * F + k];
-        s -= l * l;
-      }
-      if (!(s > 1e-13 * ajj) || !(s > 0.0)) {
-        atomicOr(flag, 1);
-        s = 1.0;
-      }
-      Ls[j] = sqrt(s);
-    }
-    __syncthreads();
-    if (lane >= 1 && lane <= p) {
-      const int i = j + lane;
-      if (i < F) {
-        double s = band[(int64_t)lane * n + F0 + j];
-        for (int k = max(0, i - p); k < j; ++k) s -= Ls[(i - k) * F + k] * Ls[(j - k) * F + k];
-        Ls[lane * F + j] = s / Ls[j];
-      } else {
-        Ls[lane * F + j] = 0.0;
-      }
-    }
-    __syncthreads();
+  for (int e = lane; e < (PP + 1) * F; e += 64) {
+    const int t = e / F, j = e - t * F;
+    As[e] = j + t < F ? band[(int64_t)t * n + F0 + j] : 0.0;
   }
-  for (int e = lane; e < (p + 1) * F; e += 64) chol[off + e] = Ls[e];
-  for (int e = lane; e < F; e += 64) rdiag[roff + e] = 1.0 / Ls[e];
+  __syncthreads();
+  if (lane != 0) return;
+  // cl[q][t] = L(j-1-q+t, j-1-q): the PP columns before column j (zero
+  // before column 0 and below row F-1)
+  double cl[PP][PP + 1];
+#pragma unroll
+  for (int q = 0; q < PP; ++q)
+#pragma unroll
+    for (int t = 0; t <= PP; ++t) cl[q][t] = 0.0;
+  double a[PP + 1];
+#pragma unroll
+  for (int t = 0; t <= PP; ++t) a[t] = As[t * F];
+  for (int j = 0; j < F; ++j) {
+    double an[PP + 1];
+    const int jn = min(j + 1, F - 1);
+#pragma unroll
+    for (int t = 0; t <= PP; ++t) an[t] = As[t * F + jn];
+    // pivot: A(j,j) - sum_k L(j,k)^2 over k = j-PP .. j-1 in increasing k
+    const double ajj = a[0];
+    double d = ajj;
+#pragma unroll
+    for (int q = PP - 1; q >= 0; --q) d -= cl[q][q + 1] * cl[q][q + 1];
+    if (!(d > 1e-13 * ajj) || !(d > 0.0)) {
+      atomicOr(flag, 1);
+      d = 1.0;
+    }
+    const double ljj = sqrt(d);
+    // L(j+t, j) = (A(j+t, j) - sum_k L(j+t,k) L(j,k)) / L(j,j)
+    double nw[PP + 1];
+    nw[0] = ljj;
+#pragma unroll
+    for (int t = 1; t <= PP; ++t) {
+      double s = a[t];
+#pragma unroll
+      for (int q = PP - 1 - t; q >= 0; --q) s -= cl[q][q + 1 + t] * cl[q][q + 1];
+      nw[t] = s / ljj;
+    }
+#pragma unroll
+    for (int t = 0; t <= PP; ++t) chol[off + (int64_t)t * F + j] = nw[t];
+    rdiag[roff + j] = 1.0 / ljj;
+#pragma unroll
+    for (int q = PP - 1; q > 0; --q)
+#pragma unroll
+      for (int t = 0; t <= PP; ++t) cl[q][t] = cl[q - 1][t];
+#pragma unroll
+    for (int t = 0; t <= PP; ++t) {
+      cl[0][t] = nw[t];
+      a[t] = an[t];
+    }
+  }
 }
 
 // The same with the factor in global memory (segments too long for LDS).
@@ -261,31 +289,60 @@ __global__ void k_inverse_global(int p, const int *blk, const double *chol, doub
 
 // The same with the factor and the inverse in LDS (F^2 + (p+1)F doubles),
 // written out coalesced at the end.
-__global__ void k_inverse(int p, const int *blk, const double *chol, double *inv) {
+// The same with the factor and the inverse in LDS, a thread per column, for
+// degree PP.  Each substitution keeps the last PP values of its column in
+// registers (zero before the column's first nonzero, and the factor's band
+// padding is zero, so every term is formed without a branch) and adds the
+// newest one last, so a step waits on a single product of the step before;
+// the diagonal is applied as a reciprocal.
+template <int PP>
+__global__ void k_inverse(const int *blk, const double *chol, double *inv) {
   extern __shared__ double sm[];
   const int b = blockIdx.x;
   int64_t offc = 0, offi = 0;
   for (int bb = 0; bb < b; ++bb) {
     const int Fb = blk[8 * bb + 3] - blk[8 * bb + 2];
-    offc += (int64_t)(p + 1) * Fb;
+    offc += (int64_t)(PP + 1) * Fb;
     offi += (int64_t)Fb * Fb;
   }
   const int F = blk[8 * b + 3] - blk[8 * b + 2];
-  double *L = sm;                       // [(p+1) * F]
-  double *Z = sm + (size_t)(p + 1) * F;  // [F * F]
-  for (int e = threadIdx.x; e < (p + 1) * F; e += blockDim.x) L[e] = chol[offc + e];
+  double *L = sm;                            // [(PP+1) * F]
+  double *Z = sm + (size_t)(PP + 1) * F;     // [F * F]
+  double *rL = Z + (size_t)F * F;            // [F], 1 / L(i, i)
+  for (int e = threadIdx.x; e < (PP + 1) * F; e += blockDim.x) L[e] = chol[offc + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < F; e += blockDim.x) rL[e] = 1.0 / L[e];
   __syncthreads();
   for (int col = threadIdx.x; col < F; col += blockDim.x) {
-    for (int i = 0; i < F; ++i) {
+    // forward: z = L^{-1} e_col, w[r] = z_{i-1-r} (zero before col); the
+    // factor entries read for i - 1 - r < 0 lie inside L and meet a zero
+    double w[PP];
+#pragma unroll
+    for (int r = 0; r < PP; ++r) w[r] = 0.0;
+    for (int i = 0; i < col; ++i) Z[i * F + col] = 0.0;
+    for (int i = col; i < F; ++i) {
       double s = (i == col) ? 1.0 : 0.0;
-      if (i > col)
-        for (int k = max(col, i - p); k < i; ++k) s -= L[(i - k) * F + k] * Z[k * F + col];
-      Z[i * F + col] = (i < col) ? 0.0 : s / L[i];
+#pragma unroll
+      for (int r = PP - 1; r >= 0; --r) s -= L[(r + 1) * F + i - 1 - r] * w[r];
+      const double z = s * rL[i];
+#pragma unroll
+      for (int r = PP - 1; r > 0; --r) w[r] = w[r - 1];
+      w[0] = z;
+      Z[i * F + col] = z;
     }
+    // backward: x = L^{-T} z, w[r] = x_{i+1+r} (zero past F, where the
+    // factor's padding L(i+1+r, i) is zero too)
+#pragma unroll
+    for (int r = 0; r < PP; ++r) w[r] = 0.0;
     for (int i = F - 1; i >= 0; --i) {
       double s = Z[i * F + col];
-      for (int k = i + 1; k <= min(F - 1, i + p); ++k) s -= L[(k - i) * F + i] * Z[k * F + col];
-      Z[i * F + col] = s / L[i];
+#pragma unroll
+      for (int r = PP - 1; r >= 0; --r) s -= L[(r + 1) * F + i] * w[r];
+      const double x = s * rL[i];
+#pragma unroll
+      for (int r = PP - 1; r > 0; --r) w[r] = w[r - 1];
+      w[0] = x;
+      Z[i * F + col] = x;
     }
   }
   __syncthreads();
@@ -779,13 +836,45 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
   MFA_TRY(hipGetLastError());
   const size_t chol_lds = sizeof(double) * (p + 1) * X.Fmax;
   if (chol_lds <= 64 * 1024)
-    k_chol<<<B, 64, chol_lds, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
+    switch (p) {
+#define MFA_CHOL_CASE(PP)                                                                          \
+  case PP:                                                                                         \
+    k_chol<PP><<<B, 64, chol_lds, st>>>(n, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag); \
+    break;
+      MFA_CHOL_CASE(1)
+      MFA_CHOL_CASE(2)
+      MFA_CHOL_CASE(3)
+      MFA_CHOL_CASE(4)
+      MFA_CHOL_CASE(5)
+      MFA_CHOL_CASE(6)
+      MFA_CHOL_CASE(7)
+      MFA_CHOL_CASE(8)
+#undef MFA_CHOL_CASE
+      default:
+        k_chol_global<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
+    }
   else
     k_chol_global<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
   MFA_TRY(hipGetLastError());
-  const size_t inv_lds = sizeof(double) * ((size_t)(p + 1) * X.Fmax + (size_t)X.Fmax * X.Fmax);
+  const size_t inv_lds = sizeof(double) * ((size_t)(p + 2) * X.Fmax + (size_t)X.Fmax * X.Fmax);
   if (inv_lds <= 64 * 1024)
-    k_inverse<<<B, 256, inv_lds, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
+    switch (p) {
+#define MFA_INV_CASE(PP)                                                    \
+  case PP:                                                                  \
+    k_inverse<PP><<<B, 256, inv_lds, st>>>(X.d_blk, X.d_chol, X.d_inv); \
+    break;
+      MFA_INV_CASE(1)
+      MFA_INV_CASE(2)
+      MFA_INV_CASE(3)
+      MFA_INV_CASE(4)
+      MFA_INV_CASE(5)
+      MFA_INV_CASE(6)
+      MFA_INV_CASE(7)
+      MFA_INV_CASE(8)
+#undef MFA_INV_CASE
+      default:
+        k_inverse_global<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
+    }
   else
     k_inverse_global<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
   MFA_TRY(hipGetLastError());
