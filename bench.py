@@ -71,7 +71,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, datasheet
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the 30 sweep
 # launches of one 512x512x384 p=4 mixed-precision encode, 480 workgroups in
 # x-chunks of 26 planes), scaled by what the same counters
-# read for a plain 1 GiB streaming copy (FETCH_SIZE 524305.6 KiB for 1048576 KiB
+# read for a plain 1 GiB streaming copy (FETCH_SIZE 524305.8 KiB for 1048576 KiB
 # read: x2.0; WRITE_SIZE 1048576 KiB for 1048576 KiB written: x1.0).  Valid only
 # for the kernel source it was taken on: the bench reports null traffic once
 # the residual kernel or its launcher has changed (digest of their source).
@@ -80,8 +80,8 @@ RESID_COUNTERS = {
     "precision": "mixed_bf16",
     "source": "paper_2210_06528_amd/csrc/sweep.hip",
     "source_sha256": "f9388565e53565288a447d0160d0017f4115ad4d041f298e84307f28706ede4d",
-    "fetch_kib": 173346.4, "write_kib": 49300.0,
-    "fetch_factor": 1048576.0 / 524305.6, "write_factor": 1.0,
+    "fetch_kib": 173347.9, "write_kib": 49300.0,
+    "fetch_factor": 1048576.0 / 524305.8, "write_factor": 1.0,
 }
 
 
