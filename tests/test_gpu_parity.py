@@ -292,6 +292,9 @@ def test_decode_points_match_oracle(name):
     assert f32.dtype == np.float32 and _rel(f32, f64) < 1e-6
     with pytest.raises(_lib.MfaError):
         enc.decode_points(ud, deriv=(p + 1,) * w.dim)
+    # no points: nothing launched, an empty result
+    empty = enc.decode_points(torch.empty((0, w.dim), dtype=torch.float64, device="cuda"))
+    assert tuple(empty.shape) == (0,)
 
 
 @pytest.mark.parametrize("which", ["ragged", "full"])
