@@ -9,6 +9,7 @@
 //             backward substitution with every subdomain's banded Cholesky
 //             factor (the batched banded solves), one line per lane, the
 //             1/n_s combine of overlapping segments done in LDS.
+#include <cstdlib>
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
@@ -544,18 +545,30 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
     k_resid<P, TG><<<grid, kRT, 0, st>>>(Pc, c, g, A0, A1, A2, n0, n1, n2, xc, slots, tn);
     return hipGetLastError();
   };
+  // MFA_RESID_XCHUNK=n (n > 0) pins the chunk for every shape and skips the
+  // tuner: a profiler's per-dispatch overhead can change the tuner's choice,
+  // and counters must be taken on the configuration that is timed
+  static const int pinned = [] {
+    const char *v = getenv("MFA_RESID_XCHUNK");
+    return v ? std::max(0, atoi(v)) : 0;
+  }();
+  if (xchunk == 0 && pinned > 0) xchunk = std::min(pinned, n0);
   if (xchunk == 0) {
     // default: at most 512 workgroups, two per CU (on 256 x 256 x 192
     // control points: 10 chunks of 26 planes, 480 workgroups, 8% less
     // time than 5 chunks of 48 planes plus one of 16, and 25% less than 6
-    // even chunks of 43 planes, which put two long chunks on 32 CUs), 768
-    // for small shapes
+    // even chunks of 43 planes, which put two long chunks on 32 CUs),
+    // unless that leaves chunks shorter than 4p planes, whose 2p halo
+    // planes would cost more than the second workgroup per CU gains: then
+    // at most 256 (128^3, p = 3: 8-plane chunks 31-33 us, 4-plane chunks
+    // 34 us); 768 for small shapes
     const int64_t nctrl = (int64_t)n0 * n1 * n2;
-    const int xdef = resid_xchunk(n0, byz, nctrl >= kTuneMinCtrl ? 512 : 768);
+    int xdef = resid_xchunk(n0, byz, nctrl >= kTuneMinCtrl ? 512 : 768);
+    if (nctrl >= kTuneMinCtrl && xdef < 4 * P) xdef = resid_xchunk(n0, byz, 256);
     xchunk = xdef;
     if (nctrl >= kTuneMinCtrl) {
       std::vector<int> cand{xdef};
-      for (int target : {256, 384, 768, 1024, 1536}) {
+      for (int target : {256, 384, 512, 768, 1024, 1536}) {
         const int xc = resid_xchunk(n0, byz, target);
         if (std::find(cand.begin(), cand.end(), xc) == cand.end()) cand.push_back(xc);
       }
