@@ -546,13 +546,13 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
     return hipGetLastError();
   };
   // MFA_RESID_XCHUNK=n (n > 0) pins the chunk for every shape and skips the
-  // tuner: a profiler's per-dispatch overhead can change the tuner's choice,
-  // and counters must be taken on the configuration that is timed
-  static const int pinned = [] {
-    const char *v = getenv("MFA_RESID_XCHUNK");
-    return v ? std::max(0, atoi(v)) : 0;
-  }();
-  if (xchunk == 0 && pinned > 0) xchunk = std::min(pinned, n0);
+  // tuner (read on every launch): a profiler's per-dispatch overhead can
+  // change the tuner's choice, and counters must be taken on the
+  // configuration that is timed
+  if (const char *pin = getenv("MFA_RESID_XCHUNK")) {
+    const int v = atoi(pin);
+    if (v > 0) xchunk = std::min(v, n0);
+  }
   if (xchunk == 0) {
     // default: at most 512 workgroups, two per CU (on 256 x 256 x 192
     // control points: 10 chunks of 26 planes, 480 workgroups, 8% less

@@ -319,3 +319,23 @@ def test_fused_correction_equals_separate_passes(which, monkeypatch):
         out[mode] = enc.get_ctrl().cpu().numpy()
         enc.close()
     assert np.array_equal(out["fused"], out["separate"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_bf16"])
+def test_residual_is_independent_of_the_chunking(precision, monkeypatch):
+    """The residual stencil forms every output with the same arithmetic
+    whatever its x-chunking, which is what lets the chunk be tuned per
+    process: sweeps with the chunk pinned to 1 plane and to ragged 3- and
+    7-plane chunks agree bitwise with the default chunking."""
+    w = W.small_3d(npts=(40, 48, 70), sizes=((8, 9), (10, 10), (17, 18)), p=4, overlap=2)
+    q = torch.from_numpy(np.ascontiguousarray(_field(w))).cuda()
+    out = {}
+    for pin in ("0", "1", "3", "7"):
+        monkeypatch.setenv("MFA_RESID_XCHUNK", pin)
+        enc = _enc(w, precision=precision)
+        st = [enc.step(q if k == 0 else None) for k in range(3)]
+        out[pin] = (enc.get_ctrl().cpu().numpy(), [s["nres_max"] for s in st])
+        enc.close()
+    for pin in ("1", "3", "7"):
+        assert np.array_equal(out[pin][0], out["0"][0]), pin
+        assert out[pin][1] == out["0"][1], pin
