@@ -321,8 +321,8 @@ def run_serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is a "
-              "design only, not built); run with --gpus 1", file=sys.stderr)
+        print("bench.py: the encoder runs on one GPU only (the multi-GPU halo exchange is "
+              "designed but not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calib:
         run_copy(args)
