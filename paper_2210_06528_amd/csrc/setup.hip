@@ -289,27 +289,89 @@ __global__ void k_inverse_global(int p, const int *blk, const double *chol, doub
 
 // The same with the factor and the inverse in LDS (F^2 + (p+1)F doubles),
 // written out coalesced at the end.
-// The same with the factor and the inverse in LDS, a thread per column, for
-// degree PP.  Each substitution keeps the last PP values of its column in
-// registers (zero before the column's first nonzero, and the factor's band
-// padding is zero, so every term is formed without a branch) and adds the
-// newest one last, so a step waits on a single product of the step before;
-// the diagonal is applied as a reciprocal.
+// Factor and dense inverse of every local normal matrix in one launch, for
+// degree PP, when both fit in LDS.  Lane 0 forms the banded Cholesky factor
+// column by column as k_chol does (last PP columns in registers), writing it
+// in place over the staged band in LDS and out to chol/rdiag; then a thread
+// per column solves L L^T z = e_col from LDS.  Each substitution keeps the
+// last PP values of its column in registers (zero before the column's first
+// nonzero, and the factor's band padding is zero, so every term is formed
+// without a branch) and adds the newest one last, so a step waits on a
+// single product of the step before; the diagonal is applied as a
+// reciprocal.  A non-positive pivot sets flag[0].
 template <int PP>
-__global__ void k_inverse(const int *blk, const double *chol, double *inv) {
+__global__ void __launch_bounds__(256) k_chol_inv(int n, const double *band, const int *blk,
+                                                  double *chol, double *rdiag, double *inv,
+                                                  int *flag) {
   extern __shared__ double sm[];
   const int b = blockIdx.x;
-  int64_t offc = 0, offi = 0;
+  int64_t off = 0, roff = 0, offi = 0;
   for (int bb = 0; bb < b; ++bb) {
     const int Fb = blk[8 * bb + 3] - blk[8 * bb + 2];
-    offc += (int64_t)(PP + 1) * Fb;
+    off += (int64_t)(PP + 1) * Fb;
+    roff += Fb;
     offi += (int64_t)Fb * Fb;
   }
-  const int F = blk[8 * b + 3] - blk[8 * b + 2];
-  double *L = sm;                            // [(PP+1) * F]
+  const int F0 = blk[8 * b + 2], F = blk[8 * b + 3] - F0;
+  double *L = sm;                            // [(PP+1) * F]: A(j+t, j), then L(j+t, j)
   double *Z = sm + (size_t)(PP + 1) * F;     // [F * F]
   double *rL = Z + (size_t)F * F;            // [F], 1 / L(i, i)
-  for (int e = threadIdx.x; e < (PP + 1) * F; e += blockDim.x) L[e] = chol[offc + e];
+  for (int e = threadIdx.x; e < (PP + 1) * F; e += blockDim.x) {
+    const int t = e / F, j = e - t * F;
+    L[e] = j + t < F ? band[(int64_t)t * n + F0 + j] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // cl[q][t] = L(j-1-q+t, j-1-q): the PP columns before column j
+    double cl[PP][PP + 1];
+#pragma unroll
+    for (int q = 0; q < PP; ++q)
+#pragma unroll
+      for (int t = 0; t <= PP; ++t) cl[q][t] = 0.0;
+    double a[PP + 1];
+#pragma unroll
+    for (int t = 0; t <= PP; ++t) a[t] = L[t * F];
+    for (int j = 0; j < F; ++j) {
+      double an[PP + 1];
+      const int jn = min(j + 1, F - 1);
+#pragma unroll
+      for (int t = 0; t <= PP; ++t) an[t] = L[t * F + jn];
+      const double ajj = a[0];
+      double d = ajj;
+#pragma unroll
+      for (int q = PP - 1; q >= 0; --q) d -= cl[q][q + 1] * cl[q][q + 1];
+      if (!(d > 1e-13 * ajj) || !(d > 0.0)) {
+        atomicOr(flag, 1);
+        d = 1.0;
+      }
+      const double ljj = sqrt(d);
+      double nw[PP + 1];
+      nw[0] = ljj;
+#pragma unroll
+      for (int t = 1; t <= PP; ++t) {
+        double s = a[t];
+#pragma unroll
+        for (int q = PP - 1 - t; q >= 0; --q) s -= cl[q][q + 1 + t] * cl[q][q + 1];
+        nw[t] = s / ljj;
+      }
+      // column j of A has been read (into a); column j+1 is in an
+#pragma unroll
+      for (int t = 0; t <= PP; ++t) {
+        L[t * F + j] = nw[t];
+        chol[off + (int64_t)t * F + j] = nw[t];
+      }
+      rdiag[roff + j] = 1.0 / ljj;
+#pragma unroll
+      for (int q = PP - 1; q > 0; --q)
+#pragma unroll
+        for (int t = 0; t <= PP; ++t) cl[q][t] = cl[q - 1][t];
+#pragma unroll
+      for (int t = 0; t <= PP; ++t) {
+        cl[0][t] = nw[t];
+        a[t] = an[t];
+      }
+    }
+  }
   __syncthreads();
   for (int e = threadIdx.x; e < F; e += blockDim.x) rL[e] = 1.0 / L[e];
   __syncthreads();
@@ -834,50 +896,56 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
   k_tab_rows<<<dim3(nblk(std::max<int64_t>(n, X.ND), 128), 4), 128, 0, st>>>(
       m, n, p, X.d_span, X.N[0], X.NT, X.d_gram, X.A, X.D, X.d_gidD, X.d_acoef);
   MFA_TRY(hipGetLastError());
+  // factor and local inverses: one fused launch when both fit in LDS, else
+  // the factor (LDS or global) and the inverses from global memory
   const size_t chol_lds = sizeof(double) * (p + 1) * X.Fmax;
-  if (chol_lds <= 64 * 1024)
+  const size_t inv_lds = sizeof(double) * ((size_t)(p + 2) * X.Fmax + (size_t)X.Fmax * X.Fmax);
+  if (inv_lds <= 64 * 1024 && p >= 1 && p <= 8) {
     switch (p) {
-#define MFA_CHOL_CASE(PP)                                                                          \
-  case PP:                                                                                         \
+#define MFA_CHOLINV_CASE(PP)                                                                 \
+  case PP:                                                                                   \
+    k_chol_inv<PP><<<B, 256, inv_lds, st>>>(n, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, X.d_inv, \
+                                            h->flag);                                        \
+    break;
+      MFA_CHOLINV_CASE(1)
+      MFA_CHOLINV_CASE(2)
+      MFA_CHOLINV_CASE(3)
+      MFA_CHOLINV_CASE(4)
+      MFA_CHOLINV_CASE(5)
+      MFA_CHOLINV_CASE(6)
+      MFA_CHOLINV_CASE(7)
+      MFA_CHOLINV_CASE(8)
+#undef MFA_CHOLINV_CASE
+      default:
+        break;
+    }
+    MFA_TRY(hipGetLastError());
+  } else {
+    if (chol_lds <= 64 * 1024 && p >= 1 && p <= 8) {
+      switch (p) {
+#define MFA_CHOL_CASE(PP)                                                                        \
+  case PP:                                                                                       \
     k_chol<PP><<<B, 64, chol_lds, st>>>(n, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag); \
     break;
-      MFA_CHOL_CASE(1)
-      MFA_CHOL_CASE(2)
-      MFA_CHOL_CASE(3)
-      MFA_CHOL_CASE(4)
-      MFA_CHOL_CASE(5)
-      MFA_CHOL_CASE(6)
-      MFA_CHOL_CASE(7)
-      MFA_CHOL_CASE(8)
+        MFA_CHOL_CASE(1)
+        MFA_CHOL_CASE(2)
+        MFA_CHOL_CASE(3)
+        MFA_CHOL_CASE(4)
+        MFA_CHOL_CASE(5)
+        MFA_CHOL_CASE(6)
+        MFA_CHOL_CASE(7)
+        MFA_CHOL_CASE(8)
 #undef MFA_CHOL_CASE
-      default:
-        k_chol_global<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
+        default:
+          break;
+      }
+    } else {
+      k_chol_global<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
     }
-  else
-    k_chol_global<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
-  MFA_TRY(hipGetLastError());
-  const size_t inv_lds = sizeof(double) * ((size_t)(p + 2) * X.Fmax + (size_t)X.Fmax * X.Fmax);
-  if (inv_lds <= 64 * 1024)
-    switch (p) {
-#define MFA_INV_CASE(PP)                                                    \
-  case PP:                                                                  \
-    k_inverse<PP><<<B, 256, inv_lds, st>>>(X.d_blk, X.d_chol, X.d_inv); \
-    break;
-      MFA_INV_CASE(1)
-      MFA_INV_CASE(2)
-      MFA_INV_CASE(3)
-      MFA_INV_CASE(4)
-      MFA_INV_CASE(5)
-      MFA_INV_CASE(6)
-      MFA_INV_CASE(7)
-      MFA_INV_CASE(8)
-#undef MFA_INV_CASE
-      default:
-        k_inverse_global<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
-    }
-  else
+    MFA_TRY(hipGetLastError());
     k_inverse_global<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
-  MFA_TRY(hipGetLastError());
+    MFA_TRY(hipGetLastError());
+  }
   // M, Om and J (they need the local inverses)
   {
     const int64_t gx = std::max<int64_t>(std::max<int64_t>(n, m), (int64_t)nif * p);
