@@ -72,7 +72,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, datasheet
 # launches of one 512x512x384 p=4 mixed-precision encode, 480 workgroups in
 # x-chunks of 26 planes, pinned with MFA_RESID_XCHUNK=26 so that the
 # profiler's overhead cannot change the tuner's choice), scaled by what the same counters
-# read for a plain 1 GiB streaming copy (FETCH_SIZE 524305.6 KiB for 1048576 KiB
+# read for a plain 1 GiB streaming copy (FETCH_SIZE 524305.4 KiB for 1048576 KiB
 # read: x2.0; WRITE_SIZE 1048576 KiB for 1048576 KiB written: x1.0).  Valid only
 # for the kernel source it was taken on: the bench reports null traffic once
 # the residual kernel or its launcher has changed (digest of their source).
@@ -81,8 +81,8 @@ RESID_COUNTERS = {
     "precision": "mixed_bf16",
     "source": "paper_2210_06528_amd/csrc/sweep.hip",
     "source_sha256": "b90b021febe77438b7397e5cbf17f4dca24f5b6d10ebcc073a04246003ccfe00",
-    "fetch_kib": 173346.7, "write_kib": 49300.0,
-    "fetch_factor": 1048576.0 / 524305.6, "write_factor": 1.0,
+    "fetch_kib": 173347.2, "write_kib": 49300.0,
+    "fetch_factor": 1048576.0 / 524305.4, "write_factor": 1.0,
 }
 
 
