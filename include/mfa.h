@@ -137,11 +137,12 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes,
  * array): start from the control points set by mfa_set_ctrl, else from zero
  * (the first sweep is then the decoupled local fit), and sweep until
  * max_r J_r < jump_tol or max_sweeps.  The jumps are evaluated every
- * `check_every` sweeps; check_every <= 0 checks at sweeps 4 and 8 and then
- * at the sweep predicted from the geometric decay observed between the last
- * two checks (at most twice the previous interval and 32 sweeps ahead), so
- * the stop may come a few sweeps after the first sweep that met the
- * tolerance.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
+ * `check_every` sweeps.  check_every <= 0 predicts the checks: the first at
+ * sweep 6; after a check at sweep k with largest jump J the next comes
+ * ceil(log(jump_tol / J) / log(rho)) sweeps later (clamped to 1..32), rho =
+ * sqrt(max|dP_k| / max|dP_{k-2}|) the decay of the corrections every sweep
+ * records (4 sweeps later when no decay is seen); so the stop may come a few
+ * sweeps after the first sweep that met the tolerance.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
  * NULL) receives the statistics of the last checked sweep.  Returns
  * MFA_ENOTCONV if the tolerance was not met (the control points are still
  * the last iterate) or a non-finite value appeared.                         */

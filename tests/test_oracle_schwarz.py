@@ -248,3 +248,137 @@ def test_more_overlap_contracts_faster(p):
         rhos.append(np.max(np.abs(np.linalg.eigvals(np.eye(A.shape[0]) - B @ A))))
     assert all(r < 1.0 for r in rhos)
     assert all(a > b for a, b in zip(rhos, rhos[1:]))
+
+
+# ----------------------------------------------------------------------------
+# jump metric (eq. nonlinear-residuals) recomputed with SciPy, 3-D, all axes
+# ----------------------------------------------------------------------------
+_J3 = dict(npts=(26, 23, 21), p=3, sizes=[[5, 6, 5], [5, 6], [6, 5]], o=2)
+
+
+def _embed(block_vals, blks, nctrl):
+    """A block's F-range array placed into a zero control array of full size."""
+    full = np.zeros(nctrl)
+    full[tuple(slice(b.F0, b.F1) for b in blks)] = block_vals
+    return full
+
+
+def _scipy_raw_jumps(plan, dPs):
+    """max |d^r/du_a^r (ext dP_i - ext dP_j)| at u*, over the data points of
+    i's owned range on every other axis, evaluated with SciPy's BSpline
+    (derivative of the spline along a, plain evaluation along the others)."""
+    p, d = plan.p, plan.dim
+    raw = np.zeros((d, p))
+    for a, ax in enumerate(plan.axes):
+        for b in range(len(ax.blocks) - 1):
+            us = float(ax.ustar[b])
+            for idx in np.ndindex(*plan.nsub):
+                if idx[a] != b:
+                    continue
+                jdx = idx[:a] + (b + 1,) + idx[a + 1:]
+                bi = [plan.axes[c].blocks[idx[c]] for c in range(d)]
+                bj = [plan.axes[c].blocks[jdx[c]] for c in range(d)]
+                diff = _embed(dPs[idx], bi, plan.nctrl) - _embed(dPs[jdx], bj, plan.nctrl)
+                for r in range(p):
+                    spl = BSpline(ax.knots, diff, p, axis=a)
+                    vals = (spl.derivative(r) if r else spl)(us)   # axis a removed
+                    for c in range(d):
+                        if c == a:
+                            continue
+                        cc = c if c < a else c - 1                  # position in vals
+                        axc = plan.axes[c]
+                        own = axc.u[bi[c].own0:bi[c].own1]
+                        vals = np.moveaxis(BSpline(axc.knots, vals, p, axis=cc)(own), 0, cc)
+                    raw[a, r] = max(raw[a, r], float(np.max(np.abs(vals))))
+    return raw
+
+
+def _random_local(plan, rng, scale=1.0):
+    dPs = {}
+    for idx in np.ndindex(*plan.nsub):
+        shp = tuple(plan.axes[a].blocks[idx[a]].F1 - plan.axes[a].blocks[idx[a]].F0
+                    for a in range(plan.dim))
+        dPs[idx] = scale * rng.standard_normal(shp)
+    return dPs
+
+
+def test_jump_metric_raw_matches_scipy_3d_all_axes():
+    plan = schwarz.make_plan(_J3["npts"], _J3["p"], _J3["sizes"], _J3["o"])
+    S = schwarz.setup(plan)
+    rng = np.random.default_rng(21)
+    dPs = _random_local(plan, rng)
+    _, raw = schwarz.jump_metric(S, dPs, rng.standard_normal(plan.nctrl))
+    want = _scipy_raw_jumps(plan, dPs)
+    assert np.all(want > 0)
+    assert np.allclose(raw, want, rtol=1e-10, atol=0), (raw, want)
+
+
+def _anisotropic(plan, rng):
+    """Control array whose derivative scales differ by axis: smooth along
+    axis 0, rough along axis 1, a ramp along axis 2."""
+    g = [np.linspace(0.0, 1.0, n) for n in plan.nctrl]
+    X, Y, Z = np.meshgrid(*g, indexing="ij")
+    return (np.sin(2.0 * X) + 0.3 * rng.standard_normal(plan.nctrl) * (1.0 + Y)
+            + 5.0 * Z)
+
+
+def test_sweep_jump_normalisation_uses_new_consensus_per_axis():
+    """The normalised jump of a sweep is max_a raw_a,r / max(S_r^a, S_0), with
+    S_r^a the largest r-th derivative control coefficient along axis a of the
+    NEW consensus (SciPy's derivative spline) and S_0 = max |P_new|.  P0 is
+    chosen far from P_new and the field anisotropic, so that normalising by
+    the old iterate or by another axis' scale fails."""
+    plan = schwarz.make_plan(_J3["npts"], _J3["p"], _J3["sizes"], _J3["o"])
+    S = schwarz.setup(plan)
+    rng = np.random.default_rng(22)
+    u = [ax.u for ax in plan.axes]
+    U, V, Wz = np.meshgrid(*u, indexing="ij")
+    Q = np.sin(3 * U) + 0.2 * np.cos(11 * V) + 4.0 * Wz + 0.05 * rng.standard_normal(U.shape)
+    P0 = 40.0 * _anisotropic(plan, rng)[::-1, ::-1, :]
+    P_new, st = schwarz.sweep(S, Q, P0)
+    dPs, _ = schwarz.local_corrections(S, Q, P0)
+    raw = _scipy_raw_jumps(plan, dPs)
+    p = plan.p
+    s0 = float(np.max(np.abs(P_new)))
+    sr = np.zeros((plan.dim, p))
+    for a, ax in enumerate(plan.axes):
+        spl = BSpline(ax.knots, P_new, p, axis=a)
+        for r in range(p):
+            sr[a, r] = float(np.max(np.abs((spl.derivative(r) if r else spl).c)))
+    want = np.max(raw / np.maximum(sr, s0), axis=0)
+    assert np.allclose(st.jump, want, rtol=1e-10, atol=0), (st.jump, want)
+    # the alternatives a slip would produce all differ from it
+    s0_old = float(np.max(np.abs(P0)))
+    sr_old = np.zeros_like(sr)
+    for a, ax in enumerate(plan.axes):
+        spl = BSpline(ax.knots, P0, p, axis=a)
+        for r in range(p):
+            sr_old[a, r] = float(np.max(np.abs((spl.derivative(r) if r else spl).c)))
+    wrong_old = np.max(raw / np.maximum(sr_old, s0_old), axis=0)
+    wrong_axis = np.max(raw / np.maximum(np.roll(sr, 1, axis=0), s0), axis=0)
+    wrong_nofloor = np.max(raw / sr, axis=0)
+    for wrong in (wrong_old, wrong_axis):
+        assert np.max(np.abs(wrong - want) / want) > 1e-3
+    # the floor S_0 acts only where a derivative scale falls below max |P|
+    assert np.all(sr[:, 1:] > s0) or np.any(np.abs(wrong_nofloor - want) / want > 1e-3)
+
+
+def test_jump_floor_applies_when_derivative_vanishes():
+    """A field constant along axis 2: its derivative coefficients along that
+    axis are zero, and the floor S_0 = max |P| keeps the normalised jump
+    finite and equal to raw / S_0 there."""
+    plan = schwarz.make_plan(_J3["npts"], _J3["p"], _J3["sizes"], _J3["o"])
+    S = schwarz.setup(plan)
+    rng = np.random.default_rng(23)
+    dPs = _random_local(plan, rng, 1e-6)
+    base = rng.standard_normal(plan.nctrl[:2])
+    P_new = np.repeat(base[:, :, None], plan.nctrl[2], axis=2)
+    norm, raw = schwarz.jump_metric(S, dPs, P_new)
+    s0 = float(np.max(np.abs(P_new)))
+    sr2 = [float(np.max(np.abs(bspline.derivative_coefficients(P_new, plan.axes[2].knots, 3, r,
+                                                                 axis=2)))) for r in (1, 2)]
+    assert max(sr2) < 1e-12 * s0
+    assert np.all(np.isfinite(norm))
+    # axis 2 contributes raw / S_0 for r = 1, 2
+    for r in (1, 2):
+        assert norm[r] >= raw[2, r] / s0 * (1 - 1e-12)
