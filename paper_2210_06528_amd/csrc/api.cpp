@@ -95,6 +95,15 @@ hipError_t run_chain(Handle &h, const Tin *in, Dims d, const std::vector<Step> &
     return launch_pass<Tin, Tout>(h.stream, in, d, steps[0].ax, *steps[0].op, out, epi, sub, h.slots,
                                   slot_base, gid, gaxis);
   double *bufs[2] = {bufA, bufB};
+  {
+    // every intermediate must fit the scratch buffer it goes to
+    const int64_t cap[2] = {bufA == h.s1 ? h.s1n : h.s2n, bufB == h.s2 ? h.s2n : h.s1n};
+    Dims t = d;
+    for (size_t s = 0; s + 1 < steps.size(); ++s) {
+      t.d[steps[s].ax] = steps[s].op->R;
+      if (t.total() > cap[s & 1]) return hipErrorInvalidValue;
+    }
+  }
   int w = 0;
   hipError_t e = launch_pass<Tin, double>(h.stream, in, d, steps[0].ax, *steps[0].op, bufs[w],
                                           EPI_STORE, nullptr, h.slots, 0, nullptr, 0);

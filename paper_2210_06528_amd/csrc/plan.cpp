@@ -310,9 +310,13 @@ size_t layout_workspace(Handle *h, char *base) {
     else s2 = std::max(s2, v);
   };
   {
+    // both chains run from axis 2 down to the first active axis, whose pass
+    // writes the chain's output (c, or the caller's decode buffer) directly
+    int first = 0;
+    while (first < 2 && !h->ax[first].active) ++first;
     Dims d{{h->ax[0].m, h->ax[1].m, h->ax[2].m}};
     int w = 0;
-    for (int ia = 2; ia >= 0; --ia) {
+    for (int ia = 2; ia > first; --ia) {
       if (!h->ax[ia].active) continue;
       d.d[ia] = h->ax[ia].n;
       upd(w, d.total());
@@ -320,7 +324,7 @@ size_t layout_workspace(Handle *h, char *base) {
     }
     Dims e{{h->ax[0].n, h->ax[1].n, h->ax[2].n}};
     w = 0;
-    for (int ia = 2; ia >= 0; --ia) {
+    for (int ia = 2; ia > first; --ia) {
       if (!h->ax[ia].active) continue;
       e.d[ia] = h->ax[ia].m;
       upd(w, e.total());
