@@ -133,6 +133,26 @@ mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes);
 mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes,
                       void *hip_stream, mfa_handle **out);
 
+/* mfa_create without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture around the call, serving loops and
+ * harnesses that forbid hipMalloc).  The handle's workspace is the library's
+ * own file-scope device array of MFA_NOALLOC_MAX_BYTES bytes (256 MiB, one
+ * copy per device, held from the first use of the library on that device
+ * until the process ends); problems whose mfa_workspace_size exceeds it are
+ * rejected with MFA_ENOMEM before any device work.  Otherwise as mfa_create
+ * (same plan, setup kernels and results), except that every launch stays on
+ * `hip_stream`: no auxiliary streams are forked, the residual stencil takes
+ * its untimed default chunking, and the call creates no HIP streams or events
+ * and calls no allocating routine (hipMalloc, hipFree, torch).  The array
+ * keeps the previous contents; everything that must start at zero is cleared
+ * on the stream by the setup.
+ * Sharing: all no-allocation handles on a device share that one array.
+ * Creating one claims the array: calls on an older no-allocation handle of
+ * the same device then fail with MFA_EINVAL (mfa_destroy still releases it),
+ * and calls that overlap on the array (two streams, two threads) race.      */
+#define MFA_NOALLOC_MAX_BYTES (256u * 1024u * 1024u)
+mfa_status mfa_create_noalloc(const mfa_problem *prob, void *hip_stream, mfa_handle **out);
+
 /* Algorithm 1 on the data q_dev (npts[0] x ... float32 or float64 device
  * array): start from the control points set by mfa_set_ctrl, else from zero
  * (the first sweep is then the decoupled local fit), and sweep until

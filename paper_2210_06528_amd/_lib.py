@@ -28,8 +28,9 @@ STATUS_NAMES = {0: "MFA_OK", -1: "MFA_EINVAL", -2: "MFA_ENOMEM", -3: "MFA_EDEVIC
 # every entry point the header declares
 EXPORTS = ["mfa_workspace_size", "mfa_create", "mfa_encode", "mfa_schwarz_step", "mfa_decode",
            "mfa_get_ctrl", "mfa_set_ctrl", "mfa_inspect", "mfa_set_timing", "mfa_kernel_time",
-           "mfa_decode_points",
+           "mfa_decode_points", "mfa_create_noalloc",
            "mfa_destroy", "mfa_last_error"]
+NOALLOC_MAX_BYTES = 256 * 1024 * 1024   # MFA_NOALLOC_MAX_BYTES
 KERNEL_CLASSES = {"project": 0, "resid": 1, "correct": 2, "metrics": 3, "decode": 4}
 
 
@@ -87,6 +88,8 @@ def load(path=LIB_PATH):
     lib.mfa_workspace_size.restype = c_int32
     lib.mfa_create.argtypes = [POINTER(mfa_problem), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
     lib.mfa_create.restype = c_int32
+    lib.mfa_create_noalloc.argtypes = [POINTER(mfa_problem), c_void_p, POINTER(c_void_p)]
+    lib.mfa_create_noalloc.restype = c_int32
     lib.mfa_encode.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_double, c_int32,
                                POINTER(mfa_step_stats)]
     lib.mfa_encode.restype = c_int32
@@ -155,10 +158,13 @@ def workspace_size(npts, degree, sizes, overlap, precision="fp64", combine="avg"
 
 
 class Encoder:
-    """One MFA problem on one GPU: owns the handle and its torch workspace."""
+    """One MFA problem on one GPU: owns the handle and its torch workspace.
+
+    noalloc=True creates the handle with mfa_create_noalloc: no workspace is
+    allocated; the handle uses the library's per-device array."""
 
     def __init__(self, npts, degree, sizes, overlap, precision="fp64", combine="avg",
-                 rhs="normal", device="cuda:0", stream=None):
+                 rhs="normal", device="cuda:0", stream=None, noalloc=False):
         import torch
         self.torch = torch
         self.lib = load()
@@ -172,8 +178,16 @@ class Encoder:
         nbytes = c_size_t(0)
         check(self.lib.mfa_workspace_size(ctypes.byref(self.prob), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
+        self.noalloc = bool(noalloc)
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            if self.noalloc:
+                self.workspace = None
+                h = c_void_p(0)
+                check(self.lib.mfa_create_noalloc(ctypes.byref(self.prob),
+                                                  c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+                self.handle = h
+                return
             self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
             base = self.workspace.data_ptr()
             self._ws_ptr = (base + 255) & ~255
@@ -187,6 +201,12 @@ class Encoder:
         """Destroy and re-create the handle on the same workspace (setup again)."""
         self.close()
         h = c_void_p(0)
+        if self.noalloc:
+            with self.torch.cuda.device(self.device):
+                check(self.lib.mfa_create_noalloc(ctypes.byref(self.prob),
+                                                  c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+            self.handle = h
+            return
         check(self.lib.mfa_create(ctypes.byref(self.prob), c_void_p(self._ws_ptr),
                                   c_size_t(self.ws_bytes), c_void_p(self.stream.cuda_stream),
                                   ctypes.byref(h)))

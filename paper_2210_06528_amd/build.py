@@ -24,7 +24,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,
 ]
-SOURCES = ["setup.hip", "passes.hip", "sweep.hip", "metrics.hip", "mfma.hip", "grid.hip", "plan.cpp", "api.cpp"]
+SOURCES = ["setup.hip", "passes.hip", "sweep.hip", "metrics.hip", "mfma.hip", "grid.hip", "noalloc.hip",
+           "plan.cpp", "api.cpp"]
 
 
 def _compile(src):

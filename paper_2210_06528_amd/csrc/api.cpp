@@ -188,7 +188,7 @@ hipError_t sweep_normal(Handle &h, const SlotTurn &turn) {
     {
       TimeScope ts(h, MFA_K_RESID);
       e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                              h.ax[2].d_acoef, n0, n1, n2, h.slots, turn);
+                              h.ax[2].d_acoef, n0, n1, n2, h.slots, turn, !h.serial);
     }
     if (e != hipSuccess) return e;
     if (h.fuse21 && h.ax[0].active && mfma_fused21_ok(h)) {
@@ -226,7 +226,7 @@ hipError_t sweep_normal(Handle &h, const SlotTurn &turn) {
       {
         TimeScope ts(h, MFA_K_RESID);
         e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                                h.ax[2].d_acoef, n0, n1, n2, h.slots, turn);
+                                h.ax[2].d_acoef, n0, n1, n2, h.slots, turn, !h.serial);
       }
       if (e != hipSuccess) return e;
       return correct_bsolve<float>(h, gf);
@@ -235,7 +235,7 @@ hipError_t sweep_normal(Handle &h, const SlotTurn &turn) {
     {
       TimeScope ts(h, MFA_K_RESID);
       e = launch_resid<double>(h.stream, h.p, h.P, h.c, h.g, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                               h.ax[2].d_acoef, n0, n1, n2, h.slots, turn);
+                               h.ax[2].d_acoef, n0, n1, n2, h.slots, turn, !h.serial);
     }
     if (e != hipSuccess) return e;
     return correct_bsolve<double>(h, h.g);
@@ -385,7 +385,7 @@ hipError_t sweep_metrics(Handle &h) {
     off[a] = tot;
     tot += (int64_t)(h.ax[a].B - 1) * h.p * (h.nctrl_total / h.ax[a].n);
   }
-  AuxStreams *aux = tot <= h.s1n ? aux_streams(h.device) : nullptr;
+  AuxStreams *aux = (tot <= h.s1n && !h.serial) ? aux_streams(h.device) : nullptr;
   if (!aux) {
     for (int a = 0; a < 3; ++a) {
       if (!jumps[a]) continue;
@@ -454,7 +454,15 @@ mfa_status read_stats(Handle &h, mfa_step_stats *out, double jump_tol, bool *fin
   return MFA_OK;
 }
 
-bool valid_handle(const mfa_handle *h) { return h != nullptr; }
+// A handle is usable unless it lives in the no-allocation array of its
+// device and a newer no-allocation handle has taken that array since.
+mfa_status check_handle(const mfa_handle *H) {
+  if (!H) return fail(MFA_EINVAL, "null handle");
+  if (H->h.noalloc_gen != 0 && noalloc_current(H->h.device) != H->h.noalloc_gen)
+    return fail(MFA_EINVAL,
+                "the device's no-allocation array now holds a newer handle (mfa_create_noalloc)");
+  return MFA_OK;
+}
 
 }  // namespace
 
@@ -471,12 +479,16 @@ mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes) {
   return MFA_OK;
 }
 
-mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, void *hip_stream,
-                      mfa_handle **out) {
-  if (!prob || !out) return fail(MFA_EINVAL, "null pointer");
-  *out = nullptr;
-  if (!workspace) return fail(MFA_EINVAL, "null workspace");
-  if (((uintptr_t)workspace & 255) != 0) return fail(MFA_EINVAL, "workspace not 256-byte aligned");
+}  // extern "C"
+
+namespace {
+
+// Plan, lay out the workspace at `workspace` and run the setup chains.
+// `serial` keeps every launch on the caller's stream (no auxiliary streams,
+// no autotuning timers): the no-allocation entry point creates no HIP
+// objects.
+mfa_status create_handle(const mfa_problem *prob, void *workspace, size_t bytes, void *hip_stream,
+                         bool serial, uint64_t noalloc_gen, mfa_handle **out) {
   mfa_handle *H = new (std::nothrow) mfa_handle();
   if (!H) return fail(MFA_ENOMEM, "host allocation failed");
   Handle &h = H->h;
@@ -492,6 +504,8 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
   }
   h.ws = (char *)workspace;
   h.ws_bytes = bytes;
+  h.serial = serial;
+  h.noalloc_gen = noalloc_gen;
   // diagnostic: MFA_UNFUSED_CORRECTION=1 runs the split-BF16 correction as
   // three separate passes (the same arithmetic) instead of the fused one
   {
@@ -516,22 +530,27 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
   // The per-axis setup chains (basis, Gram, batched Cholesky, inverses,
   // operator tables) are independent and each kernel runs only a few
   // workgroups: the first active axis runs on the caller's stream, the others
-  // on two auxiliary streams forked from it and joined back.
-  AuxStreams *aux = aux_streams(h.device);
-  if (!aux) return bail(hipErrorOutOfMemory, "auxiliary streams");
-  if ((e = hipEventRecord(aux->fork, h.stream)) != hipSuccess) return bail(e, "fork");
+  // on two auxiliary streams forked from it and joined back (all on the
+  // caller's stream when serial).
+  AuxStreams *aux = nullptr;
+  if (!serial) {
+    aux = aux_streams(h.device);
+    if (!aux) return bail(hipErrorOutOfMemory, "auxiliary streams");
+    if ((e = hipEventRecord(aux->fork, h.stream)) != hipSuccess) return bail(e, "fork");
+  }
   int used = 0;
   for (int a = 0; a < 3; ++a) {
     if (!h.ax[a].active) continue;
     hipStream_t st = h.stream;
-    if (used > 0) {
+    const bool fork = aux && used > 0;
+    if (fork) {
       st = aux->s[used - 1];
       if ((e = hipStreamWaitEvent(st, aux->fork, 0)) != hipSuccess) return bail(e, "fork");
     }
     if ((e = setup_axis(&h, a, st)) != hipSuccess) return bail(e, "setup");
     if (h.precision == MFA_PREC_MIXED_BF16 && (e = setup_mfma(&h, a, st)) != hipSuccess)
       return bail(e, "setup");
-    if (used > 0) {
+    if (fork) {
       if ((e = hipEventRecord(aux->join[used - 1], st)) != hipSuccess) return bail(e, "join");
       if ((e = hipStreamWaitEvent(h.stream, aux->join[used - 1], 0)) != hipSuccess) return bail(e, "join");
     }
@@ -550,10 +569,44 @@ mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, vo
   return MFA_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, void *hip_stream,
+                      mfa_handle **out) {
+  if (!prob || !out) return fail(MFA_EINVAL, "null pointer");
+  *out = nullptr;
+  if (!workspace) return fail(MFA_EINVAL, "null workspace");
+  if (((uintptr_t)workspace & 255) != 0) return fail(MFA_EINVAL, "workspace not 256-byte aligned");
+  return create_handle(prob, workspace, bytes, hip_stream, false, 0, out);
+}
+
+mfa_status mfa_create_noalloc(const mfa_problem *prob, void *hip_stream, mfa_handle **out) {
+  if (!prob || !out) return fail(MFA_EINVAL, "null pointer");
+  *out = nullptr;
+  size_t need = 0;
+  {
+    Handle tmp;
+    std::string msg = plan_problem(*prob, &tmp);
+    if (!msg.empty()) return fail(MFA_EINVAL, msg);
+    need = layout_workspace(&tmp, nullptr);
+  }
+  if (need > (size_t)MFA_NOALLOC_MAX_BYTES)
+    return fail(MFA_ENOMEM, "problem needs " + std::to_string(need) +
+                                " bytes of workspace, more than the no-allocation array's " +
+                                std::to_string((size_t)MFA_NOALLOC_MAX_BYTES));
+  void *ptr = nullptr;
+  uint64_t gen = 0;
+  hipError_t e = noalloc_scratch(&ptr, &gen);
+  if (e != hipSuccess) return hip_fail(e, "no-allocation array (hipGetSymbolAddress)");
+  return create_handle(prob, ptr, (size_t)MFA_NOALLOC_MAX_BYTES, hip_stream, true, gen, out);
+}
+
 void mfa_destroy(mfa_handle *h) { delete h; }
 
 mfa_status mfa_set_timing(mfa_handle *H, int32_t class_mask) {
-  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  if (mfa_status s0 = check_handle(H)) return s0;
   Handle &h = H->h;
   HIP_CHECK(hipStreamSynchronize(h.stream), "set_timing");
   for (auto &v : h.ev_used) {
@@ -568,7 +621,8 @@ mfa_status mfa_set_timing(mfa_handle *H, int32_t class_mask) {
 }
 
 mfa_status mfa_kernel_time(mfa_handle *H, int32_t kclass, double *total_ms, int64_t *launches) {
-  if (!valid_handle(H) || !total_ms || !launches) return fail(MFA_EINVAL, "null pointer");
+  if (mfa_status s0 = check_handle(H)) return s0;
+  if (!total_ms || !launches) return fail(MFA_EINVAL, "null pointer");
   if (kclass < 0 || kclass >= MFA_K_COUNT) return fail(MFA_EINVAL, "kernel class out of range");
   Handle &h = H->h;
   HIP_CHECK(hipStreamSynchronize(h.stream), "kernel_time");
@@ -653,7 +707,7 @@ static mfa_status do_sweep(Handle &h, bool metrics) {
 }
 
 mfa_status mfa_schwarz_step(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, mfa_step_stats *out) {
-  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  if (mfa_status s0 = check_handle(H)) return s0;
   Handle &h = H->h;
   hipSetDevice(h.device);
   if (q_dev) {
@@ -673,7 +727,7 @@ mfa_status mfa_schwarz_step(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype,
 
 mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32_t max_sweeps,
                       double jump_tol, int32_t check_every, mfa_step_stats *last) {
-  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  if (mfa_status s0 = check_handle(H)) return s0;
   if (!q_dev) return fail(MFA_EINVAL, "null data pointer");
   if (max_sweeps < 1) return fail(MFA_EINVAL, "max_sweeps must be >= 1");
   Handle &h = H->h;
@@ -740,7 +794,7 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
 }
 
 mfa_status mfa_decode(mfa_handle *H, void *out_dev, mfa_dtype out_dtype, const int32_t *deriv) {
-  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  if (mfa_status s0 = check_handle(H)) return s0;
   if (!out_dev) return fail(MFA_EINVAL, "null output pointer");
   Handle &h = H->h;
   hipSetDevice(h.device);
@@ -777,7 +831,7 @@ mfa_status mfa_decode(mfa_handle *H, void *out_dev, mfa_dtype out_dtype, const i
 
 mfa_status mfa_decode_points(mfa_handle *H, const double *u_dev, int64_t npoints, void *out_dev,
                              mfa_dtype out_dtype, const int32_t *deriv) {
-  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  if (mfa_status s0 = check_handle(H)) return s0;
   if (npoints < 0) return fail(MFA_EINVAL, "negative point count");
   if (npoints > 0 && (!u_dev || !out_dev)) return fail(MFA_EINVAL, "null pointer");
   if (out_dtype != MFA_F32 && out_dtype != MFA_F64) return fail(MFA_EINVAL, "bad dtype");
@@ -796,7 +850,8 @@ mfa_status mfa_decode_points(mfa_handle *H, const double *u_dev, int64_t npoints
 }
 
 mfa_status mfa_get_ctrl(mfa_handle *H, double *ctrl, int32_t on_device) {
-  if (!valid_handle(H) || !ctrl) return fail(MFA_EINVAL, "null pointer");
+  if (mfa_status s0 = check_handle(H)) return s0;
+  if (!ctrl) return fail(MFA_EINVAL, "null pointer");
   Handle &h = H->h;
   hipSetDevice(h.device);
   const size_t bytes = sizeof(double) * (size_t)h.nctrl_total;
@@ -808,7 +863,8 @@ mfa_status mfa_get_ctrl(mfa_handle *H, double *ctrl, int32_t on_device) {
 }
 
 mfa_status mfa_set_ctrl(mfa_handle *H, const double *ctrl, int32_t on_device) {
-  if (!valid_handle(H) || !ctrl) return fail(MFA_EINVAL, "null pointer");
+  if (mfa_status s0 = check_handle(H)) return s0;
+  if (!ctrl) return fail(MFA_EINVAL, "null pointer");
   Handle &h = H->h;
   hipSetDevice(h.device);
   const size_t bytes = sizeof(double) * (size_t)h.nctrl_total;
@@ -822,7 +878,7 @@ mfa_status mfa_set_ctrl(mfa_handle *H, const double *ctrl, int32_t on_device) {
 
 mfa_status mfa_inspect(mfa_handle *H, int32_t table, int32_t axis, int32_t block, double *host_out,
                        size_t count, size_t *needed) {
-  if (!valid_handle(H)) return fail(MFA_EINVAL, "null handle");
+  if (mfa_status s0 = check_handle(H)) return s0;
   Handle &h = H->h;
   hipSetDevice(h.device);
   if (table != MFA_T_RHS && (axis < 0 || axis >= h.dim)) return fail(MFA_EINVAL, "axis out of range");

@@ -122,6 +122,9 @@ struct Handle {
   int q_dtype = 0;
   int g_type = 0;           // element type of g: 0 float64, 1 float32, 2 bfloat16
   bool warm = false;        // P was set by mfa_set_ctrl: the next encode starts there
+  bool serial = false;      // every launch on `stream` (no auxiliary streams or tuner events)
+  uint64_t noalloc_gen = 0; // nonzero: the workspace is the device's no-allocation array,
+                            // claimed by this handle as generation noalloc_gen
   int sweep = 0;
   // per-class event timing
   int timing = 0;                        // mask of timed kernel classes
@@ -155,6 +158,13 @@ constexpr int kSlotCopies = 64;
 std::string plan_problem(const mfa_problem &prob, Handle *h);
 // Lays out the workspace; with base == nullptr only counts bytes.
 size_t layout_workspace(Handle *h, char *base);
+
+// The device's no-allocation array (MFA_NOALLOC_MAX_BYTES, 256-byte
+// aligned) for the current device: its device address and a new generation
+// number that marks the array as claimed by the caller; noalloc_current
+// returns the last generation handed out on `device` (0 if none).
+hipError_t noalloc_scratch(void **ptr, uint64_t *gen);
+uint64_t noalloc_current(int device);
 
 // ---------------------------------------------------------------- kernels
 enum Epi { EPI_STORE = 0, EPI_SUBFROM = 1, EPI_ADDTO = 2, EPI_MAXABS = 3, EPI_STOREMAX = 4 };
@@ -205,7 +215,8 @@ hipError_t setup_axis(Handle *h, int a, hipStream_t st);
 template <typename TG>
 hipError_t launch_resid(hipStream_t st, int p, const double *Pc, const double *c, TG *g,
                         const double *A0, const double *A1, const double *A2, int n0, int n1, int n2,
-                        unsigned long long *slots, const SlotTurn &turn = SlotTurn{});
+                        unsigned long long *slots, const SlotTurn &turn = SlotTurn{},
+                        bool may_tune = true);
 template <typename TI, typename TO, typename TC>
 hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int axis, int n0, int n1,
                          int n2, int p, const Axis &X, int combine, unsigned long long *slots);

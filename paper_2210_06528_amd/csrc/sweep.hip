@@ -527,7 +527,7 @@ constexpr int64_t kTuneMinCtrl = 1 << 20;
 template <int P, typename TG>
 hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG *g, const double *A0,
                           const double *A1, const double *A2, int n0, int n1, int n2,
-                          unsigned long long *slots, const SlotTurn &turn) {
+                          unsigned long long *slots, const SlotTurn &turn, bool may_tune) {
   // the kernel addresses within a plane with 32-bit offsets
   if ((int64_t)n1 * n2 > INT32_MAX) return hipErrorInvalidValue;
   const int byz = (int)(nblk(n2, kTZ) * nblk(n1, kTY));
@@ -566,6 +566,7 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
     int xdef = resid_xchunk(n0, byz, nctrl >= kTuneMinCtrl ? 512 : 768);
     if (nctrl >= kTuneMinCtrl && xdef < 4 * P) xdef = resid_xchunk(n0, byz, 256);
     xchunk = xdef;
+    if (!may_tune) return launch(xdef, turn);   // untimed, not cached
     if (nctrl >= kTuneMinCtrl) {
       std::vector<int> cand{xdef};
       for (int target : {256, 384, 512, 768, 1024, 1536}) {
@@ -609,11 +610,11 @@ hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG 
 template <typename TG>
 hipError_t launch_resid(hipStream_t st, int p, const double *Pc, const double *c, TG *g,
                         const double *A0, const double *A1, const double *A2, int n0, int n1, int n2,
-                        unsigned long long *slots, const SlotTurn &turn) {
+                        unsigned long long *slots, const SlotTurn &turn, bool may_tune) {
   switch (p) {
 #define MFA_RESID_CASE(PP) \
   case PP:                 \
-    return launch_resid_p<PP, TG>(st, Pc, c, g, A0, A1, A2, n0, n1, n2, slots, turn);
+    return launch_resid_p<PP, TG>(st, Pc, c, g, A0, A1, A2, n0, n1, n2, slots, turn, may_tune);
     MFA_RESID_CASE(1)
     MFA_RESID_CASE(2)
     MFA_RESID_CASE(3)
@@ -698,14 +699,14 @@ hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int 
 
 template hipError_t launch_resid<double>(hipStream_t, int, const double *, const double *, double *,
                                          const double *, const double *, const double *, int, int, int,
-                                         unsigned long long *, const SlotTurn &);
+                                         unsigned long long *, const SlotTurn &, bool);
 template hipError_t launch_resid<float>(hipStream_t, int, const double *, const double *, float *,
                                         const double *, const double *, const double *, int, int, int,
-                                        unsigned long long *, const SlotTurn &);
+                                        unsigned long long *, const SlotTurn &, bool);
 template hipError_t launch_resid<__hip_bfloat16>(hipStream_t, int, const double *, const double *,
                                                  __hip_bfloat16 *, const double *, const double *,
                                                  const double *, int, int, int, unsigned long long *,
-                                                 const SlotTurn &);
+                                                 const SlotTurn &, bool);
 template hipError_t launch_bsolve<double, double, double>(hipStream_t, const double *, double *,
                                                           double *, int, int, int, int, int,
                                                           const Axis &, int, unsigned long long *);

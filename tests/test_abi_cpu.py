@@ -81,3 +81,25 @@ def test_workspace_grows_with_problem(lib):
     a = _lib.workspace_size((200, 200), 3, [[25, 25]] * 2, 2)
     b = _lib.workspace_size((400, 400), 3, [[50, 50]] * 2, 2)
     assert b > 3 * a
+
+
+def test_noalloc_rejects_oversized_problem_before_device_work(lib):
+    import ctypes
+    w = W.cfg_3d_mixed()
+    assert _lib.workspace_size(w.npts, w.degree, w.sizes, w.overlap, "mixed_bf16") > \
+        _lib.NOALLOC_MAX_BYTES
+    prob, keep = _lib.make_problem(w.npts, w.degree, w.sizes, w.overlap, "mixed_bf16")
+    h = ctypes.c_void_p(0)
+    assert lib.mfa_create_noalloc(ctypes.byref(prob), None, ctypes.byref(h)) == _lib.MFA_ENOMEM
+    assert b"no-allocation array" in lib.mfa_last_error()
+    assert not h.value
+    assert lib.mfa_create_noalloc(None, None, None) == _lib.MFA_EINVAL
+    bad, keep2 = _lib.make_problem((100,), 3, [[10, 10]], 0)
+    assert lib.mfa_create_noalloc(ctypes.byref(bad), None, ctypes.byref(h)) == _lib.MFA_EINVAL
+
+
+def test_noalloc_array_covers_the_mid_size_workloads(lib):
+    # the 256^3 workload and the largest serving request fit the array
+    w = W.cfg_3d_batched()
+    assert _lib.workspace_size(w.npts, w.degree, w.sizes, w.overlap, "mixed_bf16") <= \
+        _lib.NOALLOC_MAX_BYTES
