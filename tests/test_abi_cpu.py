@@ -103,3 +103,44 @@ def test_noalloc_array_covers_the_mid_size_workloads(lib):
     w = W.cfg_3d_batched()
     assert _lib.workspace_size(w.npts, w.degree, w.sizes, w.overlap, "mixed_bf16") <= \
         _lib.NOALLOC_MAX_BYTES
+
+
+def _unbound_encoder(npts=(6, 5), nctrl=(4, 4)):
+    """An Encoder shell on the 'meta' device: argument checks run, nothing
+    reaches the library (no handle)."""
+    import torch
+    enc = _lib.Encoder.__new__(_lib.Encoder)
+    enc.torch = torch
+    enc.npts, enc.nctrl, enc.dim = tuple(npts), tuple(nctrl), len(npts)
+    enc.device = torch.device("meta")
+    enc.handle = None
+    return enc
+
+
+@pytest.mark.parametrize("call", ["decode", "decode_points", "set_ctrl"])
+def test_binding_rejects_wrong_device_and_dtype(call):
+    import torch
+    enc = _unbound_encoder()
+    meta = dict(device="meta")
+    if call == "decode":
+        with pytest.raises(TypeError):
+            enc.decode(out=torch.empty(enc.npts, dtype=torch.float16, **meta))
+        with pytest.raises(TypeError):
+            enc.decode(out=torch.empty(enc.npts, dtype=torch.int32, **meta))
+        with pytest.raises(ValueError):
+            enc.decode(out=torch.empty(enc.npts, dtype=torch.float32))          # host tensor
+        with pytest.raises(ValueError):
+            enc.decode(out=torch.empty((6, 4), dtype=torch.float32, **meta))    # shape
+    elif call == "decode_points":
+        u = torch.empty((3, 2), dtype=torch.float64, **meta)
+        with pytest.raises(TypeError):
+            enc.decode_points(u, out=torch.empty(3, dtype=torch.bfloat16, **meta))
+        with pytest.raises(ValueError):
+            enc.decode_points(u, out=torch.empty(3, dtype=torch.float64))
+        with pytest.raises(ValueError):
+            enc.decode_points(torch.empty((3, 2), dtype=torch.float64), dtype=torch.float64)
+    else:
+        with pytest.raises(ValueError):
+            enc.set_ctrl(torch.empty(enc.nctrl, dtype=torch.float64))            # host tensor
+        with pytest.raises(ValueError):
+            enc.set_ctrl(torch.empty(enc.nctrl, dtype=torch.float32, **meta))
