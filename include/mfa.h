@@ -93,6 +93,12 @@ typedef struct {
   int32_t precision;         /* mfa_precision                                      */
   int32_t combine;           /* mfa_combine                                        */
   int32_t rhs;               /* mfa_rhs                                            */
+  double lo[3], hi[3];       /* physical extent of each axis: data point i sits at
+                                x = lo + (hi - lo) i/(m-1) (parameter u = i/(m-1)).
+                                Only derivative outputs depend on it: they come
+                                back with respect to x, d^r/dx^r =
+                                (hi - lo)^-r d^r/du^r.  lo == hi (a zeroed struct)
+                                means the unit interval: derivatives in u.       */
 } mfa_problem;
 
 #define MFA_MAX_DEGREE 8
@@ -109,6 +115,11 @@ typedef struct {
   double max_dP;                  /* max |P_new - P| of the last sweep               */
   double nres_max;                /* max |N^T Q - N^T N P| before the last sweep     */
   double ctrl_max;                /* S_0 = max |P| after the last sweep              */
+  double res_max, res_l2;         /* error of the fit after the last sweep against
+                                     the data (Algorithm 1's E): max |Q - N P| and
+                                     ||Q - N P||_2 over all data points.  Filled by
+                                     mfa_schwarz_step; mfa_encode leaves NaN (it
+                                     never decodes on the data: mfa_fit_error)     */
 } mfa_step_stats;
 
 /* Bytes of device workspace mfa_create needs for this problem.
@@ -117,7 +128,8 @@ typedef struct {
  * control points, overlap below max(1, floor(p/2)) on a split axis (the
  * floor(p/2) shared spans needed for partition of unity, Section 2.2), an
  * owned block smaller than max(p+1, 2*overlap) on a split axis, a null
- * pointer, or a precision/combine/rhs value out of range.                  */
+ * pointer, a precision/combine/rhs value out of range, or an axis extent with
+ * hi < lo or a non-finite bound.                                            */
 mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes);
 
 /* Plan the subdomains (Section 2.2), evaluate the Cox-de Boor basis at every
@@ -175,6 +187,15 @@ mfa_status mfa_encode(mfa_handle *h, const void *q_dev, mfa_dtype q_dtype,
  * handle.  Fills *out (may be NULL) including the jumps.  Synchronises.     */
 mfa_status mfa_schwarz_step(mfa_handle *h, const void *q_dev, mfa_dtype q_dtype,
                             mfa_step_stats *out);
+
+/* Algorithm 1's error vector E = Q - N P of the current control points
+ * against the data of the last mfa_encode / mfa_schwarz_step on this handle
+ * (that buffer must still hold the data): *res_max = max |E| and *res_l2 =
+ * ||E||_2 over every data point.  One decode of the spline on the data grid,
+ * compared with Q and reduced on the device (nothing is stored; costs about
+ * one mfa_decode).  Synchronises the stream.  EINVAL when no data was loaded.
+ * mfa_schwarz_step runs the same pass for its statistics.                   */
+mfa_status mfa_fit_error(mfa_handle *h, double *res_max, double *res_l2);
 
 /* Evaluate the consensus spline (or, with deriv != NULL, the mixed partial
  * derivative of orders deriv[0..dim-1] with respect to the parameters u_a,

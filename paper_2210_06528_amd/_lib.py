@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "MFA_OK", -1: "MFA_EINVAL", -2: "MFA_ENOMEM", -3: "MFA_EDEVIC
 # every entry point the header declares
 EXPORTS = ["mfa_workspace_size", "mfa_create", "mfa_encode", "mfa_schwarz_step", "mfa_decode",
            "mfa_get_ctrl", "mfa_set_ctrl", "mfa_inspect", "mfa_set_timing", "mfa_kernel_time",
-           "mfa_decode_points", "mfa_create_noalloc",
+           "mfa_decode_points", "mfa_create_noalloc", "mfa_fit_error",
            "mfa_destroy", "mfa_last_error"]
 NOALLOC_MAX_BYTES = 256 * 1024 * 1024   # MFA_NOALLOC_MAX_BYTES
 KERNEL_CLASSES = {"project": 0, "resid": 1, "correct": 2, "metrics": 3, "decode": 4}
@@ -45,6 +45,8 @@ class mfa_problem(ctypes.Structure):
         ("precision", c_int32),
         ("combine", c_int32),
         ("rhs", c_int32),
+        ("lo", c_double * 3),
+        ("hi", c_double * 3),
     ]
 
 
@@ -56,12 +58,15 @@ class mfa_step_stats(ctypes.Structure):
         ("max_dP", c_double),
         ("nres_max", c_double),
         ("ctrl_max", c_double),
+        ("res_max", c_double),
+        ("res_l2", c_double),
     ]
 
     def as_dict(self, p):
         return {"sweep": self.sweep, "converged": bool(self.converged),
                 "jump": [self.jump[r] for r in range(p)], "max_dP": self.max_dP,
-                "nres_max": self.nres_max, "ctrl_max": self.ctrl_max}
+                "nres_max": self.nres_max, "ctrl_max": self.ctrl_max,
+                "res_max": self.res_max, "res_l2": self.res_l2}
 
 
 class MfaError(RuntimeError):
@@ -95,6 +100,8 @@ def load(path=LIB_PATH):
     lib.mfa_encode.restype = c_int32
     lib.mfa_schwarz_step.argtypes = [c_void_p, c_void_p, c_int32, POINTER(mfa_step_stats)]
     lib.mfa_schwarz_step.restype = c_int32
+    lib.mfa_fit_error.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double)]
+    lib.mfa_fit_error.restype = c_int32
     lib.mfa_decode.argtypes = [c_void_p, c_void_p, c_int32, POINTER(c_int32)]
     lib.mfa_decode.restype = c_int32
     lib.mfa_decode_points.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_int32,
@@ -125,8 +132,10 @@ def check(status):
     return status
 
 
-def make_problem(npts, degree, sizes, overlap, precision="fp64", combine="avg", rhs="normal"):
-    """Build an mfa_problem; the returned tuple keeps the size arrays alive."""
+def make_problem(npts, degree, sizes, overlap, precision="fp64", combine="avg", rhs="normal",
+                 extent=None):
+    """Build an mfa_problem; the returned tuple keeps the size arrays alive.
+    extent: optional per-axis (lo, hi) physical bounds (derivatives in x)."""
     dim = len(npts)
     prob = mfa_problem()
     prob.dim = dim
@@ -146,6 +155,9 @@ def make_problem(npts, degree, sizes, overlap, precision="fp64", combine="avg", 
     prob.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     prob.combine = COMBINE[combine] if isinstance(combine, str) else int(combine)
     prob.rhs = RHS[rhs] if isinstance(rhs, str) else int(rhs)
+    if extent is not None:
+        for a, (lo, hi) in enumerate(extent):
+            prob.lo[a], prob.hi[a] = float(lo), float(hi)
     return prob, keep
 
 
@@ -164,7 +176,7 @@ class Encoder:
     allocated; the handle uses the library's per-device array."""
 
     def __init__(self, npts, degree, sizes, overlap, precision="fp64", combine="avg",
-                 rhs="normal", device="cuda:0", stream=None, noalloc=False):
+                 rhs="normal", device="cuda:0", stream=None, noalloc=False, extent=None):
         import torch
         self.torch = torch
         self.lib = load()
@@ -174,7 +186,8 @@ class Encoder:
         self.sizes = [list(map(int, s)) for s in sizes]
         self.nctrl = tuple(sum(s) for s in self.sizes)
         self.device = torch.device(device)
-        self.prob, self._keep = make_problem(npts, degree, sizes, overlap, precision, combine, rhs)
+        self.prob, self._keep = make_problem(npts, degree, sizes, overlap, precision, combine, rhs,
+                                             extent)
         nbytes = c_size_t(0)
         check(self.lib.mfa_workspace_size(ctypes.byref(self.prob), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
@@ -225,6 +238,15 @@ class Encoder:
         if tuple(q.shape) != self.npts or not q.is_contiguous() or q.device != self.device:
             raise ValueError(f"data must be a contiguous {self.npts} tensor on {self.device}")
 
+    def _check_out(self, out, shape):
+        """An output tensor must be float32/float64, contiguous, of `shape`,
+        on this encoder's device; returns its mfa_dtype."""
+        if not isinstance(out, self.torch.Tensor) or out.device != self.device:
+            raise ValueError(f"output must be a tensor on {self.device}")
+        if tuple(out.shape) != tuple(shape) or not out.is_contiguous():
+            raise ValueError(f"output must be a contiguous tensor of shape {tuple(shape)}")
+        return self._dt(out)
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.mfa_destroy(self.handle)
@@ -257,17 +279,23 @@ class Encoder:
             check(self.lib.mfa_schwarz_step(self.handle, None, MFA_F64, ctypes.byref(st)))
         return st.as_dict(self.degree)
 
+    def fit_error(self):
+        """(max |Q - N P|, ||Q - N P||_2) of the current control points against
+        the data of the last encode or step (Algorithm 1's error vector)."""
+        mx, l2 = c_double(0.0), c_double(0.0)
+        check(self.lib.mfa_fit_error(self.handle, ctypes.byref(mx), ctypes.byref(l2)))
+        return mx.value, l2.value
+
     def decode(self, out=None, dtype=None, deriv=None):
         torch = self.torch
         if out is None:
             out = torch.empty(self.npts, dtype=dtype or torch.float64, device=self.device)
-        if tuple(out.shape) != self.npts or not out.is_contiguous():
-            raise ValueError("bad output tensor")
+        dt = self._check_out(out, self.npts)
         dptr = None
         if deriv is not None:
             arr = (c_int32 * 3)(*([int(r) for r in deriv] + [0] * (3 - len(deriv))))
             dptr = ctypes.cast(arr, POINTER(c_int32))
-        check(self.lib.mfa_decode(self.handle, c_void_p(out.data_ptr()), self._dt(out), dptr))
+        check(self.lib.mfa_decode(self.handle, c_void_p(out.data_ptr()), dt, dptr))
         return out
 
     def decode_points(self, u, dtype=None, deriv=None, out=None):
@@ -280,9 +308,7 @@ class Encoder:
         npts = u.shape[0]
         if out is None:
             out = torch.empty(npts, dtype=dtype or torch.float64, device=self.device)
-        if tuple(out.shape) != (npts,) or not out.is_contiguous():
-            raise ValueError("bad output tensor")
-        dt = MFA_F32 if out.dtype == torch.float32 else MFA_F64
+        dt = self._check_out(out, (npts,))
         dv = None
         if deriv is not None:
             dv = (c_int32 * len(deriv))(*[int(x) for x in deriv])
@@ -297,10 +323,16 @@ class Encoder:
         return out
 
     def set_ctrl(self, ctrl):
-        if tuple(ctrl.shape) != self.nctrl or ctrl.dtype != self.torch.float64:
-            raise ValueError("control points must be float64 of shape %s" % (self.nctrl,))
-        ctrl = ctrl.contiguous()
-        check(self.lib.mfa_set_ctrl(self.handle, c_void_p(ctrl.data_ptr()), 1))
+        if not isinstance(ctrl, self.torch.Tensor) or tuple(ctrl.shape) != self.nctrl or \
+                ctrl.dtype != self.torch.float64 or ctrl.device != self.device:
+            raise ValueError("control points must be a float64 tensor of shape %s on %s"
+                             % (self.nctrl, self.device))
+        src = ctrl.contiguous()
+        check(self.lib.mfa_set_ctrl(self.handle, c_void_p(src.data_ptr()), 1))
+        if src is not ctrl:
+            # the copy is asynchronous on the handle's stream: keep the
+            # temporary's memory from being reused before it has been read
+            src.record_stream(self.stream)
 
     def set_timing(self, enable=True, classes=None):
         """Event-time the kernel classes named in `classes` (all when None)."""

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -413,6 +414,50 @@ hipError_t sweep_metrics(Handle &h) {
   return hipSuccess;
 }
 
+// Algorithm 1's error E = Q - N P at the current control points: one decode
+// of the spline on the data grid compared with the data of the last encode
+// or step, reduced to max |E| and ||E||_2 (nothing is stored).
+mfa_status residual_stats(Handle &h, double *res_max, double *res_l2) {
+  const int nres = 2 * kSlotCopies;
+  hipError_t e = launch_zero_slots(h.stream, h.res_slots, nres);
+  if (e != hipSuccess) return hip_fail(e, "residual");
+  const bool f32 = h.q_dtype == MFA_F32;
+  bool done = false;
+  if (grid_pass_ok(h)) {
+    const int r[3] = {0, 0, 0};
+    e = launch_decode_grid(h, const_cast<void *>(h.q), f32, r, h.res_slots);
+    if (e == hipSuccess) done = true;
+    else if (e != hipErrorNotSupported) return hip_fail(e, "residual");
+  }
+  if (!done) {
+    std::vector<Step> st;
+    for (int a = 2; a >= 0; --a)
+      if (h.ax[a].active) st.push_back({a, &h.ax[a].N[0]});
+    unsigned long long *saved = h.slots;
+    h.slots = h.res_slots;   // the last pass reduces into the residual slots
+    e = run_chain<double, double>(h, h.P, ctrl_dims(h), st, (double *)nullptr,
+                                  f32 ? EPI_RESID32 : EPI_RESID64, (const double *)h.q, 0, nullptr,
+                                  0, h.s1, h.s2);
+    h.slots = saved;
+    if (e != hipSuccess) return hip_fail(e, "residual");
+  }
+  std::vector<unsigned long long> raw(nres);
+  HIP_CHECK(hipMemcpyAsync(raw.data(), h.res_slots, sizeof(unsigned long long) * nres,
+                           hipMemcpyDeviceToHost, h.stream), "residual");
+  HIP_CHECK(hipStreamSynchronize(h.stream), "residual");
+  unsigned long long mx = 0;
+  double sq = 0.0;
+  for (int c = 0; c < kSlotCopies; ++c) {
+    mx = std::max(mx, raw[c]);
+    double v;
+    std::memcpy(&v, &raw[kSlotCopies + c], sizeof(v));
+    sq += v;
+  }
+  std::memcpy(res_max, &mx, sizeof(double));
+  *res_l2 = std::sqrt(sq);
+  return MFA_OK;
+}
+
 mfa_status read_stats(Handle &h, mfa_step_stats *out, double jump_tol, bool *finite) {
   std::vector<unsigned long long> raw((size_t)kNumSlots * kSlotCopies);
   HIP_CHECK(hipMemcpyAsync(raw.data(), h.slots, sizeof(unsigned long long) * raw.size(),
@@ -428,6 +473,7 @@ mfa_status read_stats(Handle &h, mfa_step_stats *out, double jump_tol, bool *fin
   };
   mfa_step_stats st{};
   st.sweep = h.sweep;
+  st.res_max = st.res_l2 = std::numeric_limits<double>::quiet_NaN();
   st.max_dP = val(kSlotMaxDP);
   st.nres_max = val(kSlotNres);
   double s0 = 0.0;
@@ -722,6 +768,7 @@ mfa_status mfa_schwarz_step(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype,
   s = read_stats(h, out, 0.0, &finite);
   if (s != MFA_OK) return s;
   if (!finite) return fail(MFA_ENOTCONV, "non-finite value in the sweep");
+  if (out && (s = residual_stats(h, &out->res_max, &out->res_l2)) != MFA_OK) return s;
   return MFA_OK;
 }
 
@@ -791,6 +838,15 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
   if (last) *last = st;
   if (jump_tol > 0.0 && !converged) return fail(MFA_ENOTCONV, "jump tolerance not reached");
   return MFA_OK;
+}
+
+mfa_status mfa_fit_error(mfa_handle *H, double *res_max, double *res_l2) {
+  if (mfa_status s0 = check_handle(H)) return s0;
+  if (!res_max || !res_l2) return fail(MFA_EINVAL, "null pointer");
+  Handle &h = H->h;
+  hipSetDevice(h.device);
+  if (!h.q) return fail(MFA_EINVAL, "no data loaded: run mfa_encode or mfa_schwarz_step first");
+  return residual_stats(h, res_max, res_l2);
 }
 
 mfa_status mfa_decode(mfa_handle *H, void *out_dev, mfa_dtype out_dtype, const int32_t *deriv) {

@@ -256,6 +256,21 @@ __global__ void __launch_bounds__(256) k_dec_outer(const double *__restrict__ in
   }
 }
 
+// Residual reduction slots: kSlotCopies copies of max |d| (non-negative
+// double bit patterns, atomic max) followed by kSlotCopies copies of the sum
+// of d^2 (doubles, atomic add).
+__device__ __forceinline__ void res_reduce(unsigned long long *rs, double mx, double sq) {
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    sq += __shfl_xor(sq, off, 64);
+  }
+  if (__lane_id() == 0) {
+    const unsigned copy = (blockIdx.x * 7u + blockIdx.y * 131u + (threadIdx.x >> 6)) % kSlotCopies;
+    atomicMax(rs + copy, (unsigned long long)__double_as_longlong(mx));
+    atomicAdd(reinterpret_cast<double *>(rs + kSlotCopies + copy), sq);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // decode, inner: out[i0][i1][i2] = sum_{q1,q2} N_1[i1][q1] N_2[i2][q2]
 //                                  in[i0][span1(i1)-p+q1][span2(i2)-p+q2]
@@ -263,10 +278,12 @@ __global__ void __launch_bounds__(256) k_dec_outer(const double *__restrict__ in
 // thread k2 (< n2 <= blockDim) expands axis 1 from its p+1 open control rows
 // (registers) into RI rows in LDS.  Phase B: thread i2 (IS points per thread,
 // their N_2 rows in registers) expands axis 2 from LDS and writes the output.
-template <typename TO, int P, int RI, int IS>
+// RES: `out` holds the data Q instead (read only); each decoded value d is
+// compared with it and max |Q - d| and sum (Q - d)^2 go to `rs`.
+template <typename TO, int P, int RI, int IS, bool RES>
 __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in, TO *__restrict__ out,
                                                    int64_t m1, int64_t m2, int n1, int n2, int I1C,
-                                                   Rows r1, Rows r2) {
+                                                   Rows r1, Rows r2, unsigned long long *rs) {
   extern __shared__ __align__(16) unsigned char smem[];
   double *rows = reinterpret_cast<double *>(smem);                // [RI][n2]
   double *sw = rows + (size_t)RI * n2;                            // [I1C][P+1] axis-1 weights
@@ -303,6 +320,7 @@ __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in
 #pragma unroll
   for (int q = 0; q <= P; ++q) win[q] = slab[(int64_t)(cur - P + q) * n2];
   TO *dst = out + i0 * m1 * m2;
+  double rmax = 0.0, rsq = 0.0;
 
   for (int64_t g = I1a; g < I1b; g += RI) {
     const int nr = (int)min((int64_t)RI, I1b - g);
@@ -341,12 +359,19 @@ __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in
           double v = 0.0;
 #pragma unroll
           for (int q = 0; q <= P; ++q) v += w2[s][q] * row[c2[s] + q];
-          o[i2] = (TO)v;
+          if (RES) {
+            const double d = (double)o[i2] - v;
+            rmax = fmax(rmax, fabs(d));
+            rsq += d * d;
+          } else {
+            o[i2] = (TO)v;
+          }
         }
       }
     }
     __syncthreads();   // rows are rewritten by the next group
   }
+  if (RES) res_reduce(rs, rmax, rsq);
 }
 
 inline unsigned nblk(int64_t n, int64_t b) { return (unsigned)((n + b - 1) / b); }
@@ -450,7 +475,7 @@ hipError_t project_p(Handle &h, const void *q, bool f32) {
 }
 
 template <int P>
-hipError_t decode_p(Handle &h, void *out, bool f32, const int r[3]) {
+hipError_t decode_p(Handle &h, void *out, bool f32, const int r[3], unsigned long long *rs) {
   const Axis &X0 = h.ax[0], &X1 = h.ax[1], &X2 = h.ax[2];
   const int64_t m0 = X0.m, m1 = X1.m, m2 = X2.m;
   const int n1 = X1.n, n2 = X2.n;
@@ -475,18 +500,22 @@ hipError_t decode_p(Handle &h, void *out, bool f32, const int r[3]) {
   const dim3 g1(nblk(m1, I1C), (unsigned)m0);
   const size_t lds = (size_t)kDecRI * n2 * sizeof(double) + (size_t)I1C * ((P + 1) * sizeof(double) + sizeof(int));
   const Rows r1 = rows_of(X1, r[1]), r2 = rows_of(X2, r[2]);
-#define MFA_DI(TO, IS_)                                                                            \
-  k_dec_inner<TO, P, kDecRI, IS_><<<g1, BS, lds, h.stream>>>(src, reinterpret_cast<TO *>(out), m1, \
-                                                             m2, n1, n2, I1C, r1, r2)
+#define MFA_DI(TO, IS_)                                                                          \
+  if (rs)                                                                                        \
+    k_dec_inner<TO, P, kDecRI, IS_, true><<<g1, BS, lds, h.stream>>>(                            \
+        src, reinterpret_cast<TO *>(out), m1, m2, n1, n2, I1C, r1, r2, rs);                      \
+  else                                                                                           \
+    k_dec_inner<TO, P, kDecRI, IS_, false><<<g1, BS, lds, h.stream>>>(                           \
+        src, reinterpret_cast<TO *>(out), m1, m2, n1, n2, I1C, r1, r2, nullptr)
   if (IS == 1) {
-    if (f32) MFA_DI(float, 1);
-    else MFA_DI(double, 1);
+    if (f32) { MFA_DI(float, 1); }
+    else { MFA_DI(double, 1); }
   } else if (IS == 2) {
-    if (f32) MFA_DI(float, 2);
-    else MFA_DI(double, 2);
+    if (f32) { MFA_DI(float, 2); }
+    else { MFA_DI(double, 2); }
   } else {
-    if (f32) MFA_DI(float, 4);
-    else MFA_DI(double, 4);
+    if (f32) { MFA_DI(float, 4); }
+    else { MFA_DI(double, 4); }
   }
 #undef MFA_DI
   return hipGetLastError();
@@ -508,14 +537,15 @@ hipError_t launch_project_grid(Handle &h, const void *q, bool f32) {
   }
 }
 
-hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3]) {
+hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3],
+                              unsigned long long *rs) {
   switch (h.p) {
-    case 1: return decode_p<1>(h, out, f32, r);
-    case 2: return decode_p<2>(h, out, f32, r);
-    case 3: return decode_p<3>(h, out, f32, r);
-    case 4: return decode_p<4>(h, out, f32, r);
-    case 5: return decode_p<5>(h, out, f32, r);
-    case 6: return decode_p<6>(h, out, f32, r);
+    case 1: return decode_p<1>(h, out, f32, r, rs);
+    case 2: return decode_p<2>(h, out, f32, r, rs);
+    case 3: return decode_p<3>(h, out, f32, r, rs);
+    case 4: return decode_p<4>(h, out, f32, r, rs);
+    case 5: return decode_p<5>(h, out, f32, r, rs);
+    case 6: return decode_p<6>(h, out, f32, r, rs);
     default: return hipErrorNotSupported;
   }
 }

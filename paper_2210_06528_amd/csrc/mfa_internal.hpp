@@ -43,6 +43,7 @@ struct Axis {
   int64_t m = 1;        // data points
   int n = 1;            // control points
   int B = 1;            // subdomains
+  double dscale = 1.0;  // du/dx = 1 / (hi - lo): derivative tables carry dscale^r
   std::vector<Block> blk;
   std::vector<int> ns;            // subdomains whose free set holds each ctrl
   std::vector<int> blo, bhi;      // first / last block whose free set holds ctrl k
@@ -115,6 +116,7 @@ struct Handle {
   unsigned long long *slots = nullptr;
   int *flag = nullptr;                   // setup error flag
   double *hist = nullptr;                // max |correction| of recent sweeps (ring of kHist)
+  unsigned long long *res_slots = nullptr;   // data-residual reduction (2 x kSlotCopies)
   size_t upload_bytes = 0;               // host-planned tables: workspace bytes [0, upload_bytes)
   bool fuse21 = true;                    // fused axis-2/axis-1 correction when it applies
   bool have_rhs = false;
@@ -167,7 +169,11 @@ hipError_t noalloc_scratch(void **ptr, uint64_t *gen);
 uint64_t noalloc_current(int device);
 
 // ---------------------------------------------------------------- kernels
-enum Epi { EPI_STORE = 0, EPI_SUBFROM = 1, EPI_ADDTO = 2, EPI_MAXABS = 3, EPI_STOREMAX = 4 };
+// EPI_RESID32 / EPI_RESID64: `sub` is the data Q (float32 / float64); the
+// pass stores nothing and reduces max |Q - value| and sum (Q - value)^2 into
+// slots[0..kSlotCopies) and slots[kSlotCopies..2 kSlotCopies)
+enum Epi { EPI_STORE = 0, EPI_SUBFROM = 1, EPI_ADDTO = 2, EPI_MAXABS = 3, EPI_STOREMAX = 4,
+           EPI_RESID32 = 5, EPI_RESID64 = 6 };
 
 struct Dims {
   int64_t d[3];
@@ -233,7 +239,11 @@ size_t mfma_lds(int npad);
 // generic pass chain instead (nothing is launched then)
 bool grid_pass_ok(const Handle &h);
 hipError_t launch_project_grid(Handle &h, const void *q, bool f32);
-hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3]);
+// rs != nullptr: `out` is the data Q (float32 when f32) and the decoded values
+// are only compared with it: max |Q - N P| and sum (Q - N P)^2 go to rs
+// (kSlotCopies copies each, max then sum)
+hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3],
+                              unsigned long long *rs = nullptr);
 bool mfma_fits(int npad);
 hipError_t setup_mfma(Handle *h, int a, hipStream_t st);
 // axes 2 and 1 of the split-BF16 correction in one pass (3-D problems)

@@ -30,6 +30,23 @@ __device__ __forceinline__ void wave_slot_max(unsigned long long *slots, int slo
   }
 }
 
+// Wavefront reduction of a data-residual value d into rs: max |d| (atomic max
+// on the bit pattern) into copies [0, kSlotCopies), sum d^2 (atomic add) into
+// copies [kSlotCopies, 2 kSlotCopies).
+__device__ __forceinline__ void wave_res(unsigned long long *rs, double d) {
+  double mx = fabs(d), sq = d * d;
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    sq += __shfl_xor(sq, off, 64);
+  }
+  if (__lane_id() == 0) {
+    const unsigned copy =
+        (blockIdx.x * 7u + blockIdx.y * 131u + blockIdx.z * 1031u + (threadIdx.x >> 6)) % kSlotCopies;
+    atomicMax(rs + copy, (unsigned long long)__double_as_longlong(mx));
+    atomicAdd(reinterpret_cast<double *>(rs + kSlotCopies + copy), sq);
+  }
+}
+
 // One thread per output element; grid (ceil(o2/bs), o1, o0).  When the
 // operator acts on axis 0 or 1 the row is uniform over the workgroup (table
 // loads are scalar); on axis 2 each lane has its own row.
@@ -68,9 +85,16 @@ __global__ void __launch_bounds__(256) k_pass(const Tin *__restrict__ in, Tout *
       out[idx] = (Tout)acc;
     } else if (EPI == EPI_ADDTO) {
       out[idx] = (Tout)((double)out[idx] + acc);
+    } else if (EPI == EPI_RESID32) {
+      acc = (double)reinterpret_cast<const float *>(sub)[idx] - acc;
+    } else if (EPI == EPI_RESID64) {
+      acc = sub[idx] - acc;
     }
   }
-  if (EPI != EPI_STORE) wave_slot_max(slots, slot, valid ? fabs(acc) : 0.0);
+  if (EPI == EPI_RESID32 || EPI == EPI_RESID64)
+    wave_res(slots, valid ? acc : 0.0);
+  else if (EPI != EPI_STORE)
+    wave_slot_max(slots, slot, valid ? fabs(acc) : 0.0);
 }
 
 // point residual on the segmented data boxes: r = Q(gathered) - r
@@ -150,6 +174,14 @@ hipError_t launch_pass(hipStream_t st, const Tin *in, Dims in_dims, int ax, cons
     case EPI_ADDTO:
       k_pass<Tin, Tout, EPI_ADDTO><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op, slots,
                                                          slot_base, gid, gaxis);
+      break;
+    case EPI_RESID32:
+      k_pass<Tin, Tout, EPI_RESID32><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op,
+                                                           slots, slot_base, gid, gaxis);
+      break;
+    case EPI_RESID64:
+      k_pass<Tin, Tout, EPI_RESID64><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op,
+                                                           slots, slot_base, gid, gaxis);
       break;
     default:
       k_pass<Tin, Tout, EPI_MAXABS><<<grid, bs, 0, st>>>(in, out, sub, o0, o1, o2, ax, rin, op, slots,

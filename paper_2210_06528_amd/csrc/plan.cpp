@@ -1,6 +1,7 @@
 // Host planner: validates a problem, computes the subdomain index ranges of
 // Section 2.2 with exact integer arithmetic, and lays out the workspace.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <sstream>
 
@@ -78,6 +79,12 @@ std::string plan_problem(const mfa_problem &prob, Handle *h) {
       n += prob.nctrl[a][b];
     }
     X.n = n;
+    {
+      const double lo = prob.lo[a], hi = prob.hi[a];
+      if (!std::isfinite(lo) || !std::isfinite(hi)) return "axis extent lo/hi not finite";
+      if (hi < lo) return "axis extent with hi < lo";
+      X.dscale = hi > lo ? 1.0 / (hi - lo) : 1.0;
+    }
     if (n < p + 1) return "fewer than p+1 control points on an axis";
     if (X.m < 2) return "fewer than 2 data points on an axis";
     if (X.m < n) return "fewer data points than control points on an axis";
@@ -391,6 +398,7 @@ size_t layout_workspace(Handle *h, char *base) {
   h->slots = h->slot_base;
   h->flag = bp.take<int>(4);
   h->hist = bp.take<double>(kHist);
+  h->res_slots = bp.take<unsigned long long>(2 * (int64_t)kSlotCopies);
   return bp.off + 256;
 }
 

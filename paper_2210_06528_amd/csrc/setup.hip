@@ -83,7 +83,7 @@ struct EllSet {
   Ell t[kMaxP + 1];
 };
 __global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs, int nif,
-                        const double *ustar, const int *span_if, double *dbas_if) {
+                        const double *ustar, const int *span_if, double *dbas_if, double dscale) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((int)blockIdx.y == p + 1) {
     if (i < (int64_t)nif * p) {
@@ -101,11 +101,14 @@ __global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs, int
   const double u = (double)i / (double)(m - 1);
   double vals[kMaxP + 1];
   basis_deriv(u, (int)s, n, p, r, vals);
+  // derivative rows with respect to the physical coordinate (du/dx)^r
+  double sc = 1.0;
+  for (int k = 0; k < r; ++k) sc *= dscale;
   if (span_out) span_out[i] = (int)s;
   tab.len[i] = p + 1;
   for (int q = 0; q <= p; ++q) {
     tab.col[i * tab.L + q] = (int)s - p + q;
-    tab.val[i * tab.L + q] = vals[q];
+    tab.val[i * tab.L + q] = r == 0 ? vals[q] : vals[q] * sc;
   }
 }
 
@@ -780,6 +783,7 @@ __global__ void __launch_bounds__(64) k_tab_ops(int64_t m, int n, int p, int com
 // (p+1)^d tensor sum over the control points under the point's spans.
 struct PtAxes {
   int n[3], active[3], ua[3], r[3];
+  double scale;   // product of (du/dx)^r over the axes
 };
 
 template <typename TO>
@@ -818,7 +822,7 @@ __global__ void k_decode_points(const double *__restrict__ u, int64_t npts, int 
       for (int q2 = 0; q2 < w2; ++q2) t += val[2][q2] * row[q2];
       acc += v01 * t;
     }
-  out[i] = (TO)acc;
+  out[i] = (TO)(acc * ax.scale);
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -886,7 +890,8 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
     for (int r = 0; r <= p; ++r) tabs.t[r] = X.N[r];
     const unsigned gx = nblk(std::max<int64_t>(m, (int64_t)nif * p), 256);
     k_basis<<<dim3(gx, nif > 0 ? p + 2 : p + 1), 256, 0, st>>>(m, n, p, X.d_span, tabs, nif, X.d_ustar,
-                                                                 X.d_span_if, X.d_dbas_if);
+                                                                 X.d_span_if, X.d_dbas_if,
+                                                                 X.dscale);
     MFA_TRY(hipGetLastError());
   }
   X.d_bas = X.N[0].val;
@@ -974,11 +979,13 @@ hipError_t launch_decode_points(Handle &h, const double *u, int64_t npts, void *
                                 const int r[3]) {
   if (npts == 0) return hipSuccess;
   PtAxes ax{};
+  ax.scale = 1.0;
   for (int a = 0; a < 3; ++a) {
     ax.n[a] = h.ax[a].n;
     ax.active[a] = h.ax[a].active;
     ax.ua[a] = a - (3 - h.dim);
     ax.r[a] = r[a];
+    for (int k = 0; k < r[a]; ++k) ax.scale *= h.ax[a].dscale;
   }
   const unsigned grid = (unsigned)((npts + 255) / 256);
   if (f32)

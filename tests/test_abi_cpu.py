@@ -144,3 +144,16 @@ def test_binding_rejects_wrong_device_and_dtype(call):
             enc.set_ctrl(torch.empty(enc.nctrl, dtype=torch.float64))            # host tensor
         with pytest.raises(ValueError):
             enc.set_ctrl(torch.empty(enc.nctrl, dtype=torch.float32, **meta))
+
+
+@pytest.mark.parametrize("extent,msg", [([(1.0, 0.0)], "hi < lo"),
+                                        ([(0.0, float("inf"))], "not finite"),
+                                        ([(float("nan"), 1.0)], "not finite")])
+def test_bad_axis_extent_rejected(lib, extent, msg):
+    import ctypes
+    prob, keep = _lib.make_problem((100,), 3, [[20, 20]], 2, extent=extent)
+    out = ctypes.c_size_t(0)
+    assert lib.mfa_workspace_size(ctypes.byref(prob), ctypes.byref(out)) == _lib.MFA_EINVAL
+    assert msg in lib.mfa_last_error().decode()
+    ok, keep2 = _lib.make_problem((100,), 3, [[20, 20]], 2, extent=[(-2.0, 5.0)])
+    assert lib.mfa_workspace_size(ctypes.byref(ok), ctypes.byref(out)) == _lib.MFA_OK

@@ -365,3 +365,67 @@ def test_residual_is_independent_of_the_chunking(precision, monkeypatch):
     for pin in ("1", "3", "7"):
         assert np.array_equal(out[pin][0], out["0"][0]), pin
         assert out[pin][1] == out["0"][1], pin
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "3d", "3d-p4"])
+def test_fit_error_stats_match_oracle(name):
+    """Algorithm 1's error E = Q - N P in the step statistics and from
+    mfa_fit_error:
+    max |E| and ||E||_2 of the returned control points against the oracle's
+    decode of its own iterate (the grid decode pass for 2-D/3-D, the pass
+    chain for 1-D)."""
+    w = SMALL[name]()
+    S = _oracle(w)
+    Q = _data(w)
+    q = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    enc = _enc(w)
+    P = np.zeros(w.nctrl)
+    scale = np.max(np.abs(Q))
+    for k in range(3):
+        P, _ = schwarz.sweep(S, Q, P, k + 1)
+        g = enc.step(q if k == 0 else None)
+        E = Q - schwarz.decode(S, P)
+        assert abs(g["res_max"] - np.max(np.abs(E))) <= 1e-9 * scale, (k, g["res_max"])
+        l2 = np.sqrt(np.sum(E * E))
+        assert abs(g["res_l2"] - l2) <= 1e-9 * max(l2, scale), (k, g["res_l2"], l2)
+    # encode leaves the data error to mfa_fit_error (one decode pass)
+    enc2 = _enc(w)
+    st = enc2.encode(q, 300, 1e-8 if w.sweeps is None else 0.0, 1)
+    assert np.isnan(st["res_max"]) and np.isnan(st["res_l2"])
+    mx, l2 = enc2.fit_error()
+    Pg = enc2.get_ctrl().cpu().numpy()
+    E = Q - schwarz.decode(S, Pg)
+    assert abs(mx - np.max(np.abs(E))) <= 1e-12 * scale
+    assert abs(l2 - np.sqrt(np.sum(E * E))) <= 1e-10 * max(1.0, l2)
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "3d-p4"])
+def test_derivatives_in_physical_units(name):
+    """With an axis extent [lo, hi] the decoded derivatives are taken with
+    respect to x = lo + (hi - lo) u: the oracle's u-derivative times
+    (hi - lo)^-r per axis, on the grid and at arbitrary points; values and
+    the fit itself do not change."""
+    w = SMALL[name]()
+    S = _oracle(w)
+    rng = np.random.default_rng(31)
+    ext = [(-4 * np.pi, 4 * np.pi), (0.5, 2.0), (-1.0, 3.0)][:w.dim]
+    P = rng.standard_normal(w.nctrl)
+    enc = _lib.Encoder(w.npts, w.degree, w.sizes, w.overlap, "fp64", extent=ext)
+    enc.set_ctrl(torch.from_numpy(P).cuda())
+    p = w.degree
+    for der in [(0,) * w.dim, (1,) + (0,) * (w.dim - 1), tuple(min(2, p) for _ in range(w.dim))]:
+        got = enc.decode(deriv=der).cpu().numpy()
+        fac = np.prod([(hi - lo) ** -r for (lo, hi), r in zip(ext, der)])
+        ref = schwarz.decode(S, P, derivs=der) * fac
+        assert _rel(got, ref) < 1e-11, der
+        U = rng.random((200, w.dim))
+        gp = enc.decode_points(torch.from_numpy(U).cuda(), deriv=der).cpu().numpy()
+        rows = [bspline.collocation(ax.knots, ax.n, p, U[:, a], der[a])
+                for a, ax in enumerate(S.plan.axes)]
+        if w.dim == 1:
+            rp = rows[0] @ P
+        elif w.dim == 2:
+            rp = np.einsum("ia,ib,ab->i", rows[0], rows[1], P)
+        else:
+            rp = np.einsum("ia,ib,ic,abc->i", rows[0], rows[1], rows[2], P)
+        assert _rel(gp, rp * fac) < 1e-11, der
