@@ -221,9 +221,19 @@ mfa_status mfa_decode_points(mfa_handle *h, const double *u_dev, int64_t npoints
 /* Copy the control points (float64, nctrl[0] x ...) out of / into the handle
  * ("write MFA to disk" of Algorithm 1; set_ctrl is a warm start or refit).
  * on_device != 0: the pointer is a device pointer; otherwise host memory
- * (the copy then completes before the call returns).                       */
+ * (the copy then completes before the call returns).  mfa_set_ctrl with
+ * ctrl == NULL copies nothing and makes the next mfa_encode start from the
+ * control points the handle already holds (Algorithm 1's branch for P != 0:
+ * a refit of new data on a resident model, without the decoupled first
+ * sweep).                                                                   */
 mfa_status mfa_get_ctrl(mfa_handle *h, double *ctrl, int32_t on_device);
 mfa_status mfa_set_ctrl(mfa_handle *h, const double *ctrl, int32_t on_device);
+
+/* Move the handle's work to another HIP stream of the same device (a
+ * resident model driven from another thread or slot).  Synchronises the old
+ * stream first, so no work is left on it; later calls enqueue on
+ * `hip_stream`.                                                             */
+mfa_status mfa_set_stream(mfa_handle *h, void *hip_stream);
 
 /* Copy an intermediate table into host memory for inspection (tests):
  *  MFA_T_BASIS   basis values, axis `axis`: npts x (p+1), row i holds

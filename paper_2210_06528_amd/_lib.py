@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "MFA_OK", -1: "MFA_EINVAL", -2: "MFA_ENOMEM", -3: "MFA_EDEVIC
 # every entry point the header declares
 EXPORTS = ["mfa_workspace_size", "mfa_create", "mfa_encode", "mfa_schwarz_step", "mfa_decode",
            "mfa_get_ctrl", "mfa_set_ctrl", "mfa_inspect", "mfa_set_timing", "mfa_kernel_time",
-           "mfa_decode_points", "mfa_create_noalloc", "mfa_fit_error",
+           "mfa_decode_points", "mfa_create_noalloc", "mfa_fit_error", "mfa_set_stream",
            "mfa_destroy", "mfa_last_error"]
 NOALLOC_MAX_BYTES = 256 * 1024 * 1024   # MFA_NOALLOC_MAX_BYTES
 KERNEL_CLASSES = {"project": 0, "resid": 1, "correct": 2, "metrics": 3, "decode": 4}
@@ -111,6 +111,8 @@ def load(path=LIB_PATH):
     lib.mfa_get_ctrl.restype = c_int32
     lib.mfa_set_ctrl.argtypes = [c_void_p, c_void_p, c_int32]
     lib.mfa_set_ctrl.restype = c_int32
+    lib.mfa_set_stream.argtypes = [c_void_p, c_void_p]
+    lib.mfa_set_stream.restype = c_int32
     lib.mfa_inspect.argtypes = [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double), c_size_t,
                                 POINTER(c_size_t)]
     lib.mfa_inspect.restype = c_int32
@@ -321,6 +323,15 @@ class Encoder:
         out = torch.empty(self.nctrl, dtype=torch.float64, device=self.device)
         check(self.lib.mfa_get_ctrl(self.handle, c_void_p(out.data_ptr()), 1))
         return out
+
+    def warm_start(self):
+        """The next encode starts from the control points the handle holds."""
+        check(self.lib.mfa_set_ctrl(self.handle, None, 1))
+
+    def set_stream(self, stream):
+        """Enqueue this handle's later work on `stream` (a torch.cuda.Stream)."""
+        check(self.lib.mfa_set_stream(self.handle, c_void_p(stream.cuda_stream)))
+        self.stream = stream
 
     def set_ctrl(self, ctrl):
         if not isinstance(ctrl, self.torch.Tensor) or tuple(ctrl.shape) != self.nctrl or \

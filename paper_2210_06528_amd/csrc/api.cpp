@@ -918,11 +918,24 @@ mfa_status mfa_get_ctrl(mfa_handle *H, double *ctrl, int32_t on_device) {
   return MFA_OK;
 }
 
-mfa_status mfa_set_ctrl(mfa_handle *H, const double *ctrl, int32_t on_device) {
+mfa_status mfa_set_stream(mfa_handle *H, void *hip_stream) {
   if (mfa_status s0 = check_handle(H)) return s0;
-  if (!ctrl) return fail(MFA_EINVAL, "null pointer");
   Handle &h = H->h;
   hipSetDevice(h.device);
+  // everything queued so far on the old stream completes first
+  HIP_CHECK(hipStreamSynchronize(h.stream), "set_stream");
+  h.stream = (hipStream_t)hip_stream;
+  return MFA_OK;
+}
+
+mfa_status mfa_set_ctrl(mfa_handle *H, const double *ctrl, int32_t on_device) {
+  if (mfa_status s0 = check_handle(H)) return s0;
+  Handle &h = H->h;
+  hipSetDevice(h.device);
+  if (!ctrl) {   // warm start from the control points the handle holds
+    h.warm = true;
+    return MFA_OK;
+  }
   const size_t bytes = sizeof(double) * (size_t)h.nctrl_total;
   HIP_CHECK(hipMemcpyAsync(h.P, ctrl, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            h.stream),

@@ -290,11 +290,18 @@ class Request:
     rid: int
     arrival: float          # seconds after stream start
     workload: Workload
+    kind: str = "encode"    # "encode": a new model; "refit": new data for model `model`
+    model: int = -1         # rid of the encode request that created the model
+    t: float = 0.0          # time of the field (refits: the model's field advanced to t)
+
+    def __post_init__(self):
+        if self.model < 0:
+            self.model = self.rid
 
 
 def serving_stream(nreq=2000, rate=100.0, seed=2, side_lo=64, side_hi=512, block=32,
-                   overlap=2):
-    """Poisson arrivals of 2-D/3-D spectral-field encode requests.
+                   overlap=2, refit_frac=0.0, refit_window=50, refit_dt=0.02):
+    """Poisson arrivals of 2-D/3-D spectral-field encode and refit requests.
 
     Per request (one rng, seed `seed`): inter-arrival ~ Exp(rate), dimension
     uniform in {2, 3}, sides uniform in [side_lo, side_hi], p uniform in
@@ -302,10 +309,19 @@ def serving_stream(nreq=2000, rate=100.0, seed=2, side_lo=64, side_hi=512, block
     even blocks (fewer if a block would be smaller than max(p+1, 2*overlap));
     the field uses seed 1000 + rid and k_max = n_min // 4.  The rng draws do
     not depend on `rate`, so changing the rate only rescales arrival times.
+
+    With refit_frac > 0 a second rng (seed + 1) turns that fraction of the
+    requests into refits: new data for a model created by one of the last
+    `refit_window` encode requests, its field advanced in time by refit_dt
+    per refit (every mode's phase moves by |k| dt).  The first rng's draws
+    and the arrival times are the same whatever refit_frac is.
     """
     rng = np.random.default_rng(seed)
+    rrf = np.random.default_rng(seed + 1)
     t = 0.0
     out = []
+    encodes = []
+    nrefit = {}
     for rid in range(nreq):
         t += rng.exponential(1.0 / rate)
         dim = int(rng.integers(2, 4))
@@ -319,5 +335,13 @@ def serving_stream(nreq=2000, rate=100.0, seed=2, side_lo=64, side_hi=512, block
         w = Workload(f"req{rid}", sides, p, sizes, overlap, precision="mixed_bf16",
                      jump_tol=1e-8, dtype="f32", seed=1000 + rid)
         w.extra["kmax"] = max(1, min(nctrl) // 4)
-        out.append(Request(rid, t, w))
+        if refit_frac > 0.0 and encodes and rrf.random() < refit_frac:
+            cand = encodes[-refit_window:]
+            m = cand[int(rrf.integers(0, len(cand)))]
+            nrefit[m.rid] = nrefit.get(m.rid, 0) + 1
+            out.append(Request(rid, t, m.workload, "refit", m.rid, refit_dt * nrefit[m.rid]))
+            continue
+        req = Request(rid, t, w, "encode", rid, 0.0)
+        encodes.append(req)
+        out.append(req)
     return out
