@@ -48,6 +48,13 @@ def parse():
                     help="extra untimed steps with every kernel class event-timed")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip timing the FP64 GPU paths on the same input")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the short runs of the other workloads and the reduced serving "
+                         "stream that follow the main workload")
+    ap.add_argument("--leg-requests", type=int, default=300,
+                    help="serving requests in the reduced serving leg")
+    ap.add_argument("--refit-frac", type=float, default=0.0,
+                    help="serving: fraction of the stream that refits resident models")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="run only a plain device copy of MIB MiB (float32, read once, "
                          "written once) to calibrate the HBM byte counters, then exit")
@@ -172,6 +179,89 @@ def compare_fp64(w, q, out, f_mixed, max_sweeps, tol, args, ms_mixed):
     return rep
 
 
+def host_info():
+    """CPU model and the cores this process may use (the oracle's host)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_accuracy(S, Pstar, f_gpu, P_gpu):
+    """Largest decoded difference of a GPU result from the oracle's
+    single-domain fit (Section 2.3: the fixed point), relative to the largest
+    decoded value, and the same for the control points."""
+    from oracle import schwarz
+    fstar = schwarz.decode(S, Pstar)
+    return {"max_rel_decode_err_vs_oracle": float(np.max(np.abs(f_gpu - fstar)) /
+                                                  np.max(np.abs(fstar))),
+            "max_rel_ctrl_err_vs_oracle": float(np.max(np.abs(P_gpu - Pstar)) /
+                                                np.max(np.abs(Pstar))),
+            "target": 1e-6}
+
+
+def run_leg(name, steps=10, warmup=2):
+    """A short timed run of one more workload in its own precision (setup +
+    encode to its stop rule + decode per step, input resident), with its
+    result compared with the oracle: the single-domain fit for the workloads
+    that run to the jump tolerance, the oracle's own sweeps for the
+    fixed-sweep 1-D workload."""
+    import torch
+    from oracle import schwarz
+    from paper_2210_06528_amd import _lib
+    w = get_workload(name, None)
+    dev = torch.device("cuda:0")
+    from paper_2210_06528_amd import workloads as W
+    Q = W.make_field(w)
+    q = torch.from_numpy(np.ascontiguousarray(Q)).to(dev)
+    out = torch.empty(w.npts, dtype=torch.float32 if Q.dtype == np.float32 else torch.float64,
+                      device=dev)
+    enc = _lib.Encoder(w.npts, w.degree, w.sizes, w.overlap, w.precision, w.combine, device=dev)
+    tol = w.jump_tol or 0.0
+    max_sweeps = w.sweeps or 200
+
+    def step():
+        enc.recreate()
+        st = enc.encode(q, max_sweeps, tol, 0)
+        enc.decode(out)
+        return st
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    S = schwarz.setup(schwarz.make_plan(w.npts, w.degree, w.sizes, w.overlap))
+    P_gpu = enc.get_ctrl().cpu().numpy()
+    f_gpu = enc.decode(dtype=torch.float64).cpu().numpy()
+    Q64 = Q.astype(np.float64)
+    leg = {"workload": w.name, "npts": list(w.npts), "degree": w.degree, "nsub": list(w.nsub),
+           "precision": w.precision, "ms_per_step": ms, "points_per_s": w.npoints / (ms / 1e3),
+           "sweeps": st["sweep"], "converged": st["converged"], "steps": steps}
+    if w.sweeps:
+        Po, _ = schwarz.encode(S, Q64, w.sweeps)
+        leg["max_rel_ctrl_err_vs_oracle_sweeps"] = float(np.max(np.abs(P_gpu - Po)) /
+                                                         np.max(np.abs(Po)))
+    else:
+        leg.update(oracle_accuracy(S, schwarz.global_direct(S, Q64), f_gpu, P_gpu))
+    enc.close()
+    print(f"[bench] leg {name}: {ms:.3f} ms/step, {st['sweep']} sweeps", file=sys.stderr, flush=True)
+    return leg
+
+
 def cpu_baseline(w, Q, nsweeps_gpu, nsample):
     """Oracle timed on the host: `nsample` literal sweeps of the whole workload
     plus the final decode, extrapolated to the GPU's sweep count."""
@@ -193,11 +283,11 @@ def cpu_baseline(w, Q, nsweeps_gpu, nsample):
     # second figure: the oracle's single-domain direct solve, the fixed point
     # the iteration converges to (not the method the GPU runs)
     t0 = time.perf_counter()
-    schwarz.global_direct(S, Q64)
+    Pstar = schwarz.global_direct(S, Q64)
     t_direct = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return {"value": w.npoints / total, "unit": "points/s", "cores": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "host": host_info(),
             "sample": (f"{nsample} literal per-subdomain oracle sweeps of the full {w.name} input "
                        f"({t_sweep:.2f} s/sweep) + setup + one decode, extrapolated to the "
                        f"{nsweeps_gpu} sweeps the GPU needed"),
@@ -205,7 +295,8 @@ def cpu_baseline(w, Q, nsweeps_gpu, nsample):
             "global_direct": {"value": w.npoints / t_direct, "unit": "points/s",
                               "seconds": round(t_direct, 2),
                               "what": "oracle single-domain separable least-squares fit of the "
-                                      "same input (the iteration's fixed point), same threads"}}
+                                      "same input (the iteration's fixed point), same threads"}}, \
+        (S, Pstar)
 
 
 def run_copy(args):
@@ -274,48 +365,87 @@ def run_accuracy(args):
                       "data": "analytic", "results": rows}), flush=True)
 
 
-def run_serving(args):
-    """Poisson stream of encode requests through the continuous-batching loop.
+def run_serving(args, requests=None, calib=None, refit_frac=None, emit=True):
+    """Poisson stream of encode (and refit) requests through the
+    continuous-batching loop.
 
     The arrival rate is calibrated to 0.7x the saturated request rate measured
     on the first `calib` requests (all available at once); the input of each
     request is generated on the device when it is admitted (standing in for
-    its arrival in HBM), so latency = arrival -> input resident -> setup ->
-    encode -> decode complete.
+    its arrival in HBM), so latency = arrival -> input resident -> setup
+    (encodes) -> encode -> decode complete.  A sample of the results (every
+    20th request and every request with all sides <= 128, at most 2^24
+    points each) is compared with the oracle's single-domain fit of its data.
     """
     import torch
+    from oracle import schwarz
     from paper_2210_06528_amd import workloads as W
-    from paper_2210_06528_amd.serve import Server, spectral_field_gpu
+    from paper_2210_06528_amd.serve import Server, request_input
     dev = torch.device("cuda:0")
+    nreq = requests or args.requests
+    ncal = calib or args.calib
+    rf = args.refit_frac if refit_frac is None else refit_frac
 
     def make(req):
-        w = req.workload
-        return spectral_field_gpu(w.npts, w.extra["kmax"], w.seed, dev)
+        return request_input(req, dev)
 
-    base = W.serving_stream(args.requests, rate=1.0, seed=2)
-    srv = Server(slots=args.slots, hbm_budget=200e9, device=dev)
+    base = W.serving_stream(nreq, rate=1.0, seed=2, refit_frac=rf)
+
+    def sampled(req):
+        w = req.workload
+        return (req.rid % 20 == 0 or max(w.npts) <= 128) and w.npoints <= (1 << 24)
+
+    srv = Server(slots=args.slots, hbm_budget=200e9, device=dev, keep_results=sampled)
+
     def report(done, total):
         print(f"[bench] serving: {done}/{total} requests done", file=sys.stderr, flush=True)
 
-    warm = srv.run(base[:min(16, len(base))], make, time_scale=0.0, progress=report)
-    cal = srv.run(base[:args.calib], make, time_scale=0.0, progress=report)
+    def encodes_only(reqs):
+        return [r for r in reqs if r.kind == "encode"]
+
+    warm = srv.run(encodes_only(base[:16]), make, time_scale=0.0, progress=report)
+    cal_reqs = base[:ncal]
+    cal_reqs = [r for r in cal_reqs if r.kind == "encode" or
+                any(e.rid == r.model for e in cal_reqs)]
+    cal = srv.run(cal_reqs, make, time_scale=0.0, progress=report)
     sat_rate = cal["requests"] / cal["wall_s"]
     lam = 0.7 * sat_rate
     print(f"[bench] serving: saturated {sat_rate:.1f} req/s, lambda {lam:.1f} req/s",
           file=sys.stderr, flush=True)
     out = srv.run(base, make, time_scale=1.0 / lam, progress=report)
+    srv.close()
+    # accuracy of the sampled results against the oracle
+    errs = []
+    for req, r in zip(base, out["results"]):
+        if r.ctrl is None:
+            continue
+        w = req.workload
+        Q = make(req).cpu().numpy().astype(np.float64)
+        S = schwarz.setup(schwarz.make_plan(w.npts, w.degree, w.sizes, w.overlap))
+        Pstar = schwarz.global_direct(S, Q)
+        fstar = schwarz.decode(S, Pstar)
+        f = schwarz.decode(S, r.ctrl)
+        errs.append(float(np.max(np.abs(f - fstar)) / np.max(np.abs(fstar))))
     res = {
         "metric": METRIC, "value": out["points_per_s"], "unit": "points/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": out["wall_s"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
-        "config": {"workload": f"serving-{args.requests}-poisson", "slots": args.slots,
+        "config": {"workload": f"serving-{nreq}-poisson", "slots": args.slots,
                    "hbm_budget_gb": 200, "lambda_req_per_s": lam,
                    "saturated_req_per_s": sat_rate, "sides": [64, 512], "degrees": [2, 3, 4],
-                   "precision": "mixed_bf16", "jump_tol": 1e-8},
+                   "precision": "mixed_bf16", "jump_tol": 1e-8, "refit_frac": rf},
         "p50_ms": out["p50_ms"], "p99_ms": out["p99_ms"], "requests": out["requests"],
         "converged": out["converged"], "warm_requests": warm["requests"],
+        "accuracy_sample": {"requests": len(errs),
+                            "max_rel_decode_err_vs_oracle": max(errs) if errs else None,
+                            "target": 1e-6},
     }
-    print(json.dumps(res), flush=True)
+    for k in ("refits", "mean_sweeps_encode", "mean_sweeps_refit"):
+        if k in out:
+            res[k] = out[k]
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 def main():
@@ -419,9 +549,27 @@ def main():
         res["fp64_paths"] = compare_fp64(w, q, out, enc.decode(dtype=torch.float64), max_sweeps, tol,
                                          args, ms)
     res["roofline"] = roofline(w, ktimes)
+    # Algorithm 1's error vector of the result against the data (untimed:
+    # one decode-and-compare pass)
+    mx, l2 = enc.fit_error()
+    res["fit_error"] = {"res_max": mx, "res_l2": l2, "rms": l2 / np.sqrt(w.npoints)}
+    P_gpu = enc.get_ctrl().cpu().numpy()
+    f_gpu = enc.decode(dtype=torch.float64).cpu().numpy()
+    enc.close()
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(w, Q, st["sweep"], args.cpu_sweeps)
+        res["cpu_baseline"], (S, Pstar) = cpu_baseline(w, Q, st["sweep"], args.cpu_sweeps)
+        res["accuracy"] = oracle_accuracy(S, Pstar, f_gpu, P_gpu)
+        print(f"[bench] accuracy vs oracle: {res['accuracy']}", file=sys.stderr, flush=True)
+        del S, Pstar
+    del f_gpu, P_gpu
+    if not args.no_legs and args.workload == "3d-mixed":
+        legs = {}
+        for name in ("1d", "2d", "3d-batched"):
+            legs[name] = run_leg(name)
+        legs["serving"] = run_serving(args, requests=args.leg_requests, calib=60,
+                                      refit_frac=0.2, emit=False)
+        res["legs"] = legs
     print(json.dumps(res), flush=True)
 
 

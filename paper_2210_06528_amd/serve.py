@@ -121,6 +121,8 @@ class Server:
 
     def __init__(self, slots=8, hbm_budget=200e9, device="cuda:0", max_sweeps=300,
                  check_every=0, keep_results=False):
+        """keep_results: True, False, or a predicate on the request: whose
+        control points are copied to the host into the result."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -185,7 +187,7 @@ class Server:
                             raise_on_notconv=False)
             out = torch.empty(w.npts, dtype=torch.float32, device=self.device)
             enc.decode(out)
-            if self.keep:
+            if self.keep(req) if callable(self.keep) else self.keep:
                 res.ctrl = enc.get_ctrl().cpu().numpy()
             s.synchronize()
             if keep_model:
