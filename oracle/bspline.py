@@ -2,11 +2,13 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Follows Section 2.1 (eq. nurbs-basis with all weights W = 1, i.e. plain
-B-splines) and the Cox-de Boor recurrence the paper cites for values and exact
-derivatives.  Knot placement follows Section 2.2: one knot vector per axis,
-clamped (p+1 repeated knots) at the two ends of the global domain and uniform
-(floating) in the interior, so a subdomain's knots are a slice of it.
+Follows Section 2.1 (eq. nurbs-basis) and the Cox-de Boor recurrence the
+paper cites for values and exact derivatives: plain B-splines (all weights
+W = 1), and the rational basis R_i = N_i W_i / sum_j N_j W_j with its
+derivatives by the quotient rule (`rational_collocation`).  Knot placement
+follows Section 2.2: one knot vector per axis, clamped (p+1 repeated knots)
+at the two ends of the global domain and uniform (floating) in the interior,
+so a subdomain's knots are a slice of it.
 
 Everything here is float64 and evaluates the recurrence over *all* basis
 functions of every degree (dense tables), which is slow but easy to check by
@@ -14,6 +16,7 @@ eye.  The span rule, the Greville abscissae and the derivative-coefficient
 formula are the textbook ones (de Boor, "A Practical Guide to Splines").
 """
 from fractions import Fraction
+from math import comb
 
 import numpy as np
 
@@ -146,3 +149,31 @@ def derivative_coefficients(P, t, p, r, axis=0):
         tt = tt[1:-1]
         q -= 1
     return np.moveaxis(D, 0, axis)
+
+
+def rational_collocation(t, n, p, u, w, r=0):
+    """Dense matrix of r-th derivatives of the rational basis of eq.
+    nurbs-basis: R_j(u) = N_{j,p}(u) w_j / W(u), W(u) = sum_k N_{k,p}(u) w_k.
+
+    With A_j = N_{j,p} w_j (so that A = W R), Leibniz's rule on A = W R gives
+    A^(r) = sum_{k=0..r} C(r, k) W^(k) R^(r-k), hence
+
+        R^(r) = ( A^(r) - sum_{k=1..r} C(r, k) W^(k) R^(r-k) ) / W
+
+    computed for r = 0, 1, ... in turn; W^(k) is the row sum of A^(k).
+    w = None (or all ones) gives the B-spline collocation.
+    """
+    if w is None:
+        return collocation(t, n, p, u, r)
+    w = np.asarray(w, dtype=np.float64)
+    if w.shape != (n,) or not np.all(w > 0):
+        raise ValueError("weights must be n positive values")
+    A = [collocation(t, n, p, u, k) * w[None, :] for k in range(r + 1)]
+    Wd = [a.sum(axis=1) for a in A]
+    R = []
+    for k in range(r + 1):
+        acc = A[k].copy()
+        for j in range(1, k + 1):
+            acc -= comb(k, j) * Wd[j][:, None] * R[k - j]
+        R.append(acc / Wd[0][:, None])
+    return R[r]

@@ -32,6 +32,11 @@ What is computed, and where the paper says so
 * Fixed point: the converged multi-subdomain fit is the single-subdomain fit
   (Section 2.3, "same error profile as a single subdomain"); `global_direct`
   computes that fit directly.
+* Weights (eq. nurbs-basis, W != 1; the conclusions' NURBS extension): with
+  tensor-product weights W = w_0 x w_1 x w_2 the rational basis is the
+  product of the per-axis rational bases, so every step above runs unchanged
+  on the rational collocation matrices.  The weights are global, so averaging
+  P or P W over the subdomains is the same combine.
 
 Readings where the paper is silent are listed in the design notes of the
 repository; the important ones are restated next to the code below.
@@ -74,6 +79,11 @@ class AxisPlan:
     blocks: List[Block]
     ns: np.ndarray                    # n_s per control point along this axis
     ustar: List[Fraction] = field(default_factory=list)   # interface params
+    weights: np.ndarray = None        # NURBS weights of the axis (None: all 1)
+
+    def coll(self, u, r=0):
+        """Collocation (r-th derivative) of this axis' basis at parameters u."""
+        return bspline.rational_collocation(self.knots, self.n, self.p, u, self.weights, r)
 
 
 def min_overlap(p):
@@ -81,8 +91,9 @@ def min_overlap(p):
     return max(1, p // 2)
 
 
-def plan_axis(m, p, sizes, overlap):
-    """Plan one axis: m data points, owned control counts `sizes` per block."""
+def plan_axis(m, p, sizes, overlap, weights=None):
+    """Plan one axis: m data points, owned control counts `sizes` per block,
+    optional NURBS weights (one positive value per control point)."""
     sizes = [int(s) for s in sizes]
     n = sum(sizes)
     nb = len(sizes)
@@ -137,7 +148,11 @@ def plan_axis(m, p, sizes, overlap):
     ns = np.zeros(n, dtype=np.int64)
     for bl in blocks:
         ns[bl.F0:bl.F1] += 1
-    return AxisPlan(m, n, p, overlap, t, u, span, blocks, ns, ustar)
+    if weights is not None:
+        weights = np.asarray(weights, dtype=np.float64)
+        if weights.shape != (n,) or not np.all(np.isfinite(weights)) or not np.all(weights > 0):
+            raise ValueError("weights must be n positive finite values")
+    return AxisPlan(m, n, p, overlap, t, u, span, blocks, ns, ustar, weights)
 
 
 @dataclass
@@ -159,11 +174,13 @@ class Plan:
         return tuple(a.n for a in self.axes)
 
 
-def make_plan(npts, p, sizes_per_axis, overlap, combine="avg"):
-    """Plan a d-D problem: npts[a] points and owned sizes per block on axis a."""
+def make_plan(npts, p, sizes_per_axis, overlap, combine="avg", weights=None):
+    """Plan a d-D problem: npts[a] points and owned sizes per block on axis a;
+    weights: None, or per axis None or n_a positive NURBS weights."""
     if combine not in ("avg", "ras"):
         raise ValueError("combine must be 'avg' or 'ras'")
-    axes = [plan_axis(m, p, s, overlap) for m, s in zip(npts, sizes_per_axis)]
+    ws = weights if weights is not None else [None] * len(npts)
+    axes = [plan_axis(m, p, s, overlap, wa) for m, s, wa in zip(npts, sizes_per_axis, ws)]
     return Plan(axes, p, combine)
 
 
@@ -178,7 +195,7 @@ class Setup:
 
 
 def setup(plan):
-    colls = [bspline.collocation(ax.knots, ax.n, plan.p, ax.u) for ax in plan.axes]
+    colls = [ax.coll(ax.u) for ax in plan.axes]
     factors = {}
     for a, ax in enumerate(plan.axes):
         for b, bl in enumerate(ax.blocks):
@@ -261,8 +278,7 @@ def jump_metric(S, dPs, P_new):
             bi, bj = ax.blocks[b], ax.blocks[b + 1]
             lo, hi = bi.F0, bj.F1
             us = np.array([float(ax.ustar[b])])
-            drows = [bspline.collocation(ax.knots, ax.n, p, us, r)[0, lo:hi]
-                     for r in range(p)]
+            drows = [ax.coll(us, r)[0, lo:hi] for r in range(p)]
             for idx in np.ndindex(*plan.nsub):
                 if idx[a] != b:
                     continue
@@ -327,8 +343,7 @@ def decode(S, P, derivs=None):
     mats = []
     for a, ax in enumerate(plan.axes):
         r = 0 if derivs is None else derivs[a]
-        mats.append(S.colls[a] if r == 0 else
-                    bspline.collocation(ax.knots, ax.n, plan.p, ax.u, r))
+        mats.append(S.colls[a] if r == 0 else ax.coll(ax.u, r))
     return lsq.tensor_apply(mats, P)
 
 
