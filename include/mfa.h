@@ -99,6 +99,13 @@ typedef struct {
                                 back with respect to x, d^r/dx^r =
                                 (hi - lo)^-r d^r/du^r.  lo == hi (a zeroed struct)
                                 means the unit interval: derivatives in u.       */
+  const double *weights[3];  /* host arrays or NULL: NURBS weights of each axis'
+                                control points (length = the axis' control count,
+                                positive and finite).  The basis is then the
+                                rational basis of eq. nurbs-basis with the
+                                tensor-product weights W = w_0 x w_1 x w_2, i.e.
+                                R_a = N_a w_a / sum N_a w_a on every axis; NULL is
+                                W = 1 on that axis (plain B-splines).            */
 } mfa_problem;
 
 #define MFA_MAX_DEGREE 8
@@ -128,8 +135,9 @@ typedef struct {
  * control points, overlap below max(1, floor(p/2)) on a split axis (the
  * floor(p/2) shared spans needed for partition of unity, Section 2.2), an
  * owned block smaller than max(p+1, 2*overlap) on a split axis, a null
- * pointer, a precision/combine/rhs value out of range, or an axis extent with
- * hi < lo or a non-finite bound.                                            */
+ * pointer, a precision/combine/rhs value out of range, an axis extent with
+ * hi < lo or a non-finite bound, or a weight that is not positive and
+ * finite.                                                                   */
 mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes);
 
 /* Plan the subdomains (Section 2.2), evaluate the Cox-de Boor basis at every

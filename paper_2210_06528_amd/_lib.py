@@ -47,6 +47,7 @@ class mfa_problem(ctypes.Structure):
         ("rhs", c_int32),
         ("lo", c_double * 3),
         ("hi", c_double * 3),
+        ("weights", POINTER(c_double) * 3),
     ]
 
 
@@ -135,9 +136,10 @@ def check(status):
 
 
 def make_problem(npts, degree, sizes, overlap, precision="fp64", combine="avg", rhs="normal",
-                 extent=None):
+                 extent=None, weights=None):
     """Build an mfa_problem; the returned tuple keeps the size arrays alive.
-    extent: optional per-axis (lo, hi) physical bounds (derivatives in x)."""
+    extent: optional per-axis (lo, hi) physical bounds (derivatives in x).
+    weights: optional per-axis NURBS weights (None or a sequence of n_a)."""
     dim = len(npts)
     prob = mfa_problem()
     prob.dim = dim
@@ -160,6 +162,15 @@ def make_problem(npts, degree, sizes, overlap, precision="fp64", combine="avg", 
     if extent is not None:
         for a, (lo, hi) in enumerate(extent):
             prob.lo[a], prob.hi[a] = float(lo), float(hi)
+    for a in range(3):
+        prob.weights[a] = None
+    if weights is not None:
+        for a, wa in enumerate(weights):
+            if wa is None:
+                continue
+            arr = (c_double * len(wa))(*[float(v) for v in wa])
+            keep.append(arr)
+            prob.weights[a] = ctypes.cast(arr, POINTER(c_double))
     return prob, keep
 
 
@@ -178,7 +189,8 @@ class Encoder:
     allocated; the handle uses the library's per-device array."""
 
     def __init__(self, npts, degree, sizes, overlap, precision="fp64", combine="avg",
-                 rhs="normal", device="cuda:0", stream=None, noalloc=False, extent=None):
+                 rhs="normal", device="cuda:0", stream=None, noalloc=False, extent=None,
+                 weights=None):
         import torch
         self.torch = torch
         self.lib = load()
@@ -189,7 +201,7 @@ class Encoder:
         self.nctrl = tuple(sum(s) for s in self.sizes)
         self.device = torch.device(device)
         self.prob, self._keep = make_problem(npts, degree, sizes, overlap, precision, combine, rhs,
-                                             extent)
+                                             extent, weights)
         nbytes = c_size_t(0)
         check(self.lib.mfa_workspace_size(ctypes.byref(self.prob), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value

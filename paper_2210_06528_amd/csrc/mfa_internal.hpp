@@ -44,6 +44,8 @@ struct Axis {
   int n = 1;            // control points
   int B = 1;            // subdomains
   double dscale = 1.0;  // du/dx = 1 / (hi - lo): derivative tables carry dscale^r
+  std::vector<double> w;          // NURBS weights (empty: all 1)
+  double *d_w = nullptr;          // device copy of w (null when unweighted)
   std::vector<Block> blk;
   std::vector<int> ns;            // subdomains whose free set holds each ctrl
   std::vector<int> blo, bhi;      // first / last block whose free set holds ctrl k

@@ -85,6 +85,11 @@ std::string plan_problem(const mfa_problem &prob, Handle *h) {
       if (hi < lo) return "axis extent with hi < lo";
       X.dscale = hi > lo ? 1.0 / (hi - lo) : 1.0;
     }
+    if (prob.weights[a]) {
+      X.w.assign(prob.weights[a], prob.weights[a] + n);
+      for (double v : X.w)
+        if (!std::isfinite(v) || !(v > 0.0)) return "a weight is not positive and finite";
+    }
     if (n < p + 1) return "fewer than p+1 control points on an axis";
     if (X.m < 2) return "fewer than 2 data points on an axis";
     if (X.m < n) return "fewer data points than control points on an axis";
@@ -262,6 +267,7 @@ size_t layout_workspace(Handle *h, char *base) {
     X.d_pown = bp.take<int>(X.m);
     X.d_ustar = bp.take<double>(nif);
     X.d_span_if = bp.take<int>(nif);
+    X.d_w = X.w.empty() ? nullptr : bp.take<double>(n);
   }
   h->upload_bytes = bp.off;
   for (int ia = 0; ia < 3; ++ia) {

@@ -74,6 +74,38 @@ __device__ void basis_deriv(double u, int s, int n, int p, int r, double *out) {
   for (int q = 0; q <= p; ++q) out[q] = v[q];
 }
 
+// r-th derivative of the p+1 rational basis functions R_{s-p..s} of eq.
+// nurbs-basis, R_j = N_j w_j / W with W = sum_k N_k w_k, at parameter u
+// (w = weights of all n control points; null: the B-spline basis).  With
+// A_j = N_j w_j = W R_j, Leibniz's rule gives
+//   R^(k) = (A^(k) - sum_{j=1..k} C(k, j) W^(j) R^(k-j)) / W,
+// applied for k = 0..r with W^(j) = sum_q A_q^(j).
+__device__ void basis_deriv_w(double u, int s, int n, int p, int r, const double *w, double *out) {
+  if (!w) {
+    basis_deriv(u, s, n, p, r, out);
+    return;
+  }
+  double R[kMaxP + 1][kMaxP + 1];
+  double Wd[kMaxP + 1];
+  for (int k = 0; k <= r; ++k) {
+    double a[kMaxP + 1];
+    basis_deriv(u, s, n, p, k, a);
+    double sum = 0.0;
+    for (int q = 0; q <= p; ++q) {
+      a[q] *= w[s - p + q];
+      sum += a[q];
+    }
+    Wd[k] = sum;
+    double binom = 1.0;   // C(k, j), updated as j grows
+    for (int j = 1; j <= k; ++j) {
+      binom = binom * (double)(k - j + 1) / (double)j;
+      for (int q = 0; q <= p; ++q) a[q] -= binom * Wd[j] * R[k - j][q];
+    }
+    for (int q = 0; q <= p; ++q) R[k][q] = a[q] / Wd[0];
+  }
+  for (int q = 0; q <= p; ++q) out[q] = R[r][q];
+}
+
 // One thread per data point and derivative order r = blockIdx.y (0..p):
 // span and r-th derivative basis row, written as the ELL decode table of
 // that order (columns span-p..span); order 0 also writes the span.  The
@@ -83,12 +115,13 @@ struct EllSet {
   Ell t[kMaxP + 1];
 };
 __global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs, int nif,
-                        const double *ustar, const int *span_if, double *dbas_if, double dscale) {
+                        const double *ustar, const int *span_if, double *dbas_if, double dscale,
+                        const double *wts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((int)blockIdx.y == p + 1) {
     if (i < (int64_t)nif * p) {
       const int b = (int)(i / p), r = (int)(i % p);
-      basis_deriv(ustar[b], span_if[b], n, p, r, dbas_if + i * (p + 1));
+      basis_deriv_w(ustar[b], span_if[b], n, p, r, wts, dbas_if + i * (p + 1));
     }
     return;
   }
@@ -100,7 +133,7 @@ __global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs, int
   if (s > n - 1) s = n - 1;
   const double u = (double)i / (double)(m - 1);
   double vals[kMaxP + 1];
-  basis_deriv(u, (int)s, n, p, r, vals);
+  basis_deriv_w(u, (int)s, n, p, r, wts, vals);
   // derivative rows with respect to the physical coordinate (du/dx)^r
   double sc = 1.0;
   for (int k = 0; k < r; ++k) sc *= dscale;
@@ -783,7 +816,8 @@ __global__ void __launch_bounds__(64) k_tab_ops(int64_t m, int n, int p, int com
 // (p+1)^d tensor sum over the control points under the point's spans.
 struct PtAxes {
   int n[3], active[3], ua[3], r[3];
-  double scale;   // product of (du/dx)^r over the axes
+  const double *w[3];   // NURBS weights per axis (null: B-spline)
+  double scale;         // product of (du/dx)^r over the axes
 };
 
 template <typename TO>
@@ -808,7 +842,7 @@ __global__ void k_decode_points(const double *__restrict__ u, int64_t npts, int 
     // largest s in [p, n-1] with t_s <= x (right-continuous, as on the grid)
     while (s > p && knot(s, n, p) > x) --s;
     while (s < n - 1 && knot(s + 1, n, p) <= x) ++s;
-    basis_deriv(x, s, n, p, ax.r[a], val[a]);
+    basis_deriv_w(x, s, n, p, ax.r[a], ax.w[a], val[a]);
     s0[a] = s - p;
   }
   const int w0 = ax.active[0] ? p + 1 : 1, w1 = ax.active[1] ? p + 1 : 1, w2 = ax.active[2] ? p + 1 : 1;
@@ -872,6 +906,7 @@ hipError_t upload_plan(Handle *h) {
       put(X.d_ustar, X.ustar.data(), sizeof(double) * nif);
       put(X.d_span_if, X.span_if.data(), sizeof(int) * nif);
     }
+    if (X.d_w) put(X.d_w, X.w.data(), sizeof(double) * n);
   }
   MFA_TRY(hipMemcpyAsync(h->ws, img.data(), img.size(), hipMemcpyHostToDevice, h->stream));
   // the image is a local: wait for the copy before it goes out of scope
@@ -891,7 +926,7 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
     const unsigned gx = nblk(std::max<int64_t>(m, (int64_t)nif * p), 256);
     k_basis<<<dim3(gx, nif > 0 ? p + 2 : p + 1), 256, 0, st>>>(m, n, p, X.d_span, tabs, nif, X.d_ustar,
                                                                  X.d_span_if, X.d_dbas_if,
-                                                                 X.dscale);
+                                                                 X.dscale, X.d_w);
     MFA_TRY(hipGetLastError());
   }
   X.d_bas = X.N[0].val;
@@ -985,6 +1020,7 @@ hipError_t launch_decode_points(Handle &h, const double *u, int64_t npts, void *
     ax.active[a] = h.ax[a].active;
     ax.ua[a] = a - (3 - h.dim);
     ax.r[a] = r[a];
+    ax.w[a] = h.ax[a].d_w;
     for (int k = 0; k < r[a]; ++k) ax.scale *= h.ax[a].dscale;
   }
   const unsigned grid = (unsigned)((npts + 255) / 256);

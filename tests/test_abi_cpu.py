@@ -157,3 +157,16 @@ def test_bad_axis_extent_rejected(lib, extent, msg):
     assert msg in lib.mfa_last_error().decode()
     ok, keep2 = _lib.make_problem((100,), 3, [[20, 20]], 2, extent=[(-2.0, 5.0)])
     assert lib.mfa_workspace_size(ctypes.byref(ok), ctypes.byref(out)) == _lib.MFA_OK
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan"), float("inf")])
+def test_bad_weights_rejected(lib, bad):
+    import ctypes
+    w = np.ones(40)
+    w[7] = bad
+    prob, keep = _lib.make_problem((100,), 3, [[20, 20]], 2, weights=[w])
+    out = ctypes.c_size_t(0)
+    assert lib.mfa_workspace_size(ctypes.byref(prob), ctypes.byref(out)) == _lib.MFA_EINVAL
+    assert b"weight" in lib.mfa_last_error()
+    ok, keep2 = _lib.make_problem((100,), 3, [[20, 20]], 2, weights=[np.full(40, 2.0)])
+    assert lib.mfa_workspace_size(ctypes.byref(ok), ctypes.byref(out)) == _lib.MFA_OK

@@ -429,3 +429,58 @@ def test_derivatives_in_physical_units(name):
         else:
             rp = np.einsum("ia,ib,ic,abc->i", rows[0], rows[1], rows[2], P)
         assert _rel(gp, rp * fac) < 1e-11, der
+
+
+def _weights(w, seed=17):
+    rng = np.random.default_rng(seed)
+    return [rng.uniform(0.4, 2.5, n) for n in w.nctrl]
+
+
+@pytest.mark.parametrize("name,nsweeps", [("1d", 6), ("2d", 5), ("3d", 4), ("3d-p4", 4)])
+def test_nurbs_sweeps_match_oracle(name, nsweeps):
+    """NURBS weights (eq. nurbs-basis, W != 1, tensor-product weights): the
+    same sweeps on the rational basis as the oracle's literal per-subdomain
+    sweeps (1e-10), with the jumps, and the decode with derivatives."""
+    w = SMALL[name]()
+    ws = _weights(w)
+    S = schwarz.setup(schwarz.make_plan(w.npts, w.degree, w.sizes, w.overlap, weights=ws))
+    Q = _data(w)
+    enc = _lib.Encoder(w.npts, w.degree, w.sizes, w.overlap, "fp64", weights=ws)
+    q = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    P = np.zeros(w.nctrl)
+    for k in range(nsweeps):
+        P, st = schwarz.sweep(S, Q, P, k + 1)
+        g = enc.step(q if k == 0 else None)
+        assert _rel(enc.get_ctrl().cpu().numpy(), P) < 1e-10, k
+        for r in range(w.degree):
+            jo, jg = st.jump[r], g["jump"][r]
+            if jo > 1e-9:
+                assert abs(jg - jo) <= 1e-6 * jo, (k, r, jg, jo)
+    Pg = enc.get_ctrl().cpu().numpy()
+    p = w.degree
+    for der in [(0,) * w.dim, (1,) * w.dim, (p,) + (0,) * (w.dim - 1)]:
+        got = enc.decode(deriv=der).cpu().numpy()
+        assert _rel(got, schwarz.decode(S, Pg, derivs=der)) < 1e-11, der
+    rng = np.random.default_rng(5)
+    U = rng.random((300, w.dim))
+    got = enc.decode_points(torch.from_numpy(U).cuda(), deriv=(1,) * w.dim).cpu().numpy()
+    rows = [ax.coll(U[:, a], 1) for a, ax in enumerate(S.plan.axes)]
+    ref = {1: lambda: rows[0] @ Pg,
+           2: lambda: np.einsum("ia,ib,ab->i", rows[0], rows[1], Pg),
+           3: lambda: np.einsum("ia,ib,ic,abc->i", rows[0], rows[1], rows[2], Pg)}[w.dim]()
+    assert _rel(got, ref) < 1e-11
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+@pytest.mark.parametrize("name", ["2d", "3d-p4-fused"])
+def test_nurbs_mixed_precision_reaches_oracle_fit(precision, name):
+    w = SMALL[name]()
+    ws = _weights(w, seed=23)
+    S = schwarz.setup(schwarz.make_plan(w.npts, w.degree, w.sizes, w.overlap, weights=ws))
+    Q = _data(w)
+    Pstar = schwarz.global_direct(S, Q)
+    enc = _lib.Encoder(w.npts, w.degree, w.sizes, w.overlap, precision, weights=ws)
+    st = enc.encode(torch.from_numpy(np.ascontiguousarray(Q)).cuda(), 300, 1e-8, 0)
+    assert st["converged"]
+    assert _rel(enc.get_ctrl().cpu().numpy(), Pstar) < 1e-6
+    assert _rel(enc.decode().cpu().numpy(), schwarz.decode(S, Pstar)) < 1e-6
