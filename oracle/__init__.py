@@ -17,8 +17,12 @@ schwarz   subdomain plan (Section 2.2), the overlapping additive-Schwarz sweep
           of Algorithm 1 with the 1/n_s combine (Section 2.3.2), the interface
           jump metric (eq. nonlinear-residuals), decode, and the single-domain
           direct solve that the iteration converges to.
+variants  the two alternatives Section 2.1 and Section 3.1.1 compare with
+          floating knots: decoupled local fits (no exchange) and clamped
+          interfaces (own knots per subdomain, C^0, shared control points
+          clamped to the interface data).
 
 Every function computes in float64 and follows the passage it cites; there is
 no blocking, fusion or reordering beyond what the definition states.
 """
-from . import bspline, lsq, schwarz  # noqa: F401
+from . import bspline, lsq, schwarz, variants  # noqa: F401
