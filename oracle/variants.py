@@ -22,6 +22,8 @@ control point that sits on their common interface, and that control point
 interpolates the input datum there (Section 2.1: the common control points at
 subdomain interfaces are clamped to input data points).  The decoded field is
 therefore C^0 but in general not C^1 across an interface.  Readings taken:
+  * a block's local parameter is v = (i - a0) / (a1 - a0) for data index i
+    between its interface indices a0 < a1, so d/du = (m - 1) / (a1 - a0) d/dv;
   * the interfaces of an axis sit on data points: with n_b control points and
     n_b - p spans in block b, interface b lies at the data index closest to
     (m - 1) * (spans of blocks before b) / (all spans), halves rounded up;
@@ -128,10 +130,11 @@ class ClampedAxis:
         respect to the global parameter u) at data points i0..i1-1."""
         nb = self.sizes[b]
         t = bspline.clamped_uniform_knots(nb, self.p)
-        ua, ub = self.cuts[b] / (self.m - 1), self.cuts[b + 1] / (self.m - 1)
-        u = np.arange(i0, i1) / (self.m - 1)
-        v = np.clip((u - ua) / (ub - ua), 0.0, 1.0)
-        return bspline.collocation(t, nb, self.p, v, r) / (ub - ua) ** r
+        a0, a1 = self.cuts[b], self.cuts[b + 1]
+        # local parameter from the integer indices, so that a point on a
+        # local knot lands exactly on it: v = (i - a0) / (a1 - a0)
+        v = np.clip((np.arange(i0, i1) - a0) / (a1 - a0), 0.0, 1.0)
+        return bspline.collocation(t, nb, self.p, v, r) * ((self.m - 1) / (a1 - a0)) ** r
 
     def collocation(self, r=0):
         """Piecewise collocation (m, n): each data point uses its owner block."""
