@@ -79,6 +79,26 @@ typedef enum { MFA_COMBINE_AVG = 0, MFA_COMBINE_RAS = 1 } mfa_combine;
  *         from the point residual every sweep, as Algorithm 1 is written.  */
 typedef enum { MFA_RHS_NORMAL = 0, MFA_RHS_DATABOX = 1 } mfa_rhs;
 
+/* The model the encode builds (Section 2.1; compared in Section 3.1.1).
+ * SCHWARZ:   one spline on floating interface knots; the overlapping Schwarz
+ *            sweeps of Algorithm 1 make it the single-domain fit (C^{p-1}).
+ * DECOUPLED: every subdomain's unconstrained local fit (Algorithm 1's P = 0
+ *            branch, floating knots, no exchange), one spline per subdomain;
+ *            the decode takes each point from the subdomain that owns it, so
+ *            the field is discontinuous at interfaces.  Control points are the
+ *            subdomains' free sets side by side along every axis
+ *            (sum over blocks of |F_b| per axis).
+ * CLAMPED:   every subdomain has its own clamped uniform knots and nctrl[a][b]
+ *            control points; neighbours share the control point on their
+ *            interface, which takes the input datum there (interfaces sit on
+ *            data points, placed in proportion to the blocks' spans); lower-
+ *            dimensional interface entities are fitted first and frozen, so
+ *            the field is C^0 across interfaces.  sum(nctrl) - (nsub - 1)
+ *            control points per axis; `overlap` is not used.
+ * The two variants are one-shot fits (no sweeps) in float64: precision must
+ * be FP64 and rhs NORMAL; CLAMPED takes no weights.                       */
+typedef enum { MFA_VARIANT_SCHWARZ = 0, MFA_VARIANT_DECOUPLED = 1, MFA_VARIANT_CLAMPED = 2 } mfa_variant;
+
 typedef struct {
   int32_t dim;               /* 1, 2 or 3                                           */
   int64_t npts[3];           /* data points per axis (>= nctrl on that axis)        */
@@ -106,6 +126,7 @@ typedef struct {
                                 tensor-product weights W = w_0 x w_1 x w_2, i.e.
                                 R_a = N_a w_a / sum N_a w_a on every axis; NULL is
                                 W = 1 on that axis (plain B-splines).            */
+  int32_t variant;           /* mfa_variant value; 0 is the Schwarz encoder        */
 } mfa_problem;
 
 #define MFA_MAX_DEGREE 8
@@ -139,6 +160,11 @@ typedef struct {
  * hi < lo or a non-finite bound, or a weight that is not positive and
  * finite.                                                                   */
 mfa_status mfa_workspace_size(const mfa_problem *prob, size_t *bytes);
+
+/* Control points per axis of the problem's model (dims[a] for a < dim): the
+ * axis' control count for SCHWARZ, the free sets side by side for DECOUPLED,
+ * sum(nctrl) - (nsub - 1) for CLAMPED.  Host-side planning only.            */
+mfa_status mfa_ctrl_dims(const mfa_problem *prob, int64_t dims[3]);
 
 /* Plan the subdomains (Section 2.2), evaluate the Cox-de Boor basis at every
  * data point (Section 2.1), assemble the banded per-axis normal matrices

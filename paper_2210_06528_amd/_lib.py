@@ -19,6 +19,7 @@ MFA_F32, MFA_F64 = 0, 1
 PRECISION = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2}
 COMBINE = {"avg": 0, "ras": 1}
 RHS = {"normal": 0, "databox": 1}
+VARIANT = {"schwarz": 0, "decoupled": 1, "clamped": 2}
 TABLES = {"basis": 0, "span": 1, "gram": 2, "chol": 3, "inv": 4, "rhs": 5}
 MAX_DEGREE = 8
 
@@ -29,6 +30,7 @@ STATUS_NAMES = {0: "MFA_OK", -1: "MFA_EINVAL", -2: "MFA_ENOMEM", -3: "MFA_EDEVIC
 EXPORTS = ["mfa_workspace_size", "mfa_create", "mfa_encode", "mfa_schwarz_step", "mfa_decode",
            "mfa_get_ctrl", "mfa_set_ctrl", "mfa_inspect", "mfa_set_timing", "mfa_kernel_time",
            "mfa_decode_points", "mfa_create_noalloc", "mfa_fit_error", "mfa_set_stream",
+           "mfa_ctrl_dims",
            "mfa_destroy", "mfa_last_error"]
 NOALLOC_MAX_BYTES = 256 * 1024 * 1024   # MFA_NOALLOC_MAX_BYTES
 KERNEL_CLASSES = {"project": 0, "resid": 1, "correct": 2, "metrics": 3, "decode": 4}
@@ -48,6 +50,7 @@ class mfa_problem(ctypes.Structure):
         ("lo", c_double * 3),
         ("hi", c_double * 3),
         ("weights", POINTER(c_double) * 3),
+        ("variant", c_int32),
     ]
 
 
@@ -92,6 +95,8 @@ def load(path=LIB_PATH):
     lib = ctypes.CDLL(path)
     lib.mfa_workspace_size.argtypes = [POINTER(mfa_problem), POINTER(c_size_t)]
     lib.mfa_workspace_size.restype = c_int32
+    lib.mfa_ctrl_dims.argtypes = [POINTER(mfa_problem), POINTER(c_int64)]
+    lib.mfa_ctrl_dims.restype = c_int32
     lib.mfa_create.argtypes = [POINTER(mfa_problem), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
     lib.mfa_create.restype = c_int32
     lib.mfa_create_noalloc.argtypes = [POINTER(mfa_problem), c_void_p, POINTER(c_void_p)]
@@ -136,7 +141,7 @@ def check(status):
 
 
 def make_problem(npts, degree, sizes, overlap, precision="fp64", combine="avg", rhs="normal",
-                 extent=None, weights=None):
+                 extent=None, weights=None, variant="schwarz"):
     """Build an mfa_problem; the returned tuple keeps the size arrays alive.
     extent: optional per-axis (lo, hi) physical bounds (derivatives in x).
     weights: optional per-axis NURBS weights (None or a sequence of n_a)."""
@@ -162,6 +167,7 @@ def make_problem(npts, degree, sizes, overlap, precision="fp64", combine="avg", 
     if extent is not None:
         for a, (lo, hi) in enumerate(extent):
             prob.lo[a], prob.hi[a] = float(lo), float(hi)
+    prob.variant = VARIANT[variant] if isinstance(variant, str) else int(variant)
     for a in range(3):
         prob.weights[a] = None
     if weights is not None:
@@ -174,12 +180,21 @@ def make_problem(npts, degree, sizes, overlap, precision="fp64", combine="avg", 
     return prob, keep
 
 
-def workspace_size(npts, degree, sizes, overlap, precision="fp64", combine="avg", rhs="normal"):
+def workspace_size(npts, degree, sizes, overlap, precision="fp64", combine="avg", rhs="normal",
+                   variant="schwarz"):
     """Bytes of workspace (host-side planning only; raises MfaError on bad input)."""
-    prob, keep = make_problem(npts, degree, sizes, overlap, precision, combine, rhs)
+    prob, keep = make_problem(npts, degree, sizes, overlap, precision, combine, rhs,
+                              variant=variant)
     out = c_size_t(0)
     check(load().mfa_workspace_size(ctypes.byref(prob), ctypes.byref(out)))
     return out.value
+
+
+def ctrl_dims_of(prob):
+    """Control points per axis of a problem's model (mfa_ctrl_dims)."""
+    dims = (c_int64 * 3)()
+    check(load().mfa_ctrl_dims(ctypes.byref(prob), dims))
+    return tuple(int(dims[a]) for a in range(prob.dim))
 
 
 class Encoder:
@@ -190,7 +205,7 @@ class Encoder:
 
     def __init__(self, npts, degree, sizes, overlap, precision="fp64", combine="avg",
                  rhs="normal", device="cuda:0", stream=None, noalloc=False, extent=None,
-                 weights=None):
+                 weights=None, variant="schwarz"):
         import torch
         self.torch = torch
         self.lib = load()
@@ -201,7 +216,8 @@ class Encoder:
         self.nctrl = tuple(sum(s) for s in self.sizes)
         self.device = torch.device(device)
         self.prob, self._keep = make_problem(npts, degree, sizes, overlap, precision, combine, rhs,
-                                             extent, weights)
+                                             extent, weights, variant)
+        self.nctrl = ctrl_dims_of(self.prob)
         nbytes = c_size_t(0)
         check(self.lib.mfa_workspace_size(ctypes.byref(self.prob), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
@@ -275,6 +291,7 @@ class Encoder:
     # -- the ABI
     def encode(self, q, max_sweeps, jump_tol=0.0, check_every=1, raise_on_notconv=True):
         self._check_q(q)
+        self._q = q   # the handle reads the data again (steps without q, fit_error)
         st = mfa_step_stats()
         s = self.lib.mfa_encode(self.handle, c_void_p(q.data_ptr()), self._dt(q), int(max_sweeps),
                                 float(jump_tol), int(check_every), ctypes.byref(st))
@@ -287,6 +304,7 @@ class Encoder:
         st = mfa_step_stats()
         if q is not None:
             self._check_q(q)
+            self._q = q
             check(self.lib.mfa_schwarz_step(self.handle, c_void_p(q.data_ptr()), self._dt(q),
                                             ctypes.byref(st)))
         else:

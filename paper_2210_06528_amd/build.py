@@ -25,6 +25,7 @@ FLAGS = [
     "-I", INCLUDE, "-I", CSRC,
 ]
 SOURCES = ["setup.hip", "passes.hip", "sweep.hip", "metrics.hip", "mfma.hip", "grid.hip", "noalloc.hip",
+           "variants.hip",
            "plan.cpp", "api.cpp"]
 
 

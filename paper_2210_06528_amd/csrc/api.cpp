@@ -77,6 +77,11 @@ mfa_status hip_fail(hipError_t e, const char *where) {
   } while (0)
 
 Dims ctrl_dims(const Handle &h) { return Dims{{h.ax[0].n, h.ax[1].n, h.ax[2].n}}; }
+// control grid of the model the handle encodes (the variants' own layouts)
+Dims model_dims(const Handle &h) {
+  if (!h.variant) return ctrl_dims(h);
+  return Dims{{h.ax[0].nv, h.ax[1].nv, h.ax[2].nv}};
+}
 Dims data_dims(const Handle &h) { return Dims{{h.ax[0].m, h.ax[1].m, h.ax[2].m}}; }
 
 struct Step {
@@ -423,7 +428,7 @@ mfa_status residual_stats(Handle &h, double *res_max, double *res_l2) {
   if (e != hipSuccess) return hip_fail(e, "residual");
   const bool f32 = h.q_dtype == MFA_F32;
   bool done = false;
-  if (grid_pass_ok(h)) {
+  if (grid_pass_ok(h) && !h.variant) {
     const int r[3] = {0, 0, 0};
     e = launch_decode_grid(h, const_cast<void *>(h.q), f32, r, h.res_slots);
     if (e == hipSuccess) done = true;
@@ -432,10 +437,10 @@ mfa_status residual_stats(Handle &h, double *res_max, double *res_l2) {
   if (!done) {
     std::vector<Step> st;
     for (int a = 2; a >= 0; --a)
-      if (h.ax[a].active) st.push_back({a, &h.ax[a].N[0]});
+      if (h.ax[a].active) st.push_back({a, h.variant ? &h.ax[a].Nv[0] : &h.ax[a].N[0]});
     unsigned long long *saved = h.slots;
     h.slots = h.res_slots;   // the last pass reduces into the residual slots
-    e = run_chain<double, double>(h, h.P, ctrl_dims(h), st, (double *)nullptr,
+    e = run_chain<double, double>(h, h.P, model_dims(h), st, (double *)nullptr,
                                   f32 ? EPI_RESID32 : EPI_RESID64, (const double *)h.q, 0, nullptr,
                                   0, h.s1, h.s2);
     h.slots = saved;
@@ -455,6 +460,72 @@ mfa_status residual_stats(Handle &h, double *res_max, double *res_l2) {
   }
   std::memcpy(res_max, &mx, sizeof(double));
   *res_l2 = std::sqrt(sq);
+  return MFA_OK;
+}
+
+// One-shot fit of the DECOUPLED / CLAMPED variants: P = (L_0 x L_1 x L_2) Q
+// through the pass chain, then max |P| and the interface jumps of the model
+// (rows along the interface axis, decode rows on the others), normalised by
+// max |P|.
+mfa_status encode_variant(Handle &h, mfa_step_stats *out) {
+  const int64_t nset = (int64_t)kNumSlots * kSlotCopies;
+  h.slots = h.slot_base;
+  hipError_t e = launch_zero_slots(h.stream, h.slots, (int)nset);
+  if (e != hipSuccess) return hip_fail(e, "zero slots");
+  std::vector<Step> st;
+  for (int a = 2; a >= 0; --a)
+    if (h.ax[a].active) st.push_back({a, &h.ax[a].Lv});
+  e = h.q_dtype == MFA_F32
+          ? run_chain<float, double>(h, (const float *)h.q, data_dims(h), st, h.P, EPI_STORE, nullptr,
+                                     0, nullptr, 0, h.s1, h.s2)
+          : run_chain<double, double>(h, (const double *)h.q, data_dims(h), st, h.P, EPI_STORE,
+                                      nullptr, 0, nullptr, 0, h.s1, h.s2);
+  if (e != hipSuccess) return hip_fail(e, "variant fit");
+  if ((e = launch_maxabs(h.stream, h.P, h.nctrl_total, h.slots + (size_t)kSlotCtrl * kSlotCopies)) !=
+      hipSuccess)
+    return hip_fail(e, "variant fit");
+  const Dims md = model_dims(h);
+  for (int a = 0; a < 3; ++a) {
+    if (!h.ax[a].active || h.ax[a].B < 2) continue;
+    std::vector<Step> js{{a, &h.ax[a].Jv}};
+    for (int c = 0; c < 3; ++c)
+      if (c != a && h.ax[c].active) js.push_back({c, &h.ax[c].Nv[0]});
+    e = run_chain<double, double>(h, h.P, md, js, (double *)nullptr, EPI_MAXABS, nullptr,
+                                  kSlotJ + a * kMaxP, h.ax[a].d_gidJ, a, h.s1, h.s2);
+    if (e != hipSuccess) return hip_fail(e, "variant jumps");
+  }
+  std::vector<unsigned long long> raw((size_t)kNumSlots * kSlotCopies);
+  HIP_CHECK(hipMemcpyAsync(raw.data(), h.slots, sizeof(unsigned long long) * raw.size(),
+                           hipMemcpyDeviceToHost, h.stream), "variant stats");
+  HIP_CHECK(hipStreamSynchronize(h.stream), "variant stats");
+  auto val = [&](int s) {
+    unsigned long long m = 0;
+    for (int c = 0; c < kSlotCopies; ++c) m = std::max(m, raw[(size_t)s * kSlotCopies + c]);
+    double d;
+    std::memcpy(&d, &m, sizeof(d));
+    return d;
+  };
+  mfa_step_stats s{};
+  s.sweep = 1;
+  s.converged = 1;
+  s.ctrl_max = val(kSlotCtrl);
+  s.max_dP = s.ctrl_max;
+  s.nres_max = 0.0;
+  s.res_max = s.res_l2 = std::numeric_limits<double>::quiet_NaN();
+  bool fin = std::isfinite(s.ctrl_max);
+  for (int r = 0; r < h.p; ++r) {
+    double jr = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      if (!h.ax[a].active || h.ax[a].B < 2) continue;
+      const double rj = val(kSlotJ + a * kMaxP + r);
+      if (!std::isfinite(rj)) fin = false;
+      jr = std::max(jr, s.ctrl_max > 0.0 ? rj / s.ctrl_max : 0.0);
+    }
+    s.jump[r] = jr;
+  }
+  h.sweep = 1;
+  if (out) *out = s;
+  if (!fin) return fail(MFA_ENOTCONV, "non-finite value in the fit");
   return MFA_OK;
 }
 
@@ -593,8 +664,11 @@ mfa_status create_handle(const mfa_problem *prob, void *workspace, size_t bytes,
       st = aux->s[used - 1];
       if ((e = hipStreamWaitEvent(st, aux->fork, 0)) != hipSuccess) return bail(e, "fork");
     }
-    if ((e = setup_axis(&h, a, st)) != hipSuccess) return bail(e, "setup");
+    if (h.variant != MFA_VARIANT_CLAMPED && (e = setup_axis(&h, a, st)) != hipSuccess)
+      return bail(e, "setup");
     if (h.precision == MFA_PREC_MIXED_BF16 && (e = setup_mfma(&h, a, st)) != hipSuccess)
+      return bail(e, "setup");
+    if (h.variant != MFA_VARIANT_SCHWARZ && (e = setup_variant_axis(&h, a, st)) != hipSuccess)
       return bail(e, "setup");
     if (fork) {
       if ((e = hipEventRecord(aux->join[used - 1], st)) != hipSuccess) return bail(e, "join");
@@ -618,6 +692,15 @@ mfa_status create_handle(const mfa_problem *prob, void *workspace, size_t bytes,
 }  // namespace
 
 extern "C" {
+
+mfa_status mfa_ctrl_dims(const mfa_problem *prob, int64_t dims[3]) {
+  if (!prob || !dims) return fail(MFA_EINVAL, "null pointer");
+  Handle tmp;
+  std::string msg = plan_problem(*prob, &tmp);
+  if (!msg.empty()) return fail(MFA_EINVAL, msg);
+  for (int a = 0; a < 3; ++a) dims[a] = a < tmp.dim ? tmp.ax[a + 3 - tmp.dim].nv : 0;
+  return MFA_OK;
+}
 
 mfa_status mfa_create(const mfa_problem *prob, void *workspace, size_t bytes, void *hip_stream,
                       mfa_handle **out) {
@@ -690,7 +773,7 @@ static mfa_status load_q(Handle &h, const void *q, mfa_dtype dt) {
   if (dt != MFA_F32 && dt != MFA_F64) return fail(MFA_EINVAL, "bad dtype");
   h.q = q;
   h.q_dtype = dt;
-  if (h.rhs == MFA_RHS_DATABOX) {   // the data are read on every sweep
+  if (h.rhs == MFA_RHS_DATABOX || h.variant) {   // the data are read by every sweep / the fit
     h.have_rhs = true;
     return MFA_OK;
   }
@@ -762,6 +845,11 @@ mfa_status mfa_schwarz_step(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype,
   } else if (!h.have_rhs) {
     return fail(MFA_EINVAL, "no data loaded: pass q_dev");
   }
+  if (h.variant) {
+    mfa_status sv = encode_variant(h, out);
+    if (sv == MFA_OK && out) sv = residual_stats(h, &out->res_max, &out->res_l2);
+    return sv;
+  }
   mfa_status s = do_sweep(h, true);
   if (s != MFA_OK) return s;
   bool finite = true;
@@ -781,6 +869,10 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
   hipSetDevice(h.device);
   mfa_status s = load_q(h, q_dev, q_dtype);
   if (s != MFA_OK) return s;
+  if (h.variant) {   // one-shot fit, no sweeps
+    h.warm = false;
+    return encode_variant(h, last);
+  }
   h.sweep = 0;
   if (!h.warm) {
     hipError_t e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0);
@@ -860,12 +952,12 @@ mfa_status mfa_decode(mfa_handle *H, void *out_dev, mfa_dtype out_dtype, const i
     int r = 0;
     if (deriv) r = deriv[a - (3 - h.dim)];
     if (r < 0 || r > h.p) return fail(MFA_EINVAL, "derivative order out of range");
-    st.push_back({a, &h.ax[a].N[r]});
+    st.push_back({a, h.variant ? &h.ax[a].Nv[r] : &h.ax[a].N[r]});
   }
   hipError_t e;
   TimeScope ts(h, MFA_K_DECODE);
   if (out_dtype != MFA_F32 && out_dtype != MFA_F64) return fail(MFA_EINVAL, "bad dtype");
-  if (grid_pass_ok(h)) {
+  if (grid_pass_ok(h) && !h.variant) {
     int r[3] = {0, 0, 0};
     for (int a = 0; a < 3; ++a)
       if (h.ax[a].active && deriv) r[a] = deriv[a - (3 - h.dim)];
@@ -874,10 +966,10 @@ mfa_status mfa_decode(mfa_handle *H, void *out_dev, mfa_dtype out_dtype, const i
     if (e != hipErrorNotSupported) return hip_fail(e, "decode");
   }
   if (out_dtype == MFA_F32)
-    e = run_chain<double, float>(h, h.P, ctrl_dims(h), st, (float *)out_dev, EPI_STORE, nullptr, 0,
+    e = run_chain<double, float>(h, h.P, model_dims(h), st, (float *)out_dev, EPI_STORE, nullptr, 0,
                                  nullptr, 0, h.s1, h.s2);
   else if (out_dtype == MFA_F64)
-    e = run_chain<double, double>(h, h.P, ctrl_dims(h), st, (double *)out_dev, EPI_STORE, nullptr, 0,
+    e = run_chain<double, double>(h, h.P, model_dims(h), st, (double *)out_dev, EPI_STORE, nullptr, 0,
                                   nullptr, 0, h.s1, h.s2);
   else
     return fail(MFA_EINVAL, "bad dtype");
@@ -892,6 +984,7 @@ mfa_status mfa_decode_points(mfa_handle *H, const double *u_dev, int64_t npoints
   if (npoints > 0 && (!u_dev || !out_dev)) return fail(MFA_EINVAL, "null pointer");
   if (out_dtype != MFA_F32 && out_dtype != MFA_F64) return fail(MFA_EINVAL, "bad dtype");
   Handle &h = H->h;
+  if (h.variant) return fail(MFA_EINVAL, "decode at points is for the Schwarz model only");
   hipSetDevice(h.device);
   int r[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a) {
@@ -949,6 +1042,7 @@ mfa_status mfa_inspect(mfa_handle *H, int32_t table, int32_t axis, int32_t block
                        size_t count, size_t *needed) {
   if (mfa_status s0 = check_handle(H)) return s0;
   Handle &h = H->h;
+  if (h.variant == MFA_VARIANT_CLAMPED) return fail(MFA_EINVAL, "no such table for the clamped variant");
   hipSetDevice(h.device);
   if (table != MFA_T_RHS && (axis < 0 || axis >= h.dim)) return fail(MFA_EINVAL, "axis out of range");
   const Axis &X = h.ax[table == MFA_T_RHS ? 0 : axis + 3 - h.dim];

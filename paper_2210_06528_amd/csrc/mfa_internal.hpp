@@ -46,6 +46,16 @@ struct Axis {
   double dscale = 1.0;  // du/dx = 1 / (hi - lo): derivative tables carry dscale^r
   std::vector<double> w;          // NURBS weights (empty: all 1)
   double *d_w = nullptr;          // device copy of w (null when unweighted)
+  // variants (DECOUPLED, CLAMPED): the model's control count along the axis
+  // and its fit / decode / interface-jump operators
+  int nv = 0;
+  std::vector<int> ccut;          // CLAMPED: data index of each block boundary (B+1)
+  std::vector<int> coff, csz;     // CLAMPED: first control point and size of each block
+  int *d_ccut = nullptr, *d_coff = nullptr, *d_csz = nullptr;
+  int64_t LLv = 0;                // widest fit row (data points of one block)
+  Ell Lv;                         // nv x m: data -> control points
+  Ell Nv[kMaxP + 1];              // m x nv: decode, derivative order 0..p
+  Ell Jv;                         // (B-1)p x nv: interface derivative differences
   std::vector<Block> blk;
   std::vector<int> ns;            // subdomains whose free set holds each ctrl
   std::vector<int> blo, bhi;      // first / last block whose free set holds ctrl k
@@ -96,7 +106,7 @@ struct Axis {
 
 struct Handle {
   mfa_problem prob{};
-  int dim = 0, p = 0, overlap = 0, precision = 0, combine = 0, rhs = 0;
+  int dim = 0, p = 0, overlap = 0, precision = 0, combine = 0, rhs = 0, variant = 0;
   Axis ax[3];
   hipStream_t stream = nullptr;
   int device = 0;
@@ -218,6 +228,9 @@ hipError_t upload_plan(Handle *h);
 hipError_t launch_decode_points(Handle &h, const double *u, int64_t npts, void *out, bool f32,
                                 const int r[3]);
 hipError_t setup_axis(Handle *h, int a, hipStream_t st);
+// operator tables of the DECOUPLED / CLAMPED variants (after setup_axis for
+// DECOUPLED; alone for CLAMPED)
+hipError_t setup_variant_axis(Handle *h, int a, hipStream_t st);
 
 // sweep kernels
 template <typename TG>

@@ -54,6 +54,10 @@ std::string plan_problem(const mfa_problem &prob, Handle *h) {
   if (prob.precision < 0 || prob.precision > 2) return "precision out of range";
   if (prob.combine < 0 || prob.combine > 1) return "combine out of range";
   if (prob.rhs < 0 || prob.rhs > 1) return "rhs out of range";
+  if (prob.variant < 0 || prob.variant > 2) return "variant out of range";
+  if (prob.variant != MFA_VARIANT_SCHWARZ &&
+      (prob.precision != MFA_PREC_FP64 || prob.rhs != MFA_RHS_NORMAL))
+    return "the decoupled and clamped variants take precision FP64 and rhs NORMAL";
   h->prob = prob;
   h->dim = prob.dim;
   h->p = p;
@@ -61,6 +65,7 @@ std::string plan_problem(const mfa_problem &prob, Handle *h) {
   h->precision = prob.precision;
   h->combine = prob.combine;
   h->rhs = prob.rhs;
+  h->variant = prob.variant;
   const int o = prob.overlap;
   const int minov = std::max(1, p / 2);
   h->nctrl_total = 1;
@@ -89,6 +94,40 @@ std::string plan_problem(const mfa_problem &prob, Handle *h) {
       X.w.assign(prob.weights[a], prob.weights[a] + n);
       for (double v : X.w)
         if (!std::isfinite(v) || !(v > 0.0)) return "a weight is not positive and finite";
+    }
+    if (prob.variant == MFA_VARIANT_CLAMPED) {
+      // own clamped knots per block; neighbours share the interface control
+      // point; interface b sits on the data point nearest to (m-1) x (spans
+      // before it) / (all spans), halves rounded up
+      if (!X.w.empty()) return "the clamped variant takes no weights";
+      if (X.m < 2) return "fewer than 2 data points on an axis";
+      int64_t tot = 0;
+      for (int b = 0; b < X.B; ++b) {
+        if (prob.nctrl[a][b] < p + 1) return "a clamped block needs at least p+1 control points";
+        tot += prob.nctrl[a][b] - p;
+      }
+      X.ccut.assign(X.B + 1, 0);
+      X.coff.assign(X.B, 0);
+      X.csz.assign(X.B, 0);
+      int64_t acc = 0;
+      for (int b = 0; b + 1 < X.B; ++b) {
+        acc += prob.nctrl[a][b] - p;
+        X.ccut[b + 1] = (int)(((X.m - 1) * acc * 2 + tot) / (2 * tot));
+      }
+      X.ccut[X.B] = (int)(X.m - 1);
+      X.LLv = 0;
+      for (int b = 0; b < X.B; ++b) {
+        X.csz[b] = prob.nctrl[a][b];
+        X.coff[b] = b == 0 ? 0 : X.coff[b - 1] + X.csz[b - 1] - 1;
+        const int64_t nd = (int64_t)X.ccut[b + 1] - X.ccut[b] + 1;
+        if (nd < X.csz[b]) return "a clamped block has fewer data points than control points";
+        X.LLv = std::max(X.LLv, nd);
+      }
+      X.nv = n - (X.B - 1);
+      X.n = X.nv;
+      h->nctrl_total *= X.nv;
+      h->npts_total *= X.m;
+      continue;
     }
     if (n < p + 1) return "fewer than p+1 control points on an axis";
     if (X.m < 2) return "fewer than 2 data points on an axis";
@@ -211,9 +250,17 @@ std::string plan_problem(const mfa_problem &prob, Handle *h) {
     }
     X.doff[X.B] = X.SD;
     X.foff[X.B] = X.SF;
-    h->nctrl_total *= n;
+    X.nv = n;
+    if (prob.variant == MFA_VARIANT_DECOUPLED) {
+      X.nv = (int)X.SF;
+      X.LLv = 0;
+      for (int b = 0; b < X.B; ++b) X.LLv = std::max<int64_t>(X.LLv, X.blk[b].D1 - X.blk[b].D0);
+    }
+    h->nctrl_total *= X.nv;
     h->npts_total *= m;
   }
+  for (int ia = 0; ia < 3; ++ia)
+    if (!h->ax[ia].active) h->ax[ia].nv = 1;
   return "";
 }
 
@@ -243,7 +290,92 @@ struct Bump {
 
 }  // namespace
 
+// Largest intermediates of the pass chains between the data grid and a
+// control grid with cn[a] control points per axis: the fit / projection chain
+// (axis 2 first), the decode chain (axis 2 first) and every jump chain (rows
+// along the interface axis, then the data points of the other axes).  A
+// chain's last pass writes its output directly.
+static void chain_scratch(const Handle *h, const int64_t cn[3], int64_t *s1, int64_t *s2) {
+  auto upd = [&](int which, int64_t v) {
+    if (which == 0) *s1 = std::max(*s1, v);
+    else *s2 = std::max(*s2, v);
+  };
+  int first = 0;
+  while (first < 2 && !h->ax[first].active) ++first;
+  Dims d{{h->ax[0].m, h->ax[1].m, h->ax[2].m}};
+  int w = 0;
+  for (int ia = 2; ia > first; --ia) {
+    if (!h->ax[ia].active) continue;
+    d.d[ia] = cn[ia];
+    upd(w, d.total());
+    w ^= 1;
+  }
+  Dims e{{cn[0], cn[1], cn[2]}};
+  w = 0;
+  for (int ia = 2; ia > first; --ia) {
+    if (!h->ax[ia].active) continue;
+    e.d[ia] = h->ax[ia].m;
+    upd(w, e.total());
+    w ^= 1;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!h->ax[a].active || h->ax[a].B < 2) continue;
+    Dims j{{cn[0], cn[1], cn[2]}};
+    j.d[a] = (int64_t)(h->ax[a].B - 1) * h->p;
+    w = 0;
+    upd(w, j.total());
+    for (int c = 0; c < 3; ++c) {
+      if (c == a || !h->ax[c].active) continue;
+      w ^= 1;
+      j.d[c] = h->ax[c].m;
+      upd(w, j.total());
+    }
+  }
+}
+
+// Workspace of the CLAMPED variant: its block tables, fit / decode / jump
+// operators, control points and chain scratch only.
+static size_t layout_clamped(Handle *h, char *base) {
+  Bump bp(base);
+  const int p = h->p;
+  for (int ia = 0; ia < 3; ++ia) {
+    Axis &X = h->ax[ia];
+    if (!X.active) continue;
+    X.d_ccut = bp.take<int>(X.B + 1);
+    X.d_coff = bp.take<int>(X.B);
+    X.d_csz = bp.take<int>(X.B);
+  }
+  h->upload_bytes = bp.off;
+  for (int ia = 0; ia < 3; ++ia) {
+    Axis &X = h->ax[ia];
+    if (!X.active) continue;
+    const int nif = X.B - 1;
+    bp.ell(X.Lv, X.nv, (int)X.m, X.LLv, false);
+    for (int r = 0; r <= p; ++r) bp.ell(X.Nv[r], (int)X.m, X.nv, p + 1, false);
+    bp.ell(X.Jv, nif * p, X.nv, 2 * (p + 1), false);
+    X.d_gidJ = bp.take<int>((int64_t)nif * p);
+  }
+  const int64_t NC = h->nctrl_total;
+  h->c = bp.take<double>(1);
+  h->P = bp.take<double>(NC);
+  h->g = bp.take<double>(1);
+  const int64_t cn[3] = {h->ax[0].nv, h->ax[1].nv, h->ax[2].nv};
+  int64_t s1 = NC, s2 = NC;
+  chain_scratch(h, cn, &s1, &s2);
+  h->s1 = bp.take<double>(s1);
+  h->s2 = bp.take<double>(s2);
+  h->s1n = s1;
+  h->s2n = s2;
+  h->slot_base = bp.take<unsigned long long>(2 * (int64_t)kNumSlots * kSlotCopies);
+  h->slots = h->slot_base;
+  h->flag = bp.take<int>(4);
+  h->hist = bp.take<double>(kHist);
+  h->res_slots = bp.take<unsigned long long>(2 * (int64_t)kSlotCopies);
+  return bp.off + 256;
+}
+
 size_t layout_workspace(Handle *h, char *base) {
+  if (h->variant == MFA_VARIANT_CLAMPED) return layout_clamped(h, base);
   Bump bp(base);
   const int p = h->p;
   const bool mixed = h->precision != MFA_PREC_FP64;
@@ -300,6 +432,11 @@ size_t layout_workspace(Handle *h, char *base) {
     X.d_omT = bp.take<double>((int64_t)X.Om.L * m);
     bp.ell(X.J, nif * p, n, X.LJ, false);
     bp.ell(X.D, (int)X.ND, n, p, false);
+    if (h->variant == MFA_VARIANT_DECOUPLED) {
+      bp.ell(X.Lv, X.nv, (int)m, X.LLv, false);
+      for (int r = 0; r <= p; ++r) bp.ell(X.Nv[r], (int)m, X.nv, p + 1, false);
+      bp.ell(X.Jv, nif * p, X.nv, 2 * (p + 1), false);
+    }
     if (h->rhs == MFA_RHS_DATABOX) {
       bp.ell(X.Nseg, (int)X.SD, n, p + 1, false);
       bp.ell(X.NsegT, (int)X.SF, (int)X.SD, X.LNsT, false);
@@ -370,6 +507,10 @@ size_t layout_workspace(Handle *h, char *base) {
         upd(w, j.total());
       }
     }
+  }
+  if (h->variant == MFA_VARIANT_DECOUPLED) {
+    const int64_t cn[3] = {h->ax[0].nv, h->ax[1].nv, h->ax[2].nv};
+    chain_scratch(h, cn, &s1, &s2);
   }
   h->s1 = bp.take<double>(s1);
   h->s2 = bp.take<double>(s2);

@@ -170,3 +170,26 @@ def test_bad_weights_rejected(lib, bad):
     assert b"weight" in lib.mfa_last_error()
     ok, keep2 = _lib.make_problem((100,), 3, [[20, 20]], 2, weights=[np.full(40, 2.0)])
     assert lib.mfa_workspace_size(ctypes.byref(ok), ctypes.byref(out)) == _lib.MFA_OK
+
+
+def test_variant_ctrl_dims_and_validation(lib):
+    from oracle import schwarz, variants
+    npts, sizes, p = (61, 47), [[9, 9], [7, 8, 7]], 3
+    prob, keep = _lib.make_problem(npts, p, sizes, 2, variant="clamped")
+    axes = variants.plan_clamped(npts, p, sizes)
+    assert _lib.ctrl_dims_of(prob) == tuple(ax.n for ax in axes)
+    prob, keep = _lib.make_problem(npts, p, sizes, 2, variant="decoupled")
+    plan = schwarz.make_plan(npts, p, sizes, 2)
+    assert _lib.ctrl_dims_of(prob) == tuple(sum(b.F1 - b.F0 for b in ax.blocks) for ax in plan.axes)
+    prob, keep = _lib.make_problem(npts, p, sizes, 2)
+    assert _lib.ctrl_dims_of(prob) == tuple(sum(s) for s in sizes)
+    for kw in (dict(precision="mixed_bf16", variant="clamped"),
+               dict(rhs="databox", variant="decoupled"),
+               dict(variant=3)):
+        with pytest.raises(_lib.MfaError):
+            _lib.workspace_size(npts, p, sizes, 2, **kw)
+    # a clamped block with fewer data points than control points
+    with pytest.raises(_lib.MfaError):
+        _lib.workspace_size((20,), 3, [[12, 12]], 2, variant="clamped")
+    with pytest.raises(_lib.MfaError):
+        _lib.workspace_size((100,), 3, [[20, 20]], 2, variant="clamped", precision="mixed_fp32")
