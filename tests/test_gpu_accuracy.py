@@ -92,3 +92,39 @@ def test_mixed_precision_on_the_radial_field():
     st = enc.encode(torch.from_numpy(Q).cuda(), 300, w.jump_tol, 0)
     assert st["converged"]
     assert _rel(enc.decode().cpu().numpy(), fstar) < 1e-6
+
+
+def test_clamped_vs_floating_knots_section_3_1_1():
+    """Section 3.1.1 on the asymmetric sinc sum (10^4 points, p = 3, two
+    subdomains, 32 control points in all): the clamped interface is C^0 but
+    its first derivative jumps; the decoupled local fits jump in value; the
+    floating knots converge to jumps below 1e-8 in every order below p, and
+    with the augmented overlap (delta = p) the converged profile is the
+    single-subdomain one.  Each GPU model is also checked against the
+    oracle's model of the same data."""
+    from oracle import variants
+    w1 = W.cfg_e1(overlap=1)
+    Q = W.make_field(w1)
+    q = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    S = _setup(w1)
+    fstar = schwarz.decode(S, schwarz.global_direct(S, Q))
+    # clamped: two blocks of 16 and 17 control points sharing one (32 in all)
+    cl = _lib.Encoder(w1.npts, 3, [[16, 17]], 1, "fp64", variant="clamped")
+    st_c = cl.encode(q, 1, 0.0)
+    axes = variants.plan_clamped(w1.npts, 3, [[16, 17]])
+    Pc = variants.clamped_fit(axes, Q)
+    assert _rel(cl.get_ctrl().cpu().numpy(), Pc) < 1e-10
+    assert st_c["jump"][0] < 1e-12 and st_c["jump"][1] > 1e-6
+    # decoupled local fits on the floating knots
+    dc = _lib.Encoder(w1.npts, 3, w1.sizes, 1, "fp64", variant="decoupled")
+    st_d = dc.encode(q, 1, 0.0)
+    assert st_d["jump"][0] > 1e-6
+    fd = dc.decode().cpu().numpy()
+    assert _rel(fd, variants.decoupled_decode(S, variants.decoupled_fit(S, Q))) < 1e-10
+    # floating knots, minimum overlap and delta = p, converged
+    for o in (1, 4):
+        w = W.cfg_e1(overlap=o)
+        enc = _enc(w)
+        st = enc.encode(q, 300, 1e-8, 1)
+        assert st["converged"] and max(st["jump"]) < 1e-8
+        assert _rel(enc.decode().cpu().numpy(), fstar) < 1e-8
