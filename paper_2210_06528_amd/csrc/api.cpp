@@ -1,6 +1,9 @@
 // C ABI of the MFA encoder: handle lifecycle, Schwarz sweeps, encode loop,
 // decode and inspection.  See include/mfa.h for the contract of each call.
 #include <algorithm>
+#include <tuple>
+#include <mutex>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -179,6 +182,73 @@ hipError_t correct_bsolve(Handle &h, const T *g) {
   return hipSuccess;
 }
 
+// Autotuned choice between the fused axis-2/axis-1 split-BF16 correction and
+// the two separate passes.  Both map g to the same intermediate s1 with the
+// same arithmetic (bitwise equal) and neither touches P or the reduction
+// slots, so for a large shape the first sweep times both on the live arrays
+// (three runs each, HIP events, fastest kept) and the choice is cached per
+// shape class for the process: the padded band widths of axes 1 and 2, the
+// degree, the combine rule and axis 0's length in steps of 32.  A candidate
+// replaces the fused default only if it is at least 10% faster.  Small
+// shapes, handles without auxiliary objects (no-allocation) and event-timed
+// runs take the fused default untimed.
+struct CorrKey {
+  int np1, np2, p, comb, n0c;
+  bool operator<(const CorrKey &o) const {
+    return std::tie(np1, np2, p, comb, n0c) < std::tie(o.np1, o.np2, o.p, o.comb, o.n0c);
+  }
+};
+std::mutex g_corr_mu;
+std::map<CorrKey, bool> g_corr_fused;
+constexpr int64_t kCorrTuneMin = 1 << 20;
+
+hipError_t separate21(Handle &h, const float *gf, float *s1, float *s2) {
+  hipError_t e = launch_mfma_correct(h, 2, gf, s2, false);
+  if (e != hipSuccess) return e;
+  return launch_mfma_correct(h, 1, s2, s1, false);
+}
+
+hipError_t choose_fused21(Handle &h, const float *gf, bool *fused) {
+  *fused = h.fuse21 && h.ax[0].active && mfma_fused21_ok(h);
+  if (!*fused || h.nctrl_total < kCorrTuneMin || h.serial || h.timing) return hipSuccess;
+  const CorrKey key{h.ax[1].npad, h.ax[2].npad, h.p, h.combine, (h.ax[0].n + 31) / 32};
+  {
+    std::lock_guard<std::mutex> lk(g_corr_mu);
+    auto it = g_corr_fused.find(key);
+    if (it != g_corr_fused.end()) {
+      *fused = it->second;
+      return hipSuccess;
+    }
+  }
+  float *s1 = reinterpret_cast<float *>(h.s1), *s2 = reinterpret_cast<float *>(h.s2);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return hipErrorOutOfMemory;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return hipErrorOutOfMemory;
+  }
+  float best[2] = {1e30f, 1e30f};
+  hipError_t err = hipSuccess;
+  for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+    for (int c = 0; c < 2 && err == hipSuccess; ++c) {
+      hipEventRecord(e0, h.stream);
+      err = c == 0 ? launch_mfma_fused21(h, gf, s1) : separate21(h, gf, s1, s2);
+      hipEventRecord(e1, h.stream);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err == hipSuccess && rep > 0) best[c] = std::min(best[c], ms);   // rep 0 warms up
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (err != hipSuccess) return err;
+  *fused = !(best[1] < 0.9f * best[0]);
+  std::lock_guard<std::mutex> lk(g_corr_mu);
+  g_corr_fused[key] = *fused;
+  return hipSuccess;
+}
+
 // One sweep (NORMAL right-hand side):
 //   g = c - (A_0 x A_1 x A_2) P      (the local residuals N_F^T (Q - N P) of all
 //                                     subdomains at once)
@@ -197,7 +267,9 @@ hipError_t sweep_normal(Handle &h, const SlotTurn &turn) {
                               h.ax[2].d_acoef, n0, n1, n2, h.slots, turn, !h.serial);
     }
     if (e != hipSuccess) return e;
-    if (h.fuse21 && h.ax[0].active && mfma_fused21_ok(h)) {
+    bool fused = false;
+    if ((e = choose_fused21(h, gf, &fused)) != hipSuccess) return e;
+    if (fused) {
       // axes 2 and 1 in one pass, then axis 0 adds into P
       float *s1 = reinterpret_cast<float *>(h.s1);
       {
