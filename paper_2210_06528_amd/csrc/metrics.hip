@@ -291,7 +291,11 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
                                                             const double *__restrict__ Jval, int LJ) {
   extern __shared__ double smem_j[];
   double *sJ = smem_j;                                  // the J rows [nif*p][LJ]
-  SG *sg = reinterpret_cast<SG *>(sJ + (size_t)nif * p * LJ);   // [LPB][n2]
+  SG *sg = reinterpret_cast<SG *>(sJ + (size_t)nif * p * LJ);   // [LPB][ldg]
+  // staged lines ldg = n2 | 1 elements apart: the lanes of a wave read the
+  // same column of consecutive lines, which an even line length (n2 = 192:
+  // a multiple of the 32 banks) would put all in one LDS bank
+  const int ldg = n2 | 1;
   const int64_t l0 = (int64_t)blockIdx.x * LPB;
   const int nl = (int)min((int64_t)LPB, nlines - l0);
   for (int e = threadIdx.x; e < nif * p * LJ; e += blockDim.x) sJ[e] = Jval[e];
@@ -307,7 +311,10 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int e = e0 + threadIdx.x + blockDim.x * u;
-      if (e < nl * n2) sg[e] = v[u];
+      if (e < nl * n2) {
+        const int li = e / n2;
+        sg[li * ldg + (e - li * n2)] = v[u];
+      }
     }
   }
   __syncthreads();
@@ -316,7 +323,7 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
     const int row0 = b * p;
     const int c0 = Jcol[(int64_t)row0 * LJ];
     const int len = Jlen[row0];
-    const SG *x = sg + li * n2 + c0;
+    const SG *x = sg + li * ldg + c0;
     double acc[kMaxP];
 #pragma unroll
     for (int r = 0; r < kMaxP; ++r) acc[r] = 0.0;
@@ -561,8 +568,9 @@ hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U) {
     // staged lines: float for a float or BF16 residual (exact), else double;
     // up to 32 KB of them per workgroup
     using SG = typename std::conditional<sizeof(TG) <= 4, float, double>::type;
-    const int LPB = std::max(1, std::min(64, 32768 / ((int)sizeof(SG) * X.n)));
-    k_jump_project_lines<TG, SG><<<nblk(nlines, LPB), 256, sizeof(SG) * LPB * X.n + jbytes, h.stream>>>(
+    const int ldg = X.n | 1;
+    const int LPB = std::max(1, std::min(64, 32768 / ((int)sizeof(SG) * ldg)));
+    k_jump_project_lines<TG, SG><<<nblk(nlines, LPB), 256, sizeof(SG) * LPB * ldg + jbytes, h.stream>>>(
         g, U, nlines, X.n, X.B - 1, h.p, LPB, X.J.col, X.J.len, X.J.val, X.J.L);
     return hipGetLastError();
   }

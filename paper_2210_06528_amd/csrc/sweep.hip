@@ -68,7 +68,6 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
   constexpr int LZ = kTZ + 2 * P;
   __shared__ double tile[LY][LZ + 1];
   __shared__ double tz[LY][kTZ + 1];
-  __shared__ double azs[W][kTZ];   // axis-2 stencil rows of this tile's columns
   const int tx = threadIdx.x & 63;
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wavefront index 0..7
   const int z0 = blockIdx.x * kTZ, y0 = blockIdx.y * kTY, x0 = blockIdx.z * xchunk;
@@ -90,9 +89,13 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
     for (int e = threadIdx.x; e < kNumSlots * kSlotCopies; e += kRT) turn.prev[e] = 0ull;
   }
   const int gz = z0 + tx;
-  for (int e = threadIdx.x; e < W * kTZ; e += kRT) {
-    const int t = e / kTZ, zl = e - t * kTZ;
-    azs[t][zl] = A2[(int64_t)min(z0 + zl, n2 - 1) * W + t];
+  // this lane's axis-2 stencil row stays in registers (one LDS read per tap
+  // saved on every tile row of every plane)
+  double az[W];
+  {
+    const double *ar = A2 + (int64_t)min(gz, n2 - 1) * W;
+#pragma unroll
+    for (int t = 0; t < W; ++t) az[t] = ar[t];
   }
   double ring[W][kRY];
 #pragma unroll
@@ -177,20 +180,26 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
     for (int yy = ty; yy < LY; yy += kRT / 64) {
       double s = 0.0;
 #pragma unroll
-      for (int t = 0; t < W; ++t) s += azs[t][tx] * tile[yy][tx + t];
+      for (int t = 0; t < W; ++t) s += az[t] * tile[yy][tx + t];
       tz[yy][tx] = s;
     }
     __syncthreads();
+    {
+      // the kRY rows of a thread share W - 1 of their W taps: one read each
+      double tcol[W + kRY - 1];
 #pragma unroll
-    for (int r = 0; r < kRY; ++r) {
-      const int yl = ty * kRY + r;
-      const double *ay = A1 + (int64_t)min(y0 + yl, n1 - 1) * W;
-      double s = 0.0;
+      for (int t = 0; t < W + kRY - 1; ++t) tcol[t] = tz[ty * kRY + t][tx];
 #pragma unroll
-      for (int t = 0; t < W; ++t) s += ay[t] * tz[yl + t][tx];
+      for (int r = 0; r < kRY; ++r) {
+        const int yl = ty * kRY + r;
+        const double *ay = A1 + (int64_t)min(y0 + yl, n1 - 1) * W;
+        double s = 0.0;
 #pragma unroll
-      for (int t = 0; t < W - 1; ++t) ring[t][r] = ring[t + 1][r];
-      ring[W - 1][r] = s;
+        for (int t = 0; t < W; ++t) s += ay[t] * tcol[r + t];
+#pragma unroll
+        for (int t = 0; t < W - 1; ++t) ring[t][r] = ring[t + 1][r];
+        ring[W - 1][r] = s;
+      }
     }
     if (out_plane) {
 #pragma unroll
