@@ -70,7 +70,16 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
   __shared__ double tz[LY][kTZ + 1];
   const int tx = threadIdx.x & 63;
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wavefront index 0..7
-  const int z0 = blockIdx.x * kTZ, y0 = blockIdx.y * kTY, x0 = blockIdx.z * xchunk;
+  // Workgroups are dealt to the 8 XCDs round-robin in launch order.  Renumber
+  // them (a bijection) so that each XCD takes a contiguous run of tiles with
+  // y fastest, then z, then the x-chunk: tiles that share y and z halo rows
+  // then stream the same planes at the same time through one L2.
+  const unsigned gyz = gridDim.x * gridDim.y, G = gyz * gridDim.z;
+  const unsigned L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned xcd = L % 8, per = G / 8, rem = G % 8;
+  const unsigned lb = xcd * per + min(xcd, rem) + L / 8;
+  const unsigned tyi = lb % gridDim.y, tzi = (lb / gridDim.y) % gridDim.x, txi = lb / gyz;
+  const int z0 = tzi * kTZ, y0 = tyi * kTY, x0 = txi * xchunk;
   const int x1 = min(n0, x0 + xchunk);
   // slot bookkeeping (first workgroup): the previous sweep's max |correction|
   // into the history, then its slot set cleared for the next sweep; no other
