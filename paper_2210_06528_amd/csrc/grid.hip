@@ -16,11 +16,15 @@
 // therefore keeps just p+1 open control rows in registers: when the span
 // moves on, the oldest row has received all its contributions and is written
 // (projection), or the next control row is read (decode).
+#include <cstdlib>
+
 #include "mfa_internal.hpp"
 
 namespace mfa {
 
 namespace {
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 
 __device__ __forceinline__ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -217,8 +221,8 @@ __global__ void __launch_bounds__(256) k_proj_outer(const double *__restrict__ i
 // chunk of data rows i0 (grid.y) and 256 consecutive columns j (grid.x).  The
 // p+1 control rows under the current span sit in registers, the next one is
 // read ahead.
-template <int P>
-__global__ void __launch_bounds__(256) k_dec_outer(const double *__restrict__ in, double *__restrict__ out,
+template <int P, typename TO>
+__global__ void __launch_bounds__(256) k_dec_outer(const double *__restrict__ in, TO *__restrict__ out,
                                                    int64_t J, int I0C, Rows r0) {
   extern __shared__ __align__(16) unsigned char smem[];
   double *sw = reinterpret_cast<double *>(smem);                // [I0C][P+1]
@@ -252,7 +256,7 @@ __global__ void __launch_bounds__(256) k_dec_outer(const double *__restrict__ in
     double v = 0.0;
 #pragma unroll
     for (int q = 0; q <= P; ++q) v += w[q] * win[q];
-    out[(I0a + rr) * J + j] = v;
+    out[(I0a + rr) * J + j] = (TO)v;
   }
 }
 
@@ -374,6 +378,203 @@ __global__ void __launch_bounds__(256) k_dec_inner(const double *__restrict__ in
   if (RES) res_reduce(rs, rmax, rsq);
 }
 
+// ---------------------------------------------------------------------------
+// decode, axes 1 and 2 on the matrix cores (FP32 output).
+//
+// For one slab i0 and a tile of 16 data rows i1 = 16 I + j the slab's part
+// of the output is two banded products, U = N_1[tile] T (T the slab after
+// axis 0) and out = U N_2^T, each blocked into dense 16 x 16 tiles and run
+// as v_mfma_f32_16x16x4_f32 (FP32 operands, FP32 accumulation).  Operand
+// layout of that instruction (one wave): A[i][k] in lane i + 16 k, B[k][j]
+// in lane j + 16 k, D[i][j] in lane j + 16 (i / 4), register i % 4.
+//
+// Step 1 forms U transposed, one tile of 16 control columns k2 at a time:
+// D[k2][i1] = sum_k1 T[k1][k2] N_1[i1][k1] over the window of 4 KS control
+// rows k1 that starts at klo1(I), so that a lane ends up holding
+// U[16 I + lane % 16][16 J + 4 (lane / 16) + v] in register v.
+// Step 2 forms an output tile of 16 points i2, transposed:
+// D[i2][i1] = sum_k2 N_2[i2][k2] U[i1][k2].  The 16 columns of a U tile
+// enter as four K-steps v, step v pairing k2 = 16 J + 4 k + v with operand
+// slot k; the B operand of step v is then a lane's own U register v (no
+// data movement between the two products) and the A operand comes from a
+// table of N_2 laid out the same way, staged in LDS once per workgroup.  A
+// lane ends up holding out[16 I + lane % 16][16 J2 + 4 (lane / 16) + w],
+// w = 0..3: one 16-byte store.  The control window of an output tile starts
+// in U tile J0(J2) and reaches at most into J0 + 1 (checked on the host).
+// The loop runs over U tiles J and, inside, over the output tiles with
+// J0 = J; U tiles J and J + 1 sit in registers, the T operands of J + 2 and
+// J + 3 are in flight.  Vector memory then carries only those T requests and
+// the stores, so that waiting for one U tile's operands never waits for a
+// later request (the counters are in order).  Each wave owns one (i0, I).
+
+// Operand tables, built per decode from the basis rows of the requested
+// derivative orders:
+//   w1t[I][lane][s]      N_1[16 I + lane % 16][klo1(I) + 4 s + lane / 16]
+//   klo1[I]              span_1(16 I) - p
+//   w2t[J2][jj][lane][v] N_2[16 J2 + lane % 16][16 (J0 + jj) + 4 (lane / 16) + v]
+//   j0n[J2]              2 J0 + (window reaches tile J0 + 1), J0 = (span_2(16 J2) - p) / 16
+//   j2beg[J]             first output tile J2 with J0(J2) >= J, J = 0..ntk
+// (zero outside a row's p+1 non-zeros and past the last data point).
+template <int P>
+__global__ void __launch_bounds__(256) k_dec_tab(Rows r1, Rows r2, int nt1, int nt2, int ntk,
+                                                 float *__restrict__ w1t, int *__restrict__ klo1,
+                                                 float *__restrict__ w2t, int *__restrict__ j0n,
+                                                 int *__restrict__ j2beg) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n1e = (int64_t)nt1 * 64, n2e = (int64_t)nt2 * 128;
+  auto j0_of = [&](int J2) { return (r2.span[16 * (int64_t)J2] - P) / 16; };
+  if (t < n1e) {
+    const int I = (int)(t >> 6), l = (int)(t & 63);
+    const int64_t i1 = 16 * (int64_t)I + (l & 15);
+    const int lo = r1.span[16 * (int64_t)I] - P;
+    if (l == 0) klo1[I] = lo;
+    const bool ok = i1 < r1.m;
+    const int first = ok ? r1.span[i1] - P : 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int q = lo + 4 * s + (l >> 4) - first;
+      w1t[t * 4 + s] = ok && q >= 0 && q <= P ? (float)r1.val[i1 * r1.L + q] : 0.0f;
+    }
+  } else if (t < n1e + n2e) {
+    const int64_t u = t - n1e;
+    const int J2 = (int)(u >> 7), jj = (int)((u >> 6) & 1), l = (int)(u & 63);
+    const int64_t i2 = 16 * (int64_t)J2 + (l & 15);
+    const int J0 = j0_of(J2);
+    if (jj == 0 && l == 0) {
+      const int64_t last = min(16 * (int64_t)J2 + 15, r2.m - 1);
+      j0n[J2] = 2 * J0 + (r2.span[last] / 16 > J0 ? 1 : 0);
+    }
+    const bool ok = i2 < r2.m;
+    const int first = ok ? r2.span[i2] - P : 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = 16 * (J0 + jj) + 4 * (l >> 4) + v - first;
+      w2t[u * 4 + v] = ok && q >= 0 && q <= P ? (float)r2.val[i2 * r2.L + q] : 0.0f;
+    }
+  } else if (t <= n1e + n2e + ntk) {
+    const int J = (int)(t - n1e - n2e);
+    int J2 = 0;
+    while (J2 < nt2 && j0_of(J2) < J) ++J2;
+    j2beg[J] = J2;
+  }
+}
+
+__device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 d) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
+}
+
+template <typename TI, bool V4, int NTK>
+__global__ void __launch_bounds__(512) k_dec_mfma(const TI *__restrict__ T, float *__restrict__ out, int64_t m1,
+                                                  int64_t m2, int n1, int n2, int nt1, int nt2,
+                                                  const float *__restrict__ w1t, const int *__restrict__ klo1,
+                                                  const float *__restrict__ w2t, const int *__restrict__ j0n,
+                                                  const int *__restrict__ j2beg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ntk = (n2 + 15) >> 4;   // <= NTK
+  floatx4 *sw2 = reinterpret_cast<floatx4 *>(smem);   // [nt2][2][64]
+  int *sfl = reinterpret_cast<int *>(sw2 + (size_t)nt2 * 128);   // [nt2] two-tile flags
+  int *sbeg = sfl + nt2;                                          // [ntk + 1]
+  {
+    const floatx4 *src = reinterpret_cast<const floatx4 *>(w2t);
+    for (int e = threadIdx.x; e < nt2 * 128; e += blockDim.x) sw2[e] = src[e];
+    for (int e = threadIdx.x; e < nt2; e += blockDim.x) sfl[e] = j0n[e] & 1;
+    for (int e = threadIdx.x; e <= ntk; e += blockDim.x) sbeg[e] = j2beg[e];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int I = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (I >= nt1) return;   // whole waves, after the only barrier
+  const int g = lane >> 4, c = lane & 15;
+  const TI *Ts = T + (int64_t)blockIdx.y * n1 * n2;
+  const floatx4 b1 = *reinterpret_cast<const floatx4 *>(w1t + ((int64_t)I * 64 + lane) * 4);
+  const int lo1 = klo1[I];
+  int roff[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) roff[s] = min(lo1 + 4 * s + g, n1 - 1) * n2;
+  // Every T operand of the wave is requested at once (tile indices past the
+  // last are clamped to it: in bounds, never read by an output tile), then
+  // the U tiles are formed in order.
+  float tv[NTK][4];
+#pragma unroll
+  for (int J = 0; J < NTK; ++J) {
+    const int col = min(16 * min(J, ntk - 1) + c, n2 - 1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) tv[J][s] = (float)Ts[roff[s] + col];
+  }
+  floatx4 U[NTK];
+#pragma unroll
+  for (int J = 0; J < NTK; ++J) {
+    floatx4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) d = mfma_f32(tv[J][s], b1[s], d);
+    U[J] = d;
+  }
+  const int64_t i1 = 16 * (int64_t)I + c;
+  const bool rowok = i1 < m1;
+  float *oslab = out + (int64_t)blockIdx.y * m1 * m2;
+  float *orow = oslab + min(i1, m1 - 1) * m2 + 4 * g;
+  const floatx4 *a2 = sw2 + lane;
+  // Output tiles go out in pairs (J2 even, J2 + 1): the pair's 16 rows x 32
+  // columns are regrouped across lanes so that each store instruction covers
+  // 8 whole rows of 128 bytes (a lane takes 4 columns of one row from the
+  // lane that formed them), instead of 16 rows of 64 bytes per tile.
+  auto store_pair = [&](const floatx4 &d0, const floatx4 &d1, int J2a) {
+    const int q = lane & 7;   // column block of 4 within the pair
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int sc = 8 * k + (lane >> 3);           // row within the tile
+      const int addr = (((q & 3) << 4) + sc) << 2;  // lane holding that row's block q
+      floatx4 v;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const float x0 = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(d0[w])));
+        const float x1 = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(d1[w])));
+        v[w] = q < 4 ? x0 : x1;
+      }
+      const int64_t r = 16 * (int64_t)I + sc, col = 16 * (int64_t)J2a + 4 * q;
+      if (r < m1 && col < m2) *reinterpret_cast<floatx4 *>(oslab + r * m2 + col) = v;
+    }
+  };
+  floatx4 dprev = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int J = 0; J < NTK; ++J) {
+    const floatx4 ua = U[J], ub = U[J + 1 < NTK ? J + 1 : J];
+    // output tiles whose control window starts in U tile J (none past ntk)
+    const int e0 = J < ntk ? __builtin_amdgcn_readfirstlane(sbeg[J]) : 0;
+    const int e1 = J < ntk ? __builtin_amdgcn_readfirstlane(sbeg[J + 1]) : 0;
+    for (int J2 = e0; J2 < e1; ++J2) {
+      const floatx4 a0 = a2[J2 * 128];
+      const int two = __builtin_amdgcn_readfirstlane(sfl[J2]);
+      floatx4 d = {0.f, 0.f, 0.f, 0.f};
+      d = mfma_f32(a0[0], ua[0], d);
+      d = mfma_f32(a0[1], ua[1], d);
+      d = mfma_f32(a0[2], ua[2], d);
+      d = mfma_f32(a0[3], ua[3], d);
+      if (two) {
+        const floatx4 a1 = a2[J2 * 128 + 64];
+        d = mfma_f32(a1[0], ub[0], d);
+        d = mfma_f32(a1[1], ub[1], d);
+        d = mfma_f32(a1[2], ub[2], d);
+        d = mfma_f32(a1[3], ub[3], d);
+      }
+      const int64_t i2 = 16 * (int64_t)J2;
+      if (V4) {
+        if (J2 & 1) {
+          store_pair(dprev, d, J2 - 1);
+        } else if (J2 + 1 < nt2) {
+          dprev = d;
+        } else if (rowok && i2 + 4 * g < m2) {
+          *reinterpret_cast<floatx4 *>(orow + i2) = d;
+        }
+      } else if (rowok) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+          if (i2 + 4 * g + w < m2) orow[i2 + w] = d[w];
+      }
+    }
+  }
+}
+
 inline unsigned nblk(int64_t n, int64_t b) { return (unsigned)((n + b - 1) / b); }
 
 Rows rows_of(const Axis &X, int r) {
@@ -474,6 +675,93 @@ hipError_t project_p(Handle &h, const void *q, bool f32) {
   return hipGetLastError();
 }
 
+// Decode to FP32 with axes 1 and 2 on the matrix cores (k_dec_mfma): axis 0
+// first into an FP32 intermediate, then the operand tables, then the tiles.
+// hipErrorNotSupported when a shape does not fit the kernel's windows (the
+// caller then takes the vector kernels): a tile of 16 points of axis 1 must
+// see at most 16 control rows, and one of axis 2 at most two aligned tiles of
+// 16 control columns.  Scratch (h.s1): the intermediate, then the tables.
+template <int P>
+hipError_t decode_mfma(Handle &h, float *out, const int r[3]) {
+  const Axis &X0 = h.ax[0], &X1 = h.ax[1], &X2 = h.ax[2];
+  const int64_t m0 = X0.active ? X0.m : 1, m1 = X1.m, m2 = X2.m;
+  const int n1 = X1.n, n2 = X2.n;
+  if (getenv("MFA_VECTOR_DECODE")) return hipErrorNotSupported;
+  if ((int64_t)n1 * n2 >= (int64_t)1 << 31) return hipErrorNotSupported;
+  // host copy of the span rule: span(i) = min(n-1, p + floor(i (n-p) / (m-1)))
+  auto span = [](int64_t i, int64_t m, int n) {
+    return (int)std::min<int64_t>(n - 1, P + i * (n - P) / (m - 1));
+  };
+  const int nt1 = (int)((m1 + 15) / 16), nt2 = (int)((m2 + 15) / 16);
+  int ext1 = 0;
+  for (int I = 0; I < nt1; ++I)
+    ext1 = std::max(ext1, span(std::min<int64_t>(16 * (int64_t)I + 15, m1 - 1), m1, n1) -
+                              span(16 * (int64_t)I, m1, n1) + P + 1);
+  // one wave holds the U tiles of all of axis 2's control columns in registers
+  if (ext1 > 16 || n2 > 256) return hipErrorNotSupported;
+  for (int J2 = 0; J2 < nt2; ++J2) {
+    const int lo = span(16 * (int64_t)J2, m2, n2) - P;
+    const int hi = span(std::min<int64_t>(16 * (int64_t)J2 + 15, m2 - 1), m2, n2);
+    if (hi / 16 - lo / 16 > 1) return hipErrorNotSupported;
+  }
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t tbytes = X0.active ? up((size_t)m0 * n1 * n2 * sizeof(float)) : 0;
+  const size_t w1b = up((size_t)nt1 * 256 * sizeof(float)), w2b = up((size_t)nt2 * 512 * sizeof(float));
+  const int ntk = (n2 + 15) / 16;
+  const size_t lds = (size_t)nt2 * 128 * 16 + (size_t)(nt2 + ntk + 1) * sizeof(int);
+  if (lds > 64 * 1024) return hipErrorNotSupported;
+  const size_t need = tbytes + w1b + w2b + up((size_t)nt1 * sizeof(int)) + up((size_t)nt2 * sizeof(int)) +
+                      up((size_t)(ntk + 1) * sizeof(int));
+  if ((size_t)h.s1n * sizeof(double) < need) return hipErrorNotSupported;
+  char *base = reinterpret_cast<char *>(h.s1);
+  float *tmid = reinterpret_cast<float *>(base);
+  float *w1t = reinterpret_cast<float *>(base + tbytes);
+  float *w2t = reinterpret_cast<float *>(base + tbytes + w1b);
+  int *klo1 = reinterpret_cast<int *>(base + tbytes + w1b + w2b);
+  int *j0n = reinterpret_cast<int *>(base + tbytes + w1b + w2b + up((size_t)nt1 * sizeof(int)));
+  int *j2beg = reinterpret_cast<int *>(base + tbytes + w1b + w2b + up((size_t)nt1 * sizeof(int)) +
+                                       up((size_t)nt2 * sizeof(int)));
+  hipError_t e;
+  if (X0.active) {
+    const int64_t J = (int64_t)n1 * n2;
+    const int I0C = 64;
+    const dim3 g0(nblk(J, 256), nblk(m0, I0C));
+    const size_t lds0 = (size_t)I0C * ((P + 1) * sizeof(double) + sizeof(int));
+    k_dec_outer<P, float><<<g0, 256, lds0, h.stream>>>(h.P, tmid, J, I0C, rows_of(X0, r[0]));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const Rows r1 = rows_of(X1, r[1]), r2 = rows_of(X2, r[2]);
+  const int64_t ntab = (int64_t)nt1 * 64 + (int64_t)nt2 * 128 + ntk + 1;
+  k_dec_tab<P><<<nblk(ntab, 256), 256, 0, h.stream>>>(r1, r2, nt1, nt2, ntk, w1t, klo1, w2t, j0n, j2beg);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 8 waves per workgroup share the staged N_2 table
+  const int wpb = (int)std::min<int64_t>(8, nt1);
+  const dim3 g1(nblk(nt1, wpb), (unsigned)m0);
+  const bool v4 = m2 % 4 == 0;
+#define MFA_DM(TI, SRC, NTK_)                                                                    \
+  do {                                                                                           \
+    if (v4)                                                                                      \
+      k_dec_mfma<TI, true, NTK_><<<g1, 64 * wpb, lds, h.stream>>>(SRC, out, m1, m2, n1, n2, nt1, \
+                                                                  nt2, w1t, klo1, w2t, j0n, j2beg); \
+    else                                                                                         \
+      k_dec_mfma<TI, false, NTK_><<<g1, 64 * wpb, lds, h.stream>>>(SRC, out, m1, m2, n1, n2, nt1, \
+                                                                   nt2, w1t, klo1, w2t, j0n, j2beg); \
+  } while (0)
+#define MFA_DM_NTK(TI, SRC)                    \
+  if (ntk <= 4) MFA_DM(TI, SRC, 4);            \
+  else if (ntk <= 8) MFA_DM(TI, SRC, 8);       \
+  else if (ntk <= 12) MFA_DM(TI, SRC, 12);     \
+  else MFA_DM(TI, SRC, 16);
+  if (X0.active) {
+    MFA_DM_NTK(float, tmid);
+  } else {
+    MFA_DM_NTK(double, h.P);
+  }
+#undef MFA_DM_NTK
+#undef MFA_DM
+  return hipGetLastError();
+}
+
 template <int P>
 hipError_t decode_p(Handle &h, void *out, bool f32, const int r[3], unsigned long long *rs) {
   const Axis &X0 = h.ax[0], &X1 = h.ax[1], &X2 = h.ax[2];
@@ -483,6 +771,10 @@ hipError_t decode_p(Handle &h, void *out, bool f32, const int r[3], unsigned lon
   const int BS = m2 >= 256 || n2 > 128 ? 256 : (int)std::max<int64_t>(64, ((std::max<int64_t>(m2, n2) + 63) / 64) * 64);
   const int IS = (int)((m2 + BS - 1) / BS);
   if (IS > 4) return hipErrorNotSupported;
+  if (f32 && !rs) {
+    hipError_t e = decode_mfma<P>(h, reinterpret_cast<float *>(out), r);
+    if (e != hipErrorNotSupported) return e;
+  }
   const double *src = h.P;
   if (X0.active) {
     if (h.s1n < m0 * n1 * (int64_t)n2) return hipErrorNotSupported;
@@ -490,7 +782,7 @@ hipError_t decode_p(Handle &h, void *out, bool f32, const int r[3], unsigned lon
     const int I0C = 64;
     const dim3 g0(nblk(J, 256), nblk(m0, I0C));
     const size_t lds0 = (size_t)I0C * ((P + 1) * sizeof(double) + sizeof(int));
-    k_dec_outer<P><<<g0, 256, lds0, h.stream>>>(h.P, h.s1, J, I0C, rows_of(X0, r[0]));
+    k_dec_outer<P, double><<<g0, 256, lds0, h.stream>>>(h.P, h.s1, J, I0C, rows_of(X0, r[0]));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     src = h.s1;
