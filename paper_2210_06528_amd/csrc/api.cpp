@@ -601,10 +601,16 @@ mfa_status encode_variant(Handle &h, mfa_step_stats *out) {
   return MFA_OK;
 }
 
-mfa_status read_stats(Handle &h, mfa_step_stats *out, double jump_tol, bool *finite) {
+// hist_val (optional): h.hist[hist_idx] copied back with the slots, under the
+// same synchronisation.
+mfa_status read_stats(Handle &h, mfa_step_stats *out, double jump_tol, bool *finite,
+                      double *hist_val = nullptr, int hist_idx = 0) {
   std::vector<unsigned long long> raw((size_t)kNumSlots * kSlotCopies);
   HIP_CHECK(hipMemcpyAsync(raw.data(), h.slots, sizeof(unsigned long long) * raw.size(),
                            hipMemcpyDeviceToHost, h.stream), "read stats");
+  if (hist_val)
+    HIP_CHECK(hipMemcpyAsync(hist_val, h.hist + hist_idx, sizeof(double), hipMemcpyDeviceToHost, h.stream),
+              "read correction history");
   HIP_CHECK(hipStreamSynchronize(h.stream), "read stats");
   // non-negative doubles order like their bit patterns (NaN sorts above inf)
   auto val = [&](int s) {
@@ -967,7 +973,10 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
     if (s != MFA_OK) return s;
     if (!check) continue;
     bool finite = true;
-    s = read_stats(h, &st, jump_tol, &finite);
+    // the predicted schedule also needs max |correction| of sweep k - 2
+    const bool want_hist = jump_tol > 0.0 && check_every <= 0 && k >= 3;
+    double d2 = 0.0;
+    s = read_stats(h, &st, jump_tol, &finite, want_hist ? &d2 : nullptr, (k - 3 + kHist) % kHist);
     if (s != MFA_OK) return s;
     if (!finite) {
       if (last) *last = st;
@@ -984,11 +993,6 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
       for (int r = 0; r < h.p; ++r) jm = std::max(jm, st.jump[r]);
       int stride = 4;
       if (k >= 3) {
-        double d2 = 0.0;
-        HIP_CHECK(hipMemcpyAsync(&d2, h.hist + (k - 3) % kHist, sizeof(double), hipMemcpyDeviceToHost,
-                                 h.stream),
-                  "read correction history");
-        HIP_CHECK(hipStreamSynchronize(h.stream), "read correction history");
         const double d0 = st.max_dP;
         if (d2 > 0.0 && d0 > 0.0 && d0 < d2 && jm > 0.0) {
           const double rate = std::sqrt(d0 / d2);

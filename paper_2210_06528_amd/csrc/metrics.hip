@@ -9,6 +9,7 @@
 //                  axes (Omega_b, Omega_c) and reduce max |.| per order.
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "mfa_internal.hpp"
@@ -54,12 +55,16 @@ struct OmTab {
 // V_i[kc] = sum_kb Om_b[ib_i][kb] U[row, kb, kc] into LDS, then every data
 // point ic of axis c evaluates sum_kc Om_c[ic][kc] V_i[kc] for all i of the
 // group (one read of the Om_c row serves jb outputs); max |.| goes to slot
-// (a, row % p).  Om rows are contiguous column ranges.
+// (a, row % p).  Om rows are contiguous column ranges (the free set of the
+// point's owner), so the group's rows are laid out densely over the union
+// of their ranges (at most wmax columns, from the host): a thread per kc
+// then reads each U value of that range once and feeds all jb sums, the row
+// coefficients being the same for the whole wavefront (LDS broadcasts).
 template <int JB>
 __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ U, int R,
                                                      int64_t sr, int64_t sb, int64_t sc, OmTab Ob,
                                                      OmTab Oc, int has_c, int p, int slot_base,
-                                                     unsigned long long *slots) {
+                                                     unsigned long long *slots, int wmax) {
   constexpr int jb = JB;
   extern __shared__ double V[];   // [jb][nc]
   // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that
@@ -72,35 +77,45 @@ __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ 
   const int ib0 = (lb % nbg) * jb;
   const int nib = min(jb, Ob.m - ib0);
   const int nc = has_c ? Oc.n : 1;
-  // the group's Om_b rows (jb x Ob.L) and their column starts and lengths
-  double *VB = V + jb * nc;
-  int *CB = reinterpret_cast<int *>(VB + jb * Ob.L);
-  for (int e = threadIdx.x; e < jb * Ob.L; e += blockDim.x) {
-    const int i = e / Ob.L;
-    VB[e] = i < nib ? Ob.val[(int64_t)(ib0 + i) * Ob.L + (e - i * Ob.L)] : 0.0;
-  }
+  // the group's Om_b rows, dense over the union [kb0, kb0 + W) of their ranges
+  double *VB = V + jb * nc;                                   // [jb][wmax]
+  int *CB = reinterpret_cast<int *>(VB + jb * wmax);          // [jb][2]: start, length
   for (int i = threadIdx.x; i < jb; i += blockDim.x) {
     CB[2 * i] = i < nib ? Ob.col[(int64_t)(ib0 + i) * Ob.L] : 0;
     CB[2 * i + 1] = i < nib ? Ob.len[ib0 + i] : 0;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < jb * nc; e += blockDim.x) {
-    const int i = e / nc, kc = e - i * nc;
-    double s = 0.0;
-    if (i < nib) {
-      const int cb0 = CB[2 * i], lb = CB[2 * i + 1];
-      const double *vb = VB + i * Ob.L;
-      const double *u = U + row * sr + (int64_t)cb0 * sb + (int64_t)kc * sc;
-      // eight strided loads in flight per step
-      for (int t0 = 0; t0 < lb; t0 += 8) {
-        double x[8];
+  int kb0 = CB[0], kb1 = CB[0] + CB[1];
+  for (int i = 1; i < nib; ++i) {
+    kb0 = min(kb0, CB[2 * i]);
+    kb1 = max(kb1, CB[2 * i] + CB[2 * i + 1]);
+  }
+  const int W = min(kb1 - kb0, wmax);   // the host sizes wmax to the widest union
+  for (int e = threadIdx.x; e < jb * wmax; e += blockDim.x) {
+    const int i = e / wmax, t = e - i * wmax;
+    const int q = kb0 + t - CB[2 * i];
+    VB[e] = (i < nib && t < W && q >= 0 && q < CB[2 * i + 1]) ? Ob.val[(int64_t)(ib0 + i) * Ob.L + q] : 0.0;
+  }
+  __syncthreads();
+  for (int kc = threadIdx.x; kc < nc; kc += blockDim.x) {
+    double acc[JB];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = t0 + q < lb ? u[(int64_t)(t0 + q) * sb] : 0.0;
+    for (int i = 0; i < JB; ++i) acc[i] = 0.0;
+    const double *u = U + row * sr + (int64_t)kb0 * sb + (int64_t)kc * sc;
+    // eight strided loads in flight per step
+    for (int t0 = 0; t0 < W; t0 += 8) {
+      double x[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s += vb[min(t0 + q, Ob.L - 1)] * x[q];
+      for (int q = 0; q < 8; ++q) x[q] = t0 + q < W ? u[(int64_t)(t0 + q) * sb] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int t = min(t0 + q, wmax - 1);
+#pragma unroll
+        for (int i = 0; i < JB; ++i) acc[i] += VB[i * wmax + t] * x[q];
       }
     }
-    V[e] = s;
+#pragma unroll
+    for (int i = 0; i < JB; ++i) V[i * nc + kc] = acc[i];
   }
   __syncthreads();
   double mx = 0.0;
@@ -631,11 +646,23 @@ hipError_t launch_jump_expand(Handle &h, int a, const double *U) {
   // 192 grid: more workgroups, all resident at once), fewer for long rows
   const int jb = nc <= 768 ? 8 : (nc <= 1536 ? 4 : 1);
   const unsigned grid = (unsigned)((int64_t)R * ((Ob.m + jb - 1) / jb));
-  const size_t lds = sizeof(double) * jb * (nc + Ob.L) + sizeof(int) * 2 * jb;
+  // widest union of the Om_b column ranges (owners' free sets) over a group
+  // of jb consecutive data points
+  int wmax = 1;
+  for (int64_t i0 = 0; i0 < Xb.m; i0 += jb) {
+    int lo = 1 << 30, hi = 0;
+    for (int64_t i = i0; i < std::min<int64_t>(Xb.m, i0 + jb); ++i) {
+      const Block &B = Xb.blk[Xb.pown[i]];
+      lo = std::min(lo, B.F0);
+      hi = std::max(hi, B.F1);
+    }
+    wmax = std::max(wmax, hi - lo);
+  }
+  const size_t lds = sizeof(double) * jb * (nc + wmax) + sizeof(int) * 2 * jb;
   if (lds > 64 * 1024) return hipErrorInvalidValue;
 #define MFA_JE(JB)                                                                                  \
   k_jump_expand<JB><<<grid, 256, lds, h.stream>>>(U, R, st[a], st[oth[0]], sc, Ob, Oc, has_c, h.p, \
-                                                 kSlotJ + a * kMaxP, h.slots)
+                                                 kSlotJ + a * kMaxP, h.slots, wmax)
   if (jb == 8) MFA_JE(8);
   else if (jb == 4) MFA_JE(4);
   else MFA_JE(1);
