@@ -66,8 +66,9 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
   constexpr int W = 2 * P + 1;
   constexpr int LY = kTY + 2 * P;
   constexpr int LZ = kTZ + 2 * P;
-  __shared__ double tile[LY][LZ + 1];
-  __shared__ double tz[LY][kTZ + 1];
+  // double-buffered by plane parity (one barrier per plane, see below)
+  __shared__ double tile[2][LY][LZ + 1];
+  __shared__ double tz[2][LY][kTZ + 1];
   const int tx = threadIdx.x & 63;
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wavefront index 0..7
   // Workgroups are dealt to the 8 XCDs round-robin in launch order.  Renumber
@@ -145,6 +146,11 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
   // where the values are used, so no load is followed by an early wait; the
   // plane count is rounded up to even so that no branch separates a load from
   // its wait (the extra plane writes nothing).
+  // One barrier per plane: the step of plane xi stores its tile into the
+  // buffer of its parity, waits once, then runs the z pass of plane xi
+  // (tile -> tz of that parity) and the y and x passes of plane xi - 1 (from
+  // the other tz buffer, written before the barrier).  A buffer is rewritten
+  // two steps after it was read, with a barrier in between.
   double preA[NE], preB[NE];
   bool inA = false, inB = false;   // the plane held in the buffer lies inside the array
   auto gload = [&](double (&buf)[NE], bool &bin, int xi) {
@@ -153,51 +159,15 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
 #pragma unroll
     for (int i = 0; i < NE; ++i) buf[i] = base[toff[i]];
   };
-  auto step = [&](double (&buf)[NE], bool &bin, int xi) {
-    const int xo = xi - P;
-    const bool out_plane = xo >= x0 && xo < x1;
-    // axis-0 stencil row of the output plane (scalar loads, covered by the
-    // barrier's wait)
-    double axv[W];
-    {
-      const double *ax = A0 + (int64_t)(out_plane ? xo : 0) * W;
-#pragma unroll
-      for (int t = 0; t < W; ++t) axv[t] = ax[t];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NE; ++i) {
-      const int e = threadIdx.x + kRT * i;
-      if (e < LY * LZ) {
-        const int yy = e / LZ, zz = e - yy * LZ;
-        tile[yy][zz] = (bin && ((tmask >> i) & 1)) ? buf[i] : 0.0;
-      }
-    }
-    // the right-hand side of the plane completed in this step, requested
-    // after the wait for the tile (loads return in order) and before the
-    // tile two planes ahead, so that neither wait covers the other
-    double cv[kRY];
-    {
-      const double *cb = c + (out_plane ? xo : 0) * plane;
-#pragma unroll
-      for (int r = 0; r < kRY; ++r) cv[r] = cb[coff[r]];
-    }
-    __syncthreads();
-    // past the chunk's last plane the prefetch re-reads that plane (cache
-    // hits, never used) instead of the next chunk's planes
-    gload(buf, bin, min(xi + 2, x1 + P - 1));
-    for (int yy = ty; yy < LY; yy += kRT / 64) {
-      double s = 0.0;
-#pragma unroll
-      for (int t = 0; t < W; ++t) s += az[t] * tile[yy][tx + t];
-      tz[yy][tx] = s;
-    }
-    __syncthreads();
+  const int xs = x0 - P, npl = (x1 + P - xs + 1) & ~1;
+  // y pass of plane xo + P from tz[q] (ring of the last W planes' results),
+  // then, for an owned plane xo, its x pass and the residual
+  auto yx = [&](int q, int xo, const double (&axv)[W], const double (&cv)[kRY]) {
     {
       // the kRY rows of a thread share W - 1 of their W taps: one read each
       double tcol[W + kRY - 1];
 #pragma unroll
-      for (int t = 0; t < W + kRY - 1; ++t) tcol[t] = tz[ty * kRY + t][tx];
+      for (int t = 0; t < W + kRY - 1; ++t) tcol[t] = tz[q][ty * kRY + t][tx];
 #pragma unroll
       for (int r = 0; r < kRY; ++r) {
         const int yl = ty * kRY + r;
@@ -210,7 +180,7 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
         ring[W - 1][r] = s;
       }
     }
-    if (out_plane) {
+    if (xo >= x0 && xo < x1) {
 #pragma unroll
       for (int r = 0; r < kRY; ++r) {
         if ((cmask >> r) & 1) {
@@ -225,14 +195,56 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
       }
     }
   };
-  const int xs = x0 - P, npl = (x1 + P - xs + 1) & ~1;
+  // axis-0 stencil row (scalar loads) and right-hand side of output plane xo
+  auto rhs = [&](int xo, double (&axv)[W], double (&cv)[kRY]) {
+    const bool own = xo >= x0 && xo < x1;
+    const double *ax = A0 + (int64_t)(own ? xo : 0) * W;
+#pragma unroll
+    for (int t = 0; t < W; ++t) axv[t] = ax[t];
+    const double *cb = c + (own ? xo : 0) * plane;
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) cv[r] = cb[coff[r]];
+  };
+  auto step = [&](double (&buf)[NE], bool &bin, int xi, int q) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = threadIdx.x + kRT * i;
+      if (e < LY * LZ) {
+        const int yy = e / LZ, zz = e - yy * LZ;
+        tile[q][yy][zz] = (bin && ((tmask >> i) & 1)) ? buf[i] : 0.0;
+      }
+    }
+    // the right-hand side of the plane output in this step, requested after
+    // the wait for the tile (loads return in order) and before the tile two
+    // planes ahead, so that neither wait covers the other
+    double axv[W], cv[kRY];
+    rhs(xi - 1 - P, axv, cv);
+    __syncthreads();
+    // past the chunk's last plane the prefetch re-reads that plane (cache
+    // hits, never used) instead of the next chunk's planes
+    gload(buf, bin, min(xi + 2, x1 + P - 1));
+    for (int yy = ty; yy < LY; yy += kRT / 64) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < W; ++t) s += az[t] * tile[q][yy][tx + t];
+      tz[q][yy][tx] = s;
+    }
+    if (xi > xs) yx(q ^ 1, xi - 1 - P, axv, cv);
+  };
   gload(preA, inA, xs);
   // keep A's loads ahead of B's: the waits count loads in issue order
   asm volatile("" ::: "memory");
   gload(preB, inB, xs + 1);
   for (int xi = xs; xi < xs + npl; xi += 2) {
-    step(preA, inA, xi);
-    step(preB, inB, xi + 1);
+    step(preA, inA, xi, 0);
+    step(preB, inB, xi + 1, 1);
+  }
+  {
+    // the last plane's y and x passes (its z pass went to tz[1]: npl is even)
+    double axv[W], cv[kRY];
+    rhs(xs + npl - 1 - P, axv, cv);
+    __syncthreads();
+    yx(1, xs + npl - 1 - P, axv, cv);
   }
   slot_max_c(slots, kSlotNres, nres);
 }
