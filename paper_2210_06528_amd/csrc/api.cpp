@@ -722,38 +722,16 @@ mfa_status create_handle(const mfa_problem *prob, void *workspace, size_t bytes,
     return bail(e, "zero flag");
   if ((e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0)) != hipSuccess) return bail(e, "fill P");
   if ((e = upload_plan(&h)) != hipSuccess) return bail(e, "upload plan");
-  // The per-axis setup chains (basis, Gram, batched Cholesky, inverses,
-  // operator tables) are independent and each kernel runs only a few
-  // workgroups: the first active axis runs on the caller's stream, the others
-  // on two auxiliary streams forked from it and joined back (all on the
-  // caller's stream when serial).
-  AuxStreams *aux = nullptr;
-  if (!serial) {
-    aux = aux_streams(h.device);
-    if (!aux) return bail(hipErrorOutOfMemory, "auxiliary streams");
-    if ((e = hipEventRecord(aux->fork, h.stream)) != hipSuccess) return bail(e, "fork");
-  }
-  int used = 0;
-  for (int a = 0; a < 3; ++a) {
-    if (!h.ax[a].active) continue;
-    hipStream_t st = h.stream;
-    const bool fork = aux && used > 0;
-    if (fork) {
-      st = aux->s[used - 1];
-      if ((e = hipStreamWaitEvent(st, aux->fork, 0)) != hipSuccess) return bail(e, "fork");
-    }
-    if (h.variant != MFA_VARIANT_CLAMPED && (e = setup_axis(&h, a, st)) != hipSuccess)
-      return bail(e, "setup");
-    if (h.precision == MFA_PREC_MIXED_BF16 && (e = setup_mfma(&h, a, st)) != hipSuccess)
-      return bail(e, "setup");
-    if (h.variant != MFA_VARIANT_SCHWARZ && (e = setup_variant_axis(&h, a, st)) != hipSuccess)
-      return bail(e, "setup");
-    if (fork) {
-      if ((e = hipEventRecord(aux->join[used - 1], st)) != hipSuccess) return bail(e, "join");
-      if ((e = hipStreamWaitEvent(h.stream, aux->join[used - 1], 0)) != hipSuccess) return bail(e, "join");
-    }
-    ++used;
-  }
+  // Setup (basis, Gram, batched Cholesky, inverses, operator tables) runs
+  // stage by stage, each stage of every active axis in one launch on the
+  // caller's stream; the variants' tables follow per axis.
+  if (h.variant != MFA_VARIANT_CLAMPED && (e = setup_axes(&h, h.stream)) != hipSuccess)
+    return bail(e, "setup");
+  if (h.precision == MFA_PREC_MIXED_BF16 && (e = setup_mfma_axes(&h, h.stream)) != hipSuccess)
+    return bail(e, "setup");
+  if (h.variant != MFA_VARIANT_SCHWARZ)
+    for (int a = 0; a < 3; ++a)
+      if (h.ax[a].active && (e = setup_variant_axis(&h, a, h.stream)) != hipSuccess) return bail(e, "setup");
   int flag = 0;
   if ((e = hipMemcpyAsync(&flag, h.flag, sizeof(int), hipMemcpyDeviceToHost, h.stream)) != hipSuccess)
     return bail(e, "read flag");

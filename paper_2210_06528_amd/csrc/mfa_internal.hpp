@@ -227,7 +227,7 @@ hipError_t upload_plan(Handle *h);
 // decode at arbitrary parameter points (npts x dim, float64, device)
 hipError_t launch_decode_points(Handle &h, const double *u, int64_t npts, void *out, bool f32,
                                 const int r[3]);
-hipError_t setup_axis(Handle *h, int a, hipStream_t st);
+hipError_t setup_axes(Handle *h, hipStream_t st);   // every active axis, one launch per stage
 // operator tables of the DECOUPLED / CLAMPED variants (after setup_axis for
 // DECOUPLED; alone for CLAMPED)
 hipError_t setup_variant_axis(Handle *h, int a, hipStream_t st);
@@ -260,7 +260,7 @@ hipError_t launch_project_grid(Handle &h, const void *q, bool f32);
 hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3],
                               unsigned long long *rs = nullptr);
 bool mfma_fits(int npad);
-hipError_t setup_mfma(Handle *h, int a, hipStream_t st);
+hipError_t setup_mfma_axes(Handle *h, hipStream_t st);
 // axes 2 and 1 of the split-BF16 correction in one pass (3-D problems)
 int fuse21_ldw(const Handle &h);
 bool mfma_fused21_ok(const Handle &h);

@@ -618,13 +618,25 @@ __device__ __forceinline__ void tab_ktiles(int n, Ell M, int *klo, int *knc) {
   knc[t] = (hi - lo + 31) / 32;
 }
 
-// both tables in one launch (blockIdx.y: the BF16 rows, the tile K ranges)
-__global__ void k_tab_mfma(int n, int nrows, int npad, Ell M, __hip_bfloat16 *Mhi, __hip_bfloat16 *Mlo,
-                           int *klo, int *knc) {
+// both tables of every active axis in one launch (blockIdx.y: the BF16 rows,
+// the tile K ranges; blockIdx.z: the axis)
+struct MbArgs {
+  int n, nrows, npad;
+  Ell M;
+  __hip_bfloat16 *Mhi, *Mlo;
+  int *klo, *knc;
+};
+
+struct MbArgs3 {
+  MbArgs a[3];
+};
+
+__global__ void k_tab_mfma3(MbArgs3 t) {
+  const MbArgs &a = t.a[blockIdx.z];
   if (blockIdx.y == 0)
-    tab_Mbf16(n, nrows, npad, M, Mhi, Mlo);
+    tab_Mbf16(a.n, a.nrows, a.npad, a.M, a.Mhi, a.Mlo);
   else
-    tab_ktiles(n, M, klo, knc);
+    tab_ktiles(a.n, a.M, a.klo, a.knc);
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -643,13 +655,21 @@ static int contig_lines(int npad) {
 
 bool mfma_fits(int npad) { return mfma_lds(npad) <= 64 * 1024 && contig_lines(npad) > 0; }
 
-hipError_t setup_mfma(Handle *h, int ia, hipStream_t st) {
-  Axis &X = h->ax[ia];
-  const int nrows = (X.n + 15) / 16 * 16;
-  __hip_bfloat16 *Mhi = reinterpret_cast<__hip_bfloat16 *>(X.d_Mb);
-  __hip_bfloat16 *Mlo = Mhi + (int64_t)nrows * X.npad;
-  k_tab_mfma<<<dim3(std::max<unsigned>(nrows, nblk((X.n + 15) / 16, 128)), 2), 128, 0, st>>>(
-      X.n, nrows, X.npad, X.M, Mhi, Mlo, X.d_klo, X.d_knc);
+hipError_t setup_mfma_axes(Handle *h, hipStream_t st) {
+  MbArgs3 t{};
+  int na = 0;
+  unsigned gx = 1;
+  for (int a = 0; a < 3; ++a) {
+    Axis &X = h->ax[a];
+    if (!X.active) continue;
+    const int nrows = (X.n + 15) / 16 * 16;
+    __hip_bfloat16 *Mhi = reinterpret_cast<__hip_bfloat16 *>(X.d_Mb);
+    __hip_bfloat16 *Mlo = Mhi + (int64_t)nrows * X.npad;
+    t.a[na++] = MbArgs{X.n, nrows, X.npad, X.M, Mhi, Mlo, X.d_klo, X.d_knc};
+    gx = std::max(gx, std::max<unsigned>(nrows, nblk((X.n + 15) / 16, 128)));
+  }
+  if (na == 0) return hipSuccess;
+  k_tab_mfma3<<<dim3(gx, 2, na), 128, 0, st>>>(t);
   return hipGetLastError();
 }
 

@@ -31,9 +31,9 @@ __device__ __forceinline__ int64_t d_last_with_span_le(int s, int64_t m, int n, 
 // slice blockIdx.y = p + 1 evaluates the derivatives of orders 0..p-1 at the
 // interface parameters u*_b (nif * p threads).
 
-__global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs, int nif,
-                        const double *ustar, const int *span_if, double *dbas_if, double dscale,
-                        const double *wts) {
+__device__ __forceinline__ void basis_rows(int64_t m, int n, int p, int *span_out, const EllSet &tabs,
+                                           int nif, const double *ustar, const int *span_if,
+                                           double *dbas_if, double dscale, const double *wts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((int)blockIdx.y == p + 1) {
     if (i < (int64_t)nif * p) {
@@ -67,8 +67,8 @@ __global__ void k_basis(int64_t m, int n, int p, int *span_out, EllSet tabs, int
 // band[t*n + k] = A[k+t][k].  One wavefront per row k: the lanes stride over
 // the data points in the support of N_k and the p+1 partial sums are reduced
 // across the wavefront with shuffles (fixed order, deterministic).
-__global__ void __launch_bounds__(64) k_gram(int64_t m, int n, int p, const int *span,
-                                             Ell basis, double *band) {
+__device__ __forceinline__ void gram_row(int64_t m, int n, int p, const int *span, const Ell &basis,
+                                         double *band) {
   const int k = blockIdx.x;
   const int lane = threadIdx.x;
   const int smin = max(k, p), smax = min(k + p, n - 1);
@@ -253,9 +253,8 @@ __global__ void k_inverse_global(int p, const int *blk, const double *chol, doub
 // single product of the step before; the diagonal is applied as a
 // reciprocal.  A non-positive pivot sets flag[0].
 template <int PP>
-__global__ void __launch_bounds__(256) k_chol_inv(int n, const double *band, const int *blk,
-                                                  double *chol, double *rdiag, double *inv,
-                                                  int *flag) {
+__device__ __forceinline__ void chol_inv_block(int n, const double *band, const int *blk, double *chol,
+                                               double *rdiag, double *inv, int *flag) {
   extern __shared__ double sm[];
   const int b = blockIdx.x;
   int64_t off = 0, roff = 0, offi = 0;
@@ -695,8 +694,9 @@ __device__ __forceinline__ void tab_acoef(int n, int p, const double *band, doub
 // The row tables that need only the basis rows and the normal-matrix band,
 // in one launch (a thread per row, blockIdx.y the table): N^T, A, the
 // derivative operators D and the residual stencil rows.
-__global__ void k_tab_rows(int64_t m, int n, int p, const int *span, Ell basis, Ell NT,
-                           const double *band, Ell A, Ell D, int *gidD, double *acoef) {
+__device__ __forceinline__ void tab_rows(int64_t m, int n, int p, const int *span, const Ell &basis,
+                                         const Ell &NT, const double *band, const Ell &A, const Ell &D,
+                                         int *gidD, double *acoef) {
   switch (blockIdx.y) {
     case 0: tab_NT(m, n, p, span, basis, NT); break;
     case 1: tab_A(n, p, band, A); break;
@@ -709,12 +709,12 @@ __global__ void k_tab_rows(int64_t m, int n, int p, const int *span, Ell basis, 
 // per row, blockIdx.y the table): M (n rows), Om (m data points, with its
 // values also written transposed) and the interface functionals J (nif * p
 // rows, none with one block).
-__global__ void __launch_bounds__(64) k_tab_ops(int64_t m, int n, int p, int combine, int nif,
-                                                const int *blk, const int *blo, const int *bhi,
-                                                const int *owner, const int *ns, const int *pown,
-                                                const int *span, Ell basis, const double *inv,
-                                                const int *span_if, const double *dbas_if, Ell M,
-                                                Ell Om, double *omT, Ell J, int *gidJ) {
+__device__ __forceinline__ void tab_ops(int64_t m, int n, int p, int combine, int nif, const int *blk,
+                                        const int *blo, const int *bhi, const int *owner, const int *ns,
+                                        const int *pown, const int *span, const Ell &basis,
+                                        const double *inv, const int *span_if, const double *dbas_if,
+                                        const Ell &M, const Ell &Om, double *omT, const Ell &J,
+                                        int *gidJ) {
   switch (blockIdx.y) {
     case 0:
       if (blockIdx.x < (unsigned)n) tab_M(n, combine, blk, blo, bhi, owner, ns, inv, M);
@@ -726,6 +726,92 @@ __global__ void __launch_bounds__(64) k_tab_ops(int64_t m, int n, int p, int com
       if (blockIdx.x < (unsigned)(nif * p)) tab_J(nif, p, blk, span_if, dbas_if, inv, J, gidJ);
       break;
   }
+}
+
+// Setup stages of every active axis in one launch each: blockIdx.z selects
+// the axis, whose arguments travel in a small array (the grid covers the
+// largest axis; every stage checks its own bounds).  One launch per stage
+// instead of one per stage and axis: setup is bound by the host's launch
+// rate, not by these kernels.
+template <typename A>
+struct Tri {
+  A a[3];
+};
+
+struct BasisArgs {
+  int64_t m;
+  int n, p, nif;
+  int *span;
+  EllSet tabs;
+  const double *ustar;
+  const int *span_if;
+  double *dbas_if;
+  double dscale;
+  const double *w;
+};
+
+struct GramArgs {
+  int64_t m;
+  int n, p;
+  const int *span;
+  Ell basis;
+  double *band;
+};
+
+struct RowsArgs {
+  int64_t m;
+  int n, p;
+  const int *span;
+  Ell basis, NT, A, D;
+  const double *band;
+  int *gidD;
+  double *acoef;
+};
+
+struct CholArgs {
+  int n, B;
+  const double *band;
+  const int *blk;
+  double *chol, *rdiag, *inv;
+};
+
+struct OpsArgs {
+  int64_t m;
+  int n, p, nif;
+  const int *blk, *blo, *bhi, *owner, *ns, *pown, *span, *span_if;
+  Ell basis, M, Om, J;
+  const double *inv, *dbas_if;
+  double *omT;
+  int *gidJ;
+};
+
+__global__ void k_basis3(Tri<BasisArgs> t) {
+  const BasisArgs &a = t.a[blockIdx.z];
+  basis_rows(a.m, a.n, a.p, a.span, a.tabs, a.nif, a.ustar, a.span_if, a.dbas_if, a.dscale, a.w);
+}
+
+__global__ void __launch_bounds__(64) k_gram3(Tri<GramArgs> t) {
+  const GramArgs &a = t.a[blockIdx.z];
+  if (blockIdx.x >= (unsigned)a.n) return;
+  gram_row(a.m, a.n, a.p, a.span, a.basis, a.band);
+}
+
+__global__ void k_tab_rows3(Tri<RowsArgs> t) {
+  const RowsArgs &a = t.a[blockIdx.z];
+  tab_rows(a.m, a.n, a.p, a.span, a.basis, a.NT, a.band, a.A, a.D, a.gidD, a.acoef);
+}
+
+template <int PP>
+__global__ void __launch_bounds__(256) k_chol_inv3(Tri<CholArgs> t, int *flag) {
+  const CholArgs &a = t.a[blockIdx.z];
+  if (blockIdx.x >= (unsigned)a.B) return;   // whole workgroups, before any barrier
+  chol_inv_block<PP>(a.n, a.band, a.blk, a.chol, a.rdiag, a.inv, flag);
+}
+
+__global__ void __launch_bounds__(64) k_tab_ops3(Tri<OpsArgs> t, int combine) {
+  const OpsArgs &a = t.a[blockIdx.z];
+  tab_ops(a.m, a.n, a.p, combine, a.nif, a.blk, a.blo, a.bhi, a.owner, a.ns, a.pown, a.span, a.basis,
+          a.inv, a.span_if, a.dbas_if, a.M, a.Om, a.omT, a.J, a.gidJ);
 }
 
 // Decode at arbitrary points: one thread per point, the p+1 basis values
@@ -842,59 +928,105 @@ hipError_t upload_plan(Handle *h) {
   return hipStreamSynchronize(h->stream);
 }
 
-hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
-  Axis &X = h->ax[ia];
-  const int p = h->p, n = X.n, B = X.B, nif = B - 1;
-  const int64_t m = X.m;
-
-  // basis values and derivative tables at the data points, all orders in one
-  // launch
-  {
-    EllSet tabs;
-    for (int r = 0; r <= p; ++r) tabs.t[r] = X.N[r];
-    const unsigned gx = nblk(std::max<int64_t>(m, (int64_t)nif * p), 256);
-    k_basis<<<dim3(gx, nif > 0 ? p + 2 : p + 1), 256, 0, st>>>(m, n, p, X.d_span, tabs, nif, X.d_ustar,
-                                                                 X.d_span_if, X.d_dbas_if,
-                                                                 X.dscale, X.d_w);
-    MFA_TRY(hipGetLastError());
+hipError_t setup_axes(Handle *h, hipStream_t st) {
+  const int p = h->p;
+  int act[3], na = 0;
+  for (int a = 0; a < 3; ++a)
+    if (h->ax[a].active) act[na++] = a;
+  if (na == 0) return hipSuccess;
+  Tri<BasisArgs> tb{};
+  Tri<GramArgs> tg{};
+  Tri<RowsArgs> tr{};
+  Tri<OpsArgs> to{};
+  unsigned gb = 1, gg = 1, gr = 1, go = 1;
+  bool any_if = false;
+  for (int k = 0; k < na; ++k) {
+    Axis &X = h->ax[act[k]];
+    const int n = X.n, nif = X.B - 1;
+    const int64_t m = X.m;
+    X.d_bas = X.N[0].val;
+    BasisArgs &b = tb.a[k];
+    b.m = m;
+    b.n = n;
+    b.p = p;
+    b.nif = nif;
+    b.span = X.d_span;
+    for (int r = 0; r <= p; ++r) b.tabs.t[r] = X.N[r];
+    b.ustar = X.d_ustar;
+    b.span_if = X.d_span_if;
+    b.dbas_if = X.d_dbas_if;
+    b.dscale = X.dscale;
+    b.w = X.d_w;
+    gb = std::max(gb, nblk(std::max<int64_t>(m, (int64_t)nif * p), 256));
+    tg.a[k] = GramArgs{m, n, p, X.d_span, X.N[0], X.d_gram};
+    gg = std::max<unsigned>(gg, (unsigned)n);
+    RowsArgs &rw = tr.a[k];
+    rw.m = m;
+    rw.n = n;
+    rw.p = p;
+    rw.span = X.d_span;
+    rw.basis = X.N[0];
+    rw.NT = X.NT;
+    rw.A = X.A;
+    rw.D = X.D;
+    rw.band = X.d_gram;
+    rw.gidD = X.d_gidD;
+    rw.acoef = X.d_acoef;
+    gr = std::max(gr, nblk(std::max<int64_t>(n, X.ND), 128));
+    OpsArgs &o = to.a[k];
+    o.m = m;
+    o.n = n;
+    o.p = p;
+    o.nif = nif;
+    o.blk = X.d_blk;
+    o.blo = X.d_blo;
+    o.bhi = X.d_bhi;
+    o.owner = X.d_owner;
+    o.ns = X.d_ns;
+    o.pown = X.d_pown;
+    o.span = X.d_span;
+    o.span_if = X.d_span_if;
+    o.basis = X.N[0];
+    o.M = X.M;
+    o.Om = X.Om;
+    o.J = X.J;
+    o.inv = X.d_inv;
+    o.dbas_if = X.d_dbas_if;
+    o.omT = X.d_omT;
+    o.gidJ = X.d_gidJ;
+    go = std::max<unsigned>(go, (unsigned)std::max<int64_t>(std::max<int64_t>(n, m), (int64_t)nif * p));
+    any_if = any_if || nif > 0;
   }
-  X.d_bas = X.N[0].val;
-  k_gram<<<n, 64, 0, st>>>(m, n, p, X.d_span, X.N[0], X.d_gram);
+  // basis values and derivative tables at the data points, all orders
+  k_basis3<<<dim3(gb, any_if ? p + 2 : p + 1, na), 256, 0, st>>>(tb);
+  MFA_TRY(hipGetLastError());
+  k_gram3<<<dim3(gg, 1, na), 64, 0, st>>>(tg);
   MFA_TRY(hipGetLastError());
   // N^T, A, D and the stencil rows (they need the basis rows and the band)
-  k_tab_rows<<<dim3(nblk(std::max<int64_t>(n, X.ND), 128), 4), 128, 0, st>>>(
-      m, n, p, X.d_span, X.N[0], X.NT, X.d_gram, X.A, X.D, X.d_gidD, X.d_acoef);
+  k_tab_rows3<<<dim3(gr, 4, na), 128, 0, st>>>(tr);
   MFA_TRY(hipGetLastError());
-  // factor and local inverses: one fused launch when both fit in LDS, else
-  // the factor (LDS or global) and the inverses from global memory
-  const size_t chol_lds = sizeof(double) * (p + 1) * X.Fmax;
-  const size_t inv_lds = sizeof(double) * ((size_t)(p + 2) * X.Fmax + (size_t)X.Fmax * X.Fmax);
-  if (inv_lds <= 64 * 1024 && p >= 1 && p <= 8) {
-    switch (p) {
-#define MFA_CHOLINV_CASE(PP)                                                                 \
-  case PP:                                                                                   \
-    k_chol_inv<PP><<<B, 256, inv_lds, st>>>(n, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, X.d_inv, \
-                                            h->flag);                                        \
-    break;
-      MFA_CHOLINV_CASE(1)
-      MFA_CHOLINV_CASE(2)
-      MFA_CHOLINV_CASE(3)
-      MFA_CHOLINV_CASE(4)
-      MFA_CHOLINV_CASE(5)
-      MFA_CHOLINV_CASE(6)
-      MFA_CHOLINV_CASE(7)
-      MFA_CHOLINV_CASE(8)
-#undef MFA_CHOLINV_CASE
-      default:
-        break;
+  // factor and local inverses: one launch for the axes whose blocks fit in
+  // LDS together with their inverses; the others take the factor (LDS or
+  // global) and the inverses from global memory
+  Tri<CholArgs> tc{};
+  int nc = 0;
+  unsigned gc = 1;
+  size_t clds = 0;
+  for (int k = 0; k < na; ++k) {
+    Axis &X = h->ax[act[k]];
+    const size_t chol_lds = sizeof(double) * (p + 1) * X.Fmax;
+    const size_t inv_lds = sizeof(double) * ((size_t)(p + 2) * X.Fmax + (size_t)X.Fmax * X.Fmax);
+    if (inv_lds <= 64 * 1024 && p >= 1 && p <= 8) {
+      tc.a[nc++] = CholArgs{X.n, X.B, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, X.d_inv};
+      gc = std::max<unsigned>(gc, (unsigned)X.B);
+      clds = std::max(clds, inv_lds);
+      continue;
     }
-    MFA_TRY(hipGetLastError());
-  } else {
     if (chol_lds <= 64 * 1024 && p >= 1 && p <= 8) {
       switch (p) {
-#define MFA_CHOL_CASE(PP)                                                                        \
-  case PP:                                                                                       \
-    k_chol<PP><<<B, 64, chol_lds, st>>>(n, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag); \
+#define MFA_CHOL_CASE(PP)                                                                            \
+  case PP:                                                                                           \
+    k_chol<PP><<<X.B, 64, chol_lds, st>>>(X.n, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag); \
     break;
         MFA_CHOL_CASE(1)
         MFA_CHOL_CASE(2)
@@ -909,31 +1041,51 @@ hipError_t setup_axis(Handle *h, int ia, hipStream_t st) {
           break;
       }
     } else {
-      k_chol_global<<<B, 64, 0, st>>>(n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
+      k_chol_global<<<X.B, 64, 0, st>>>(X.n, p, X.d_gram, X.d_blk, X.d_chol, X.d_rdiag, h->flag);
     }
     MFA_TRY(hipGetLastError());
-    k_inverse_global<<<B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
+    k_inverse_global<<<X.B, 256, 0, st>>>(p, X.d_blk, X.d_chol, X.d_inv);
+    MFA_TRY(hipGetLastError());
+  }
+  if (nc > 0) {
+    switch (p) {
+#define MFA_CHOLINV_CASE(PP)                                                        \
+  case PP:                                                                          \
+    k_chol_inv3<PP><<<dim3(gc, 1, nc), 256, clds, st>>>(tc, h->flag);               \
+    break;
+      MFA_CHOLINV_CASE(1)
+      MFA_CHOLINV_CASE(2)
+      MFA_CHOLINV_CASE(3)
+      MFA_CHOLINV_CASE(4)
+      MFA_CHOLINV_CASE(5)
+      MFA_CHOLINV_CASE(6)
+      MFA_CHOLINV_CASE(7)
+      MFA_CHOLINV_CASE(8)
+#undef MFA_CHOLINV_CASE
+      default:
+        break;
+    }
     MFA_TRY(hipGetLastError());
   }
   // M, Om and J (they need the local inverses)
-  {
-    const int64_t gx = std::max<int64_t>(std::max<int64_t>(n, m), (int64_t)nif * p);
-    k_tab_ops<<<dim3((unsigned)gx, nif > 0 ? 3 : 2), 64, 0, st>>>(
-        m, n, p, h->combine, nif, X.d_blk, X.d_blo, X.d_bhi, X.d_owner, X.d_ns, X.d_pown, X.d_span,
-        X.N[0], X.d_inv, X.d_span_if, X.d_dbas_if, X.M, X.Om, X.d_omT, X.J, X.d_gidJ);
-    MFA_TRY(hipGetLastError());
-  }
+  k_tab_ops3<<<dim3(go, any_if ? 3 : 2, na), 64, 0, st>>>(to, h->combine);
+  MFA_TRY(hipGetLastError());
   if (h->rhs == MFA_RHS_DATABOX) {
-    k_tab_Nseg<<<nblk(X.SD, 128), 128, 0, st>>>(p, B, X.d_blk, nullptr, X.N[0], X.Nseg, X.d_qmap);
-    k_tab_NsegT<<<nblk(X.SF, 128), 128, 0, st>>>(m, n, p, B, X.d_blk, X.d_span, X.N[0], X.NsegT);
-    k_tab_Zseg<<<nblk(X.SF, 64), 64, 0, st>>>(B, X.d_blk, X.d_inv, X.Zseg);
-    k_tab_Comb<<<nblk(n, 128), 128, 0, st>>>(n, h->combine, X.d_blk, X.d_blo, X.d_bhi, X.d_owner,
-                                             X.d_ns, X.Comb);
-    if (nif > 0)
-      k_tab_Jseg<<<nblk((int64_t)nif * p, 64), 64, 0, st>>>(nif, p, X.d_blk, X.d_span_if, X.d_dbas_if,
-                                                            X.d_inv, X.Jseg);
-    k_tab_Omseg<<<nblk(m, 128), 128, 0, st>>>(m, X.d_blk, X.d_pown, X.Om, X.Omseg);
-    MFA_TRY(hipGetLastError());
+    for (int k = 0; k < na; ++k) {
+      Axis &X = h->ax[act[k]];
+      const int n = X.n, B = X.B, nif = B - 1;
+      const int64_t m = X.m;
+      k_tab_Nseg<<<nblk(X.SD, 128), 128, 0, st>>>(p, B, X.d_blk, nullptr, X.N[0], X.Nseg, X.d_qmap);
+      k_tab_NsegT<<<nblk(X.SF, 128), 128, 0, st>>>(m, n, p, B, X.d_blk, X.d_span, X.N[0], X.NsegT);
+      k_tab_Zseg<<<nblk(X.SF, 64), 64, 0, st>>>(B, X.d_blk, X.d_inv, X.Zseg);
+      k_tab_Comb<<<nblk(n, 128), 128, 0, st>>>(n, h->combine, X.d_blk, X.d_blo, X.d_bhi, X.d_owner,
+                                               X.d_ns, X.Comb);
+      if (nif > 0)
+        k_tab_Jseg<<<nblk((int64_t)nif * p, 64), 64, 0, st>>>(nif, p, X.d_blk, X.d_span_if, X.d_dbas_if,
+                                                              X.d_inv, X.Jseg);
+      k_tab_Omseg<<<nblk(m, 128), 128, 0, st>>>(m, X.d_blk, X.d_pown, X.Om, X.Omseg);
+      MFA_TRY(hipGetLastError());
+    }
   }
   return hipSuccess;
 }
