@@ -715,13 +715,17 @@ mfa_status create_handle(const mfa_problem *prob, void *workspace, size_t bytes,
     return hip_fail(e, "hipGetDevice");
   }
   auto bail = [&](hipError_t err, const char *where) {
+    // work already queued may still read the plan image or the workspace
+    (void)hipStreamSynchronize(h.stream);
     delete H;
     return hip_fail(err, where);
   };
   if ((e = launch_zero_slots(h.stream, (unsigned long long *)h.flag, 2)) != hipSuccess)
     return bail(e, "zero flag");
   if ((e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0)) != hipSuccess) return bail(e, "fill P");
-  if ((e = upload_plan(&h)) != hipSuccess) return bail(e, "upload plan");
+  // the plan image stays alive until the synchronisation at the end of setup
+  std::vector<char> plan_img;
+  if ((e = upload_plan(&h, plan_img)) != hipSuccess) return bail(e, "upload plan");
   // Setup (basis, Gram, batched Cholesky, inverses, operator tables) runs
   // stage by stage, each stage of every active axis in one launch on the
   // caller's stream; the variants' tables follow per axis.
@@ -793,7 +797,10 @@ void mfa_destroy(mfa_handle *h) { delete h; }
 mfa_status mfa_set_timing(mfa_handle *H, int32_t class_mask) {
   if (mfa_status s0 = check_handle(H)) return s0;
   Handle &h = H->h;
-  HIP_CHECK(hipStreamSynchronize(h.stream), "set_timing");
+  // events still recorded on the stream return to the pool only once it is idle
+  bool pending = false;
+  for (auto &v : h.ev_used) pending = pending || !v.empty();
+  if (pending) HIP_CHECK(hipStreamSynchronize(h.stream), "set_timing");
   for (auto &v : h.ev_used) {
     for (auto &pr : v) {
       h.ev_pool.push_back(pr.first);

@@ -223,7 +223,9 @@ hipError_t launch_maxabs(hipStream_t st, const double *x, int64_t n, unsigned lo
 // setup kernels (one axis at a time)
 // one copy of every host-planned table (block bounds, owners, n_s, interface
 // parameters, identity stencil rows of inactive axes) into the workspace
-hipError_t upload_plan(Handle *h);
+// Copy the plan tables into the workspace (asynchronous on h->stream): `img`
+// holds the host image and must live until the stream has been synchronised.
+hipError_t upload_plan(Handle *h, std::vector<char> &img);
 // decode at arbitrary parameter points (npts x dim, float64, device)
 hipError_t launch_decode_points(Handle &h, const double *u, int64_t npts, void *out, bool f32,
                                 const int r[3]);

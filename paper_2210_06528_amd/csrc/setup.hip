@@ -873,8 +873,8 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
     if (e_ != hipSuccess) return e_;     \
   } while (0)
 
-hipError_t upload_plan(Handle *h) {
-  std::vector<char> img(h->upload_bytes, 0);
+hipError_t upload_plan(Handle *h, std::vector<char> &img) {
+  img.assign(h->upload_bytes, 0);
   auto put = [&](void *dev, const void *src, size_t bytes) {
     if (bytes) std::memcpy(img.data() + ((char *)dev - h->ws), src, bytes);
   };
@@ -888,8 +888,7 @@ hipError_t upload_plan(Handle *h) {
       put(X.d_csz, X.csz.data(), sizeof(int) * X.csz.size());
     }
     if (img.empty()) return hipSuccess;
-    MFA_TRY(hipMemcpyAsync(h->ws, img.data(), img.size(), hipMemcpyHostToDevice, h->stream));
-    return hipStreamSynchronize(h->stream);
+    return hipMemcpyAsync(h->ws, img.data(), img.size(), hipMemcpyHostToDevice, h->stream);
   }
   for (int ia = 0; ia < 3; ++ia) {
     Axis &X = h->ax[ia];
@@ -923,9 +922,8 @@ hipError_t upload_plan(Handle *h) {
     }
     if (X.d_w) put(X.d_w, X.w.data(), sizeof(double) * n);
   }
-  MFA_TRY(hipMemcpyAsync(h->ws, img.data(), img.size(), hipMemcpyHostToDevice, h->stream));
-  // the image is a local: wait for the copy before it goes out of scope
-  return hipStreamSynchronize(h->stream);
+  // the caller keeps the image until its next synchronisation of the stream
+  return hipMemcpyAsync(h->ws, img.data(), img.size(), hipMemcpyHostToDevice, h->stream);
 }
 
 hipError_t setup_axes(Handle *h, hipStream_t st) {
