@@ -10,6 +10,7 @@
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "mfa_internal.hpp"
@@ -365,6 +366,83 @@ __global__ void __launch_bounds__(256) k_jump_project_lines(const TG *__restrict
   }
 }
 
+// Interface projection on the matrix cores (FP64 MFMA, v_mfma_f64_16x16x4_f64):
+// U[row][col] = sum_k J[row][k] g[k][col], where k runs along axis a and col
+// over the other coordinates (their layout in strides: g element (k, col) at
+// gbase + k*gsk + col*gsc, U element (row, col) at ubase + row*usk + col),
+// with an outer index o for the axis-1 case (a line of axis 2 per o).  A wave
+// forms one 16 x 16 tile (16 interface rows, 16 columns): the K range is the
+// union of its rows' supports, and K-step s pairs operand slot q with
+// k = k0 + 4q + s, so that for the contiguous axis (CONTIG: columns are lines
+// of g, k contiguous) a lane's four values of four consecutive steps are one
+// 16-byte load.  Lane layout, checked by an in-bounds probe: A[i][k] in lane
+// i + 16k, B[k][j] in lane j + 16k, and D[i][j] in lane j + 16(i%4),
+// register i/4 (the FP32 instruction's D differs: lane j + 16(i/4), register
+// i%4).  A = J (rows from the table), B = g, D = U.  J rows outside their
+// support and columns past the array contribute zero.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename TG, bool CONTIG>
+__global__ void __launch_bounds__(256) k_jproj_mfma(const TG *__restrict__ g, double *__restrict__ U, int R,
+                                                    int nrt, int64_t ncol, int nct, int64_t gstride_o,
+                                                    int64_t ustride_o, int64_t gsk, int64_t gsc, int64_t usk,
+                                                    int nk, int64_t ntask, const int *__restrict__ Jcol,
+                                                    const int *__restrict__ Jlen,
+                                                    const double *__restrict__ Jval, int LJ) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int64_t task = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (task >= ntask) return;   // whole waves
+  const int T = (int)(task % nrt);
+  const int64_t ctg = task / nrt;
+  const int64_t o = ctg / nct;
+  const int64_t col = (ctg % nct) * 16 + c;
+  const bool colok = col < ncol;
+  const TG *gb = g + o * gstride_o + (colok ? col : 0) * gsc;
+  // this lane's J row (as operand row c) and the tile's K range
+  const int row = 16 * T + c;
+  const bool rowok = row < R;
+  const int c0 = rowok ? Jcol[(int64_t)row * LJ] : (1 << 30);
+  const int len = rowok ? Jlen[row] : 0;
+  int klo = rowok ? c0 : (1 << 30), khi = rowok ? c0 + len : 0;
+  for (int off = 32; off > 0; off >>= 1) {
+    klo = min(klo, __shfl_xor(klo, off, 64));
+    khi = max(khi, __shfl_xor(khi, off, 64));
+  }
+  klo = __builtin_amdgcn_readfirstlane(klo) & ~3;
+  khi = __builtin_amdgcn_readfirstlane(khi);
+  const double *jr = Jval + (int64_t)(rowok ? row : 0) * LJ;
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+  // four K-steps (16 values of k) per trip: slot q takes k = kb + 4q + s
+  for (int kb = klo; kb < khi; kb += 16) {
+    const int k4 = kb + 4 * q;   // this lane's four consecutive k
+    double a[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k4 + s;
+      const int t = k - c0;
+      a[s] = (t >= 0 && t < len) ? jr[t] : 0.0;
+    }
+    // four values of k per lane; contiguous (one cache line) when CONTIG
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = min(k4 + s, nk - 1);
+      const double v = tod(gb[(int64_t)k * gsk]);
+      b[s] = (colok && k4 + s < nk) ? v : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+  }
+  // D[i][j]: rows 16T + q + 4v, column col
+  if (colok) {
+    double *ub = U + o * ustride_o + col;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * T + q + 4 * v;
+      if (r < R) ub[(int64_t)r * usk] = acc[v];
+    }
+  }
+}
+
 // S_r^a for all axes and orders r < p.  Workgroup: a 16 x 64 tile of
 // (k1, k2) and a chunk [k0a, k0b) of k0; 64 x 4 threads, each owning 4 rows of
 // the tile.  Each plane of P (tile plus p-1 halo rows and columns) is staged
@@ -577,6 +655,33 @@ hipError_t launch_deriv_scale(Handle &h) {
 template <typename TG>
 hipError_t launch_jump_project(Handle &h, int a, const TG *g, double *U) {
   const Axis &X = h.ax[a];
+  if (!getenv("MFA_VECTOR_JPROJ")) {
+    // U = J_a applied along axis a on the matrix cores; U keeps the layout the
+    // expansion reads (axis a replaced by the rows in place; for a = 2 the
+    // rows outermost)
+    const int R = (X.B - 1) * h.p;
+    if (R == 0) return hipSuccess;
+    const int64_t n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
+    int64_t ncol, go = 0, uo = 0, gsk, gsc, usk, outer = 1;
+    if (a == 0) {
+      ncol = n1 * n2; gsk = n1 * n2; gsc = 1; usk = n1 * n2;
+    } else if (a == 1) {
+      outer = n0; ncol = n2; go = n1 * n2; uo = (int64_t)R * n2; gsk = n2; gsc = 1; usk = n2;
+    } else {
+      ncol = n0 * n1; gsk = 1; gsc = n2; usk = n0 * n1;
+    }
+    const int nct = (int)((ncol + 15) / 16), nrt = (R + 15) / 16;
+    const int64_t ntask = outer * nct * (int64_t)nrt;
+    const unsigned grid = (unsigned)((ntask + 3) / 4);
+    const int nk = X.n;
+    if (a == 2)
+      k_jproj_mfma<TG, true><<<grid, 256, 0, h.stream>>>(g, U, R, nrt, ncol, nct, go, uo, gsk, gsc, usk, nk,
+                                                         ntask, X.J.col, X.J.len, X.J.val, X.J.L);
+    else
+      k_jproj_mfma<TG, false><<<grid, 256, 0, h.stream>>>(g, U, R, nrt, ncol, nct, go, uo, gsk, gsc, usk, nk,
+                                                          ntask, X.J.col, X.J.len, X.J.val, X.J.L);
+    return hipGetLastError();
+  }
   const size_t jbytes = sizeof(double) * (size_t)(X.B - 1) * h.p * X.J.L;
   if (a == 2 && (int64_t)X.n * 8 <= 32768 && jbytes <= 16384) {
     const int64_t nlines = (int64_t)h.ax[0].n * h.ax[1].n;
