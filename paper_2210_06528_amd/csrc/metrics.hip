@@ -412,25 +412,47 @@ __global__ void __launch_bounds__(256) k_jproj_mfma(const TG *__restrict__ g, do
   khi = __builtin_amdgcn_readfirstlane(khi);
   const double *jr = Jval + (int64_t)(rowok ? row : 0) * LJ;
   doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-  // four K-steps (16 values of k) per trip: slot q takes k = kb + 4q + s
-  for (int kb = klo; kb < khi; kb += 16) {
-    const int k4 = kb + 4 * q;   // this lane's four consecutive k
-    double a[4], b[4];
+  // J operands of the four consecutive k from k4 (zero outside the row)
+  auto load_a = [&](int k4, double (&a)[4]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int k = k4 + s;
-      const int t = k - c0;
+      const int t = k4 + s - c0;
       a[s] = (t >= 0 && t < len) ? jr[t] : 0.0;
     }
-    // four values of k per lane; contiguous (one cache line) when CONTIG
+  };
+  // residual operands: k4 .. k4+3 of this lane's column (zero past the axis
+  // or the columns); one 16-byte read when they are contiguous floats
+  const bool vec = CONTIG && sizeof(TG) == 4 && (nk & 3) == 0 && (gsc & 3) == 0;
+  auto load_b = [&](int k4, double (&b)[4]) {
+    if (vec && k4 + 3 < nk) {
+      const float4 f = *reinterpret_cast<const float4 *>(gb + k4);
+      b[0] = colok ? f.x : 0.0;
+      b[1] = colok ? f.y : 0.0;
+      b[2] = colok ? f.z : 0.0;
+      b[3] = colok ? f.w : 0.0;
+    } else {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = min(k4 + s, nk - 1);
-      const double v = tod(gb[(int64_t)k * gsk]);
-      b[s] = (colok && k4 + s < nk) ? v : 0.0;
+      for (int s = 0; s < 4; ++s) {
+        const int k = min(k4 + s, nk - 1);
+        const double v = tod(gb[(int64_t)k * gsk]);
+        b[s] = (colok && k4 + s < nk) ? v : 0.0;
+      }
     }
+  };
+  // two groups of four K-steps (32 values of k) per trip, all operands
+  // requested before the first product; K-step s of a group pairs slot q
+  // with k = base + 4q + s
+  for (int kb = klo; kb < khi; kb += 32) {
+    double a0[4], b0[4], a1[4], b1[4];
+    load_a(kb + 4 * q, a0);
+    load_a(kb + 16 + 4 * q, a1);
+    load_b(kb + 4 * q, b0);
+    // past khi a1 is zero: any in-bounds, 4-aligned k serves
+    load_b(min(kb + 16, (khi - 1) & ~3) + 4 * q, b1);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], acc, 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], acc, 0, 0, 0);
   }
   // D[i][j]: rows 16T + q + 4v, column col
   if (colok) {
