@@ -439,9 +439,9 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
 // The grid is one-dimensional, nb2 blocks per plane: workgroups are dealt to
 // the 8 XCDs round-robin, and the renumbering gives each XCD a contiguous run
 // of planes, so the blocks of one plane (whose column ranges overlap) share an
-// L2.  The M_2 fragments of a wave's tile are loaded once; the next chunk of
-// lines is loaded into registers while the current one is multiplied.  At
-// most 168 registers per lane (three waves per SIMD, as many workgroups per CU
+// L2.  The M_2 fragments of a wave's tile are loaded once; the next two
+// chunks of lines are in flight in registers while the current one is
+// multiplied.  At most 168 registers per lane (three waves per SIMD, as many workgroups per CU
 // as the LDS holds).
 template <bool VEC>
 __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict__ in, float *__restrict__ out,
@@ -499,32 +499,39 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
   // rows are 16-byte aligned (VEC), columns past n2 read as zeros, and each
   // block stored split as one 16-byte write per half.
   const int nbw = jw / 8, nblk32 = 32 * nbw;
-  float v[2][8];
-  auto fetch = [&](int l0) {
+  // Two chunks of lines in flight: the loads of chunk l0 + 64 are issued
+  // after chunk l0 is staged, so a chunk's data has the products of the
+  // chunk before it to arrive.  Every load is issued (indices clamped in
+  // bounds, values past the plane zeroed after the load) so that the waits,
+  // which count loads in issue order, never cover the later chunk.
+  auto fetch = [&](int l0, float(&v)[2][8]) {
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
       const int bi = threadIdx.x + 256 * hh;
       const int li = bi / nbw, j0 = jlo + 8 * (bi - li * nbw);
       const bool ok = bi < nblk32 && l0 + li < n1;
-      const float *src = plane + (int64_t)(ok ? l0 + li : 0) * n2 + (ok ? j0 : 0);
+      const float *row = plane + (int64_t)min(l0 + li, n1 - 1) * n2;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        if (VEC && ok && j0 + 4 * u + 3 < n2) {
-          const float4 f = *reinterpret_cast<const float4 *>(src + 4 * u);
-          v[hh][4 * u] = f.x;
-          v[hh][4 * u + 1] = f.y;
-          v[hh][4 * u + 2] = f.z;
-          v[hh][4 * u + 3] = f.w;
+        if (VEC) {
+          const int jj = j0 + 4 * u;   // a multiple of 4, as is n2
+          const float4 f = *reinterpret_cast<const float4 *>(row + min(jj, n2 - 4));
+          const bool okk = ok && jj < n2;
+          v[hh][4 * u] = okk ? f.x : 0.f;
+          v[hh][4 * u + 1] = okk ? f.y : 0.f;
+          v[hh][4 * u + 2] = okk ? f.z : 0.f;
+          v[hh][4 * u + 3] = okk ? f.w : 0.f;
         } else {
 #pragma unroll
-          for (int q = 4 * u; q < 4 * u + 4; ++q) v[hh][q] = (ok && j0 + q < n2) ? src[q] : 0.f;
+          for (int q = 4 * u; q < 4 * u + 4; ++q) {
+            const float f = row[min(j0 + q, n2 - 1)];
+            v[hh][q] = (ok && j0 + q < n2) ? f : 0.f;
+          }
         }
       }
     }
   };
-  fetch(0);
-  for (int l0 = 0; l0 < n1; l0 += 32) {
-    __syncthreads();   // the previous chunk's staging is consumed
+  auto stage = [&](const float(&v)[2][8]) {
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
       const int bi = threadIdx.x + 256 * hh;
@@ -540,40 +547,56 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
         *reinterpret_cast<bf16x8 *>(Llo + li * ldw + 8 * bj) = lv;
       }
     }
-    __syncthreads();
-    if (l0 + 32 < n1) fetch(l0 + 32);
-    if (mine) {
-      floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-      const int aoff = (16 * lbk + r16) * ldw + 8 * kq - jlo;
+  };
+  auto apply = [&](int l0) {
+    if (!mine) return;
+    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int aoff = (16 * lbk + r16) * ldw + 8 * kq - jlo;
 #pragma unroll
-      for (int c = 0; c < kPre; ++c) {
-        if (c < nc2) {
-          const int j0 = lo2 + 32 * c;
-          acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), bhi[c], blo[c], acc);
-        }
-      }
-      for (int c = kPre; c < nc2; ++c) {
+    for (int c = 0; c < kPre; ++c) {
+      if (c < nc2) {
         const int j0 = lo2 + 32 * c;
-        acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), load8(M2hi + moff + j0),
-                    load8(M2lo + moff + j0), acc);
-      }
-      const int ii = 16 * (w & 1) + r16;   // output k2 - K2a
-      const int j1 = l0 + 16 * lbk + 4 * kq;
-      if (j1 + 3 < n1) {   // four consecutive rows: one 8-byte write per half
-        __hip_bfloat16 hb[4], lb[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) split_bf16(acc[q], hb[q], lb[q]);
-        uint2 hv, lv;
-        __builtin_memcpy(&hv, hb, sizeof(hv));
-        __builtin_memcpy(&lv, lb, sizeof(lv));
-        *reinterpret_cast<uint2 *>(Thi + ii * ld1 + j1) = hv;
-        *reinterpret_cast<uint2 *>(Tlo + ii * ld1 + j1) = lv;
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (j1 + q < n1) split_bf16(acc[q], Thi[ii * ld1 + j1 + q], Tlo[ii * ld1 + j1 + q]);
+        acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), bhi[c], blo[c], acc);
       }
     }
+    for (int c = kPre; c < nc2; ++c) {
+      const int j0 = lo2 + 32 * c;
+      acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), load8(M2hi + moff + j0),
+                  load8(M2lo + moff + j0), acc);
+    }
+    const int ii = 16 * (w & 1) + r16;   // output k2 - K2a
+    const int j1 = l0 + 16 * lbk + 4 * kq;
+    if (j1 + 3 < n1) {   // four consecutive rows: one 8-byte write per half
+      __hip_bfloat16 hb[4], lb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) split_bf16(acc[q], hb[q], lb[q]);
+      uint2 hv, lv;
+      __builtin_memcpy(&hv, hb, sizeof(hv));
+      __builtin_memcpy(&lv, lb, sizeof(lv));
+      *reinterpret_cast<uint2 *>(Thi + ii * ld1 + j1) = hv;
+      *reinterpret_cast<uint2 *>(Tlo + ii * ld1 + j1) = lv;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (j1 + q < n1) split_bf16(acc[q], Thi[ii * ld1 + j1 + q], Tlo[ii * ld1 + j1 + q]);
+    }
+  };
+  // two chunks per trip, so that the buffers swap roles without copies
+  float va[2][8], vb[2][8];
+  fetch(0, va);
+  fetch(32, vb);
+  for (int l0 = 0; l0 < n1; l0 += 64) {
+    __syncthreads();   // the previous chunk's staging is consumed
+    stage(va);
+    __syncthreads();
+    fetch(l0 + 64, va);
+    apply(l0);
+    if (l0 + 32 >= n1) break;
+    __syncthreads();
+    stage(vb);
+    __syncthreads();
+    fetch(l0 + 96, vb);
+    apply(l0 + 32);
   }
   __syncthreads();
   double dmax = 0.0;
