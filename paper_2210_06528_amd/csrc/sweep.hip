@@ -53,11 +53,53 @@ constexpr int kTZ = 64;   // z outputs per workgroup (one per lane)
 constexpr int kTY = 16;   // y outputs per workgroup
 constexpr int kRY = 2;    // y outputs per thread
 constexpr int kRT = 512;  // threads per workgroup (kTY / kRY wavefronts)
+// a buffer offset beyond every range the residual builds (ranges stay below
+// 2^31 bytes, which the launcher checks)
+constexpr unsigned kOOB = 0x80000000u;
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Raw buffer descriptor over `bytes` bytes from p (no stride, 32-bit data
+// format): a load past the range returns zero and a store past it is
+// dropped.  The residual takes its zero halo (cells outside the array,
+// planes outside the array) and its discarded outputs (points past the
+// array's edge, planes another chunk owns) from this range check instead
+// of lane masks and branches.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld64(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <typename TG>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, double v);
+template <>
+__device__ __forceinline__ void buf_st<float>(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)v), r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buf_st<double>(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buf_st<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, unsigned off,
+                                                       double v) {
+  __builtin_amdgcn_raw_buffer_store_b16(
+      __builtin_bit_cast(unsigned short, __float2bfloat16((float)v)), r, (int)off, 0, 0);
+}
+// lane l's value of v, as a wave-uniform (scalar) value
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const u32x2 b = __builtin_bit_cast(u32x2, v);
+  u32x2 o;
+  o.x = (unsigned)__builtin_amdgcn_readlane((int)b.x, l);
+  o.y = (unsigned)__builtin_amdgcn_readlane((int)b.y, l);
+  return __builtin_bit_cast(double, o);
+}
 
 // Coefficient tables Aa[k*(2P+1) + t] = A_a[k][k-P+t] (0 outside the matrix);
 // an inactive axis (length 1) has the identity row.
 template <int P, typename TG>
-__global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
+__global__ void __launch_bounds__(kRT, (P <= 4 ? 4 : 1)) k_resid(const double *__restrict__ Pc,
                                                const double *__restrict__ c, TG *__restrict__ g,
                                                const double *__restrict__ A0,
                                                const double *__restrict__ A1,
@@ -66,9 +108,15 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
   constexpr int W = 2 * P + 1;
   constexpr int LY = kTY + 2 * P;
   constexpr int LZ = kTZ + 2 * P;
-  // double-buffered by plane parity (one barrier per plane, see below)
-  __shared__ double tile[2][LY][LZ + 1];
-  __shared__ double tz[2][LY][kTZ + 1];
+  constexpr int NE = (LY * LZ + kRT - 1) / kRT;   // tile elements per thread
+  constexpr int NZR = (LY + 7) / 8;               // z-pass rows per wavefront
+  // tile rows: the z pass reads rows up to 8 NZR - 1, and the flat stores of
+  // the last element group run past LY LZ (rows beyond LY are never used)
+  constexpr int TR = (8 * NZR > (NE * kRT + LZ - 1) / LZ) ? 8 * NZR : (NE * kRT + LZ - 1) / LZ;
+  // double-buffered by plane parity (one barrier per plane, see below);
+  // tile rows are unpadded (every access is contiguous across the lanes)
+  __shared__ double tile[2][TR * LZ];
+  __shared__ double tz[2][8 * NZR][kTZ + 1];
   const int tx = threadIdx.x & 63;
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wavefront index 0..7
   // Workgroups are dealt to the 8 XCDs round-robin in launch order.  Renumber
@@ -99,13 +147,20 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
     for (int e = threadIdx.x; e < kNumSlots * kSlotCopies; e += kRT) turn.prev[e] = 0ull;
   }
   const int gz = z0 + tx;
-  // this lane's axis-2 stencil row stays in registers (one LDS read per tap
-  // saved on every tile row of every plane)
+  // Stencil rows of the points past the array's edge are zero, so that those
+  // points' residuals are exactly 0 (their stores are dropped by the range
+  // check and they do not reach the max |g| reduction).  This lane's axis-2
+  // row stays in registers; the wavefront's two axis-1 rows are uniform and
+  // loaded once.
   double az[W];
-  {
-    const double *ar = A2 + (int64_t)min(gz, n2 - 1) * W;
 #pragma unroll
-    for (int t = 0; t < W; ++t) az[t] = ar[t];
+  for (int t = 0; t < W; ++t) az[t] = gz < n2 ? A2[(int64_t)gz * W + t] : 0.0;
+  double ay[kRY][W];
+#pragma unroll
+  for (int r = 0; r < kRY; ++r) {
+    const int gy = y0 + ty * kRY + r;
+#pragma unroll
+    for (int t = 0; t < W; ++t) ay[r][t] = gy < n1 ? A1[(int64_t)gy * W + t] : 0.0;
   }
   double ring[W][kRY];
 #pragma unroll
@@ -113,56 +168,54 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
 #pragma unroll
     for (int r = 0; r < kRY; ++r) ring[t][r] = 0.0;
   double nres = 0.0;
-  // Plane-invariant gathers: every thread's tile elements and right-hand-side
-  // entries as 32-bit offsets within a plane (clamped to 0 where outside the
-  // array, the value then replaced by 0), so a plane's loads are one address
-  // add each and carry no branches.
-  constexpr int NE = (LY * LZ + kRT - 1) / kRT;
+  // Plane-invariant byte offsets: every thread's tile elements and output
+  // points within a plane, kOOB where outside the array (the load then
+  // returns 0, the store is dropped).
   const int64_t plane = (int64_t)n1 * n2;
-  int toff[NE];
-  unsigned tmask = 0;
+  unsigned toff[NE];
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
     const int e = threadIdx.x + kRT * i;
     const int yy = e / LZ, zz = e - yy * LZ;
     const int gy = y0 - P + yy, gzz = z0 - P + zz;
     const bool ok = e < LY * LZ && gy >= 0 && gy < n1 && gzz >= 0 && gzz < n2;
-    toff[i] = ok ? gy * n2 + gzz : 0;
-    tmask |= (unsigned)ok << i;
+    toff[i] = ok ? (unsigned)(gy * n2 + gzz) * 8u : kOOB;
   }
-  int coff[kRY];
-  unsigned cmask = 0;
+  // right-hand side byte offsets of the thread's points; the output offset
+  // is this shifted right by log2(8 / sizeof(TG)), which keeps kOOB past
+  // the output's range
+  unsigned coff[kRY];
 #pragma unroll
   for (int r = 0; r < kRY; ++r) {
     const int gy = y0 + ty * kRY + r;
-    const bool ok = gy < n1 && gz < n2;
-    coff[r] = ok ? gy * n2 + gz : 0;
-    cmask |= (unsigned)ok << r;
+    coff[r] = (gy < n1 && gz < n2) ? (unsigned)(gy * n2 + gz) * 8u : kOOB;
   }
+  constexpr int kGShift = sizeof(TG) == 8 ? 0 : sizeof(TG) == 4 ? 1 : 2;
+  const int pbytes = (int)(plane * 8);
   // The tiles of the next two planes are in flight in registers while the
   // current plane is computed (software pipelining of the global loads, two
-  // buffers, the loop unrolled by two).  The loads are unconditional
-  // (in-bounds addresses) and the zero fill of out-of-range entries happens
-  // where the values are used, so no load is followed by an early wait; the
-  // plane count is rounded up to even so that no branch separates a load from
-  // its wait (the extra plane writes nothing).
+  // buffers, the loop unrolled by two); the plane count is rounded up to
+  // even so that no branch separates a load from its wait (the extra plane
+  // writes nothing).  Every global access is a buffer access, so the loop
+  // issues no scalar memory loads: their completion count is shared with
+  // LDS operations and would make every LDS wait a full wait.
   // One barrier per plane: the step of plane xi stores its tile into the
   // buffer of its parity, waits once, then runs the z pass of plane xi
   // (tile -> tz of that parity) and the y and x passes of plane xi - 1 (from
   // the other tz buffer, written before the barrier).  A buffer is rewritten
   // two steps after it was read, with a barrier in between.
   double preA[NE], preB[NE];
-  bool inA = false, inB = false;   // the plane held in the buffer lies inside the array
-  auto gload = [&](double (&buf)[NE], bool &bin, int xi) {
-    bin = xi >= 0 && xi < n0;
-    const double *base = Pc + (bin ? xi : 0) * plane;
+  auto gload = [&](double (&buf)[NE], int xi) {
+    const bool in = xi >= 0 && xi < n0;
+    const __amdgpu_buffer_rsrc_t r = buf_rsrc(Pc + (in ? xi : 0) * plane, in ? pbytes : 0);
 #pragma unroll
-    for (int i = 0; i < NE; ++i) buf[i] = base[toff[i]];
+    for (int i = 0; i < NE; ++i) buf[i] = buf_ld64(r, toff[i]);
   };
   const int xs = x0 - P, npl = (x1 + P - xs + 1) & ~1;
   // y pass of plane xo + P from tz[q] (ring of the last W planes' results),
-  // then, for an owned plane xo, its x pass and the residual
-  auto yx = [&](int q, int xo, const double (&axv)[W], const double (&cv)[kRY]) {
+  // then, for an owned plane xo, its x pass and the residual (zero stencil
+  // row and right-hand side elsewhere, store dropped)
+  auto yx = [&](int q, int xo, double a0v, const double (&cv)[kRY]) {
     {
       // the kRY rows of a thread share W - 1 of their W taps: one read each
       double tcol[W + kRY - 1];
@@ -170,81 +223,78 @@ __global__ void __launch_bounds__(kRT) k_resid(const double *__restrict__ Pc,
       for (int t = 0; t < W + kRY - 1; ++t) tcol[t] = tz[q][ty * kRY + t][tx];
 #pragma unroll
       for (int r = 0; r < kRY; ++r) {
-        const int yl = ty * kRY + r;
-        const double *ay = A1 + (int64_t)min(y0 + yl, n1 - 1) * W;
         double s = 0.0;
 #pragma unroll
-        for (int t = 0; t < W; ++t) s += ay[t] * tcol[r + t];
+        for (int t = 0; t < W; ++t) s += ay[r][t] * tcol[r + t];
 #pragma unroll
         for (int t = 0; t < W - 1; ++t) ring[t][r] = ring[t + 1][r];
         ring[W - 1][r] = s;
       }
     }
-    if (xo >= x0 && xo < x1) {
-#pragma unroll
-      for (int r = 0; r < kRY; ++r) {
-        if ((cmask >> r) & 1) {
-          double s = 0.0;
-#pragma unroll
-          for (int t = 0; t < W; ++t) s += axv[t] * ring[t][r];
-          const int64_t idx = xo * plane + coff[r];
-          const double gv = cv[r] - s;
-          g[idx] = from_d<TG>(gv);
-          nres = fmax(nres, fabs(gv));
-        }
-      }
-    }
-  };
-  // axis-0 stencil row (scalar loads) and right-hand side of output plane xo
-  auto rhs = [&](int xo, double (&axv)[W], double (&cv)[kRY]) {
     const bool own = xo >= x0 && xo < x1;
-    const double *ax = A0 + (int64_t)(own ? xo : 0) * W;
+    const __amdgpu_buffer_rsrc_t rg =
+        buf_rsrc(g + (own ? xo : 0) * plane, own ? (int)(plane * sizeof(TG)) : 0);
+    double axv[W];
 #pragma unroll
-    for (int t = 0; t < W; ++t) axv[t] = ax[t];
-    const double *cb = c + (own ? xo : 0) * plane;
+    for (int t = 0; t < W; ++t) axv[t] = lane_value(a0v, t);
 #pragma unroll
-    for (int r = 0; r < kRY; ++r) cv[r] = cb[coff[r]];
-  };
-  auto step = [&](double (&buf)[NE], bool &bin, int xi, int q) {
+    for (int r = 0; r < kRY; ++r) {
+      double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < NE; ++i) {
-      const int e = threadIdx.x + kRT * i;
-      if (e < LY * LZ) {
-        const int yy = e / LZ, zz = e - yy * LZ;
-        tile[q][yy][zz] = (bin && ((tmask >> i) & 1)) ? buf[i] : 0.0;
-      }
+      for (int t = 0; t < W; ++t) s += axv[t] * ring[t][r];
+      const double gv = cv[r] - s;
+      buf_st<TG>(rg, coff[r] >> kGShift, gv);
+      nres = fmax(nres, fabs(gv));
     }
+  };
+  // right-hand side and axis-0 stencil row of output plane xo (lane t < W
+  // holds the row's t-th coefficient; zero for a plane this chunk does not own)
+  auto rhs = [&](int xo, double &a0v, double (&cv)[kRY]) {
+    const bool own = xo >= x0 && xo < x1;
+    const __amdgpu_buffer_rsrc_t rc = buf_rsrc(c + (own ? xo : 0) * plane, own ? pbytes : 0);
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) cv[r] = buf_ld64(rc, coff[r]);
+    const __amdgpu_buffer_rsrc_t ra = buf_rsrc(A0, n0 * W * 8);
+    a0v = buf_ld64(ra, own ? (unsigned)(xo * W + min(tx, W - 1)) * 8u : kOOB);
+  };
+  auto step = [&](double (&buf)[NE], int xi, int q) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) tile[q][threadIdx.x + kRT * i] = buf[i];
     // the right-hand side of the plane output in this step, requested after
     // the wait for the tile (loads return in order) and before the tile two
     // planes ahead, so that neither wait covers the other
-    double axv[W], cv[kRY];
-    rhs(xi - 1 - P, axv, cv);
+    double a0v, cv[kRY];
+    rhs(xi - 1 - P, a0v, cv);
     __syncthreads();
     // past the chunk's last plane the prefetch re-reads that plane (cache
     // hits, never used) instead of the next chunk's planes
-    gload(buf, bin, min(xi + 2, x1 + P - 1));
-    for (int yy = ty; yy < LY; yy += kRT / 64) {
+    gload(buf, min(xi + 2, x1 + P - 1));
+    // z pass: a wavefront's rows ty, ty + 8, ... as independent chains
+    // (rows past LY are computed from unused tile rows and never read)
+#pragma unroll
+    for (int k = 0; k < NZR; ++k) {
+      const double *tr = &tile[q][(ty + 8 * k) * LZ + tx];
       double s = 0.0;
 #pragma unroll
-      for (int t = 0; t < W; ++t) s += az[t] * tile[q][yy][tx + t];
-      tz[q][yy][tx] = s;
+      for (int t = 0; t < W; ++t) s += az[t] * tr[t];
+      tz[q][ty + 8 * k][tx] = s;
     }
-    if (xi > xs) yx(q ^ 1, xi - 1 - P, axv, cv);
+    if (xi > xs) yx(q ^ 1, xi - 1 - P, a0v, cv);
   };
-  gload(preA, inA, xs);
+  gload(preA, xs);
   // keep A's loads ahead of B's: the waits count loads in issue order
   asm volatile("" ::: "memory");
-  gload(preB, inB, xs + 1);
+  gload(preB, xs + 1);
   for (int xi = xs; xi < xs + npl; xi += 2) {
-    step(preA, inA, xi, 0);
-    step(preB, inB, xi + 1, 1);
+    step(preA, xi, 0);
+    step(preB, xi + 1, 1);
   }
   {
     // the last plane's y and x passes (its z pass went to tz[1]: npl is even)
-    double axv[W], cv[kRY];
-    rhs(xs + npl - 1 - P, axv, cv);
+    double a0v, cv[kRY];
+    rhs(xs + npl - 1 - P, a0v, cv);
     __syncthreads();
-    yx(1, xs + npl - 1 - P, axv, cv);
+    yx(1, xs + npl - 1 - P, a0v, cv);
   }
   slot_max_c(slots, kSlotNres, nres);
 }
@@ -558,8 +608,10 @@ template <int P, typename TG>
 hipError_t launch_resid_p(hipStream_t st, const double *Pc, const double *c, TG *g, const double *A0,
                           const double *A1, const double *A2, int n0, int n1, int n2,
                           unsigned long long *slots, const SlotTurn &turn, bool may_tune) {
-  // the kernel addresses within a plane with 32-bit offsets
-  if ((int64_t)n1 * n2 > INT32_MAX) return hipErrorInvalidValue;
+  // the kernel addresses a plane (and the axis-0 table) through buffer
+  // ranges of fewer than 2^31 bytes
+  if ((int64_t)n1 * n2 * 8 > INT32_MAX || (int64_t)n0 * (2 * P + 1) * 8 > INT32_MAX)
+    return hipErrorInvalidValue;
   const int byz = (int)(nblk(n2, kTZ) * nblk(n1, kTY));
   const ResidKey key{n0, n1, n2, P, (int)sizeof(TG)};
   int xchunk = 0;
