@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=5,
                     help="oracle sweeps timed for the CPU baseline (about 3 s each here)")
+    ap.add_argument("--resid-every", type=int, default=5,
+                    help="in the timed steps, event-time one residual stencil launch in every N "
+                         "(launches s mod N, s + N, ... in timed step s, so that every launch "
+                         "position is sampled alike; each event record takes a few microseconds "
+                         "of the stream)")
     ap.add_argument("--breakdown-steps", type=int, default=2,
                     help="extra untimed steps with every kernel class event-timed")
     ap.add_argument("--no-fp64-compare", action="store_true",
@@ -111,7 +116,7 @@ def _resid_digest(path):
     return hashlib.sha256("".join(parts).encode()).hexdigest()
 
 
-def roofline(w, ktimes):
+def roofline(w, ktimes, every=1):
     """Roofline of the residual stencil k_resid, the largest single kernel of
     the sweep (one launch per sweep; HBM bound).
 
@@ -119,7 +124,10 @@ def roofline(w, ktimes):
     c = N^T Q (float64) once, write the residual g once (float32 in the
     mixed modes, float64 otherwise): 20 or 24 B.  The average duration is the
     HIP-event time of the launches on the encoder's stream over the timed
-    steps.
+    steps, one launch in every `every` (launches s mod every, + every, ...
+    in timed step s, so that over the steps every launch position of an
+    encode is sampled alike: the first sweep's launch is slower; each event
+    record costs the stream a few microseconds).
     """
     ms, n = ktimes.get("resid", (0.0, 0))
     if n == 0 or ms <= 0:
@@ -136,7 +144,8 @@ def roofline(w, ktimes):
         traffic = (rc["fetch_kib"] * rc["fetch_factor"] + rc["write_kib"] * rc["write_factor"]) * 1024
     return {"kernel": "k_resid", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-            "bytes_per_launch": per, "avg_launch_us": avg_s * 1e6, "launches": n}
+            "bytes_per_launch": per, "avg_launch_us": avg_s * 1e6, "launches": n,
+            "timed_every": every}
 
 
 def compare_fp64(w, q, out, f_mixed, max_sweeps, tol, args, ms_mixed):
@@ -519,10 +528,10 @@ def main():
     max_sweeps = w.sweeps or args.max_sweeps
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
 
-    def step(classes=("resid",)):
+    def step(classes=("resid",), every=args.resid_every, first=0):
         ev[0].record()
         enc.recreate()
-        enc.set_timing(True, classes)
+        enc.set_timing(True, classes, every, first)
         ev[1].record()
         st = enc.encode(q, max_sweeps, tol, args.check_every)
         ev[2].record()
@@ -537,9 +546,9 @@ def main():
     sweeps_total = 0
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for si in range(args.steps):
         ts = time.perf_counter()
-        st = step()
+        st = step(first=si % max(1, args.resid_every))
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - ts) * 1e3)
         phases.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
@@ -559,7 +568,7 @@ def main():
     # stencil, the kernel the roofline reports
     breakdown = {}
     for _ in range(args.breakdown_steps):
-        step(classes=None)
+        step(classes=None, every=1)
         for k in _lib.KERNEL_CLASSES:
             ms_k, n_k = enc.kernel_time(k)
             a, b = breakdown.get(k, (0.0, 0))
@@ -585,7 +594,7 @@ def main():
     if w.precision != "fp64" and not args.no_fp64_compare:
         res["fp64_paths"] = compare_fp64(w, q, out, enc.decode(dtype=torch.float64), max_sweeps, tol,
                                          args, ms)
-    res["roofline"] = roofline(w, ktimes)
+    res["roofline"] = roofline(w, ktimes, args.resid_every)
     # Algorithm 1's error vector of the result against the data (untimed:
     # one decode-and-compare pass)
     mx, l2 = enc.fit_error()

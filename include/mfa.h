@@ -307,6 +307,16 @@ typedef enum {
 mfa_status mfa_set_timing(mfa_handle *h, int32_t class_mask);
 mfa_status mfa_kernel_time(mfa_handle *h, int32_t kclass, double *total_ms, int64_t *launches);
 
+/* Sampled timing: counting the launches of each timed class from 0 (from
+ * this call or the last mfa_set_timing), only launches first, first + every,
+ * first + 2 every, ... get the event pair (every = 1, first = 0, the
+ * default, times them all); the launch count mfa_kernel_time returns is the
+ * number timed.  Each event record costs the stream a few microseconds, so a
+ * caller that times a kernel launched many times over can sample it; varying
+ * `first` over repeated runs samples every launch position equally.  Needs
+ * every >= 1 and 0 <= first < every, else MFA_EINVAL.  */
+mfa_status mfa_set_timing_every(mfa_handle *h, int32_t every, int32_t first);
+
 /* Release the handle (not the caller-owned workspace).  NULL is ignored.   */
 void mfa_destroy(mfa_handle *h);
 

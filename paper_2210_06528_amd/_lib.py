@@ -28,8 +28,8 @@ STATUS_NAMES = {0: "MFA_OK", -1: "MFA_EINVAL", -2: "MFA_ENOMEM", -3: "MFA_EDEVIC
 
 # every entry point the header declares
 EXPORTS = ["mfa_workspace_size", "mfa_create", "mfa_encode", "mfa_schwarz_step", "mfa_decode",
-           "mfa_get_ctrl", "mfa_set_ctrl", "mfa_inspect", "mfa_set_timing", "mfa_kernel_time",
-           "mfa_decode_points", "mfa_create_noalloc", "mfa_fit_error", "mfa_set_stream",
+           "mfa_get_ctrl", "mfa_set_ctrl", "mfa_inspect", "mfa_set_timing", "mfa_set_timing_every",
+           "mfa_kernel_time", "mfa_decode_points", "mfa_create_noalloc", "mfa_fit_error", "mfa_set_stream",
            "mfa_ctrl_dims",
            "mfa_destroy", "mfa_last_error"]
 NOALLOC_MAX_BYTES = 256 * 1024 * 1024   # MFA_NOALLOC_MAX_BYTES
@@ -124,6 +124,8 @@ def load(path=LIB_PATH):
     lib.mfa_inspect.restype = c_int32
     lib.mfa_set_timing.argtypes = [c_void_p, c_int32]
     lib.mfa_set_timing.restype = c_int32
+    lib.mfa_set_timing_every.argtypes = [c_void_p, c_int32, c_int32]
+    lib.mfa_set_timing_every.restype = c_int32
     lib.mfa_kernel_time.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]
     lib.mfa_kernel_time.restype = c_int32
     lib.mfa_destroy.argtypes = [c_void_p]
@@ -375,11 +377,13 @@ class Encoder:
             # temporary's memory from being reused before it has been read
             src.record_stream(self.stream)
 
-    def set_timing(self, enable=True, classes=None):
-        """Event-time the kernel classes named in `classes` (all when None)."""
+    def set_timing(self, enable=True, classes=None, every=1, first=0):
+        """Event-time the kernel classes named in `classes` (all when None):
+        launches first, first + every, ... of each (all of them by default)."""
         mask = 0
         if enable:
             mask = 31 if classes is None else sum(1 << KERNEL_CLASSES[c] for c in classes)
+        check(self.lib.mfa_set_timing_every(self.handle, int(every), int(first)))
         check(self.lib.mfa_set_timing(self.handle, mask))
 
     def kernel_time(self, kclass):

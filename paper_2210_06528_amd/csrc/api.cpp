@@ -46,6 +46,7 @@ static hipEvent_t take_event(Handle &h) {
 
 TimeScope::TimeScope(Handle &hh, int c) : h(hh), cls(c) {
   if (!(h.timing & (1 << c))) return;
+  if (h.timing_seen[c]++ % h.timing_every != h.timing_first) return;
   e0 = take_event(h);
   e1 = take_event(h);
   if (e0) hipEventRecord(e0, h.stream);
@@ -809,6 +810,18 @@ mfa_status mfa_set_timing(mfa_handle *H, int32_t class_mask) {
     v.clear();
   }
   h.timing = class_mask & MFA_K_ALL;
+  for (auto &n : h.timing_seen) n = 0;
+  return MFA_OK;
+}
+
+mfa_status mfa_set_timing_every(mfa_handle *H, int32_t every, int32_t first) {
+  if (mfa_status s0 = check_handle(H)) return s0;
+  if (every < 1 || first < 0 || first >= every)
+    return fail(MFA_EINVAL, "timing sample: need every >= 1 and 0 <= first < every");
+  Handle &h = H->h;
+  h.timing_every = every;
+  h.timing_first = first;
+  for (auto &n : h.timing_seen) n = 0;
   return MFA_OK;
 }
 

@@ -142,6 +142,9 @@ struct Handle {
   int sweep = 0;
   // per-class event timing
   int timing = 0;                        // mask of timed kernel classes
+  int timing_every = 1;                  // time one launch in this many per class,
+  int timing_first = 0;                  // starting with this one (< timing_every)
+  int64_t timing_seen[MFA_K_COUNT] = {}; // launches per class since timing was set
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[MFA_K_COUNT];
   std::vector<hipEvent_t> ev_pool;
   ~Handle();
