@@ -414,6 +414,19 @@ struct AuxStreams {
   hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
 };
 
+double *pinned_block(int device) {
+  static thread_local double *per_dev[16] = {};
+  static thread_local bool tried[16] = {};
+  if (device < 0 || device >= 16) return nullptr;
+  if (!tried[device]) {
+    tried[device] = true;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, sizeof(double) * kPinnedDoubles, hipHostMallocDefault) == hipSuccess)
+      per_dev[device] = static_cast<double *>(p);
+  }
+  return per_dev[device];
+}
+
 static AuxStreams *aux_streams(int device) {
   static thread_local AuxStreams per_dev[16];
   if (device < 0 || device >= 16) return nullptr;
@@ -606,21 +619,35 @@ mfa_status encode_variant(Handle &h, mfa_step_stats *out) {
 // same synchronisation.
 mfa_status read_stats(Handle &h, mfa_step_stats *out, double jump_tol, bool *finite,
                       double *hist_val = nullptr, int hist_idx = 0) {
-  std::vector<unsigned long long> raw((size_t)kNumSlots * kSlotCopies);
-  HIP_CHECK(hipMemcpyAsync(raw.data(), h.slots, sizeof(unsigned long long) * raw.size(),
-                           hipMemcpyDeviceToHost, h.stream), "read stats");
-  if (hist_val)
-    HIP_CHECK(hipMemcpyAsync(hist_val, h.hist + hist_idx, sizeof(double), hipMemcpyDeviceToHost, h.stream),
-              "read correction history");
-  HIP_CHECK(hipStreamSynchronize(h.stream), "read stats");
-  // non-negative doubles order like their bit patterns (NaN sorts above inf)
-  auto val = [&](int s) {
-    unsigned long long m = 0;
-    for (int c = 0; c < kSlotCopies; ++c) m = std::max(m, raw[(size_t)s * kSlotCopies + c]);
-    double d;
-    std::memcpy(&d, &m, sizeof(d));
-    return d;
-  };
+  static_assert(kNumSlots + 1 <= kPinnedDoubles, "the slot maxima fit the pinned block");
+  // non-negative doubles order like their bit patterns (NaN sorts above inf):
+  // a slot's value is the largest bit pattern of its copies
+  std::vector<double> vals(kNumSlots);
+  // handles without allocations copy to pageable memory; the others have the
+  // slots reduced on the device into this thread's pinned block
+  double *pin = h.noalloc_gen ? nullptr : pinned_block(h.device);
+  if (pin) {
+    HIP_CHECK(launch_pack_slots(h.stream, h.slots, kNumSlots, kSlotCopies,
+                                hist_val ? h.hist + hist_idx : nullptr, pin),
+              "read stats");
+    HIP_CHECK(hipStreamSynchronize(h.stream), "read stats");
+    for (int s = 0; s < kNumSlots; ++s) vals[s] = pin[s];
+    if (hist_val) *hist_val = pin[kNumSlots];
+  } else {
+    std::vector<unsigned long long> raw((size_t)kNumSlots * kSlotCopies);
+    HIP_CHECK(hipMemcpyAsync(raw.data(), h.slots, sizeof(unsigned long long) * raw.size(),
+                             hipMemcpyDeviceToHost, h.stream), "read stats");
+    if (hist_val)
+      HIP_CHECK(hipMemcpyAsync(hist_val, h.hist + hist_idx, sizeof(double), hipMemcpyDeviceToHost, h.stream),
+                "read correction history");
+    HIP_CHECK(hipStreamSynchronize(h.stream), "read stats");
+    for (int s = 0; s < kNumSlots; ++s) {
+      unsigned long long m = 0;
+      for (int c = 0; c < kSlotCopies; ++c) m = std::max(m, raw[(size_t)s * kSlotCopies + c]);
+      std::memcpy(&vals[s], &m, sizeof(double));
+    }
+  }
+  auto val = [&](int s) { return vals[s]; };
   mfa_step_stats st{};
   st.sweep = h.sweep;
   st.res_max = st.res_l2 = std::numeric_limits<double>::quiet_NaN();
@@ -737,10 +764,22 @@ mfa_status create_handle(const mfa_problem *prob, void *workspace, size_t bytes,
   if (h.variant != MFA_VARIANT_SCHWARZ)
     for (int a = 0; a < 3; ++a)
       if (h.ax[a].active && (e = setup_variant_axis(&h, a, h.stream)) != hipSuccess) return bail(e, "setup");
+  // the pivot flag (an int in the first of two zeroed 8-byte slots): through
+  // this thread's pinned block unless the handle may not allocate
   int flag = 0;
-  if ((e = hipMemcpyAsync(&flag, h.flag, sizeof(int), hipMemcpyDeviceToHost, h.stream)) != hipSuccess)
-    return bail(e, "read flag");
-  if ((e = hipStreamSynchronize(h.stream)) != hipSuccess) return bail(e, "setup sync");
+  if (double *pin = noalloc_gen ? nullptr : pinned_block(h.device)) {
+    if ((e = launch_pack_slots(h.stream, (const unsigned long long *)h.flag, 1, 1, nullptr, pin)) !=
+        hipSuccess)
+      return bail(e, "read flag");
+    if ((e = hipStreamSynchronize(h.stream)) != hipSuccess) return bail(e, "setup sync");
+    unsigned long long bits = 0ull;   // compare bits: the pattern is a denormal
+    std::memcpy(&bits, pin, sizeof(bits));
+    flag = bits != 0ull;
+  } else {
+    if ((e = hipMemcpyAsync(&flag, h.flag, sizeof(int), hipMemcpyDeviceToHost, h.stream)) != hipSuccess)
+      return bail(e, "read flag");
+    if ((e = hipStreamSynchronize(h.stream)) != hipSuccess) return bail(e, "setup sync");
+  }
   if (flag) {
     delete H;
     return fail(MFA_ESINGULAR,

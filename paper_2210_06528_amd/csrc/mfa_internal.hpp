@@ -222,6 +222,16 @@ struct SlotTurn {
   int idx = 0;
 };
 hipError_t launch_maxabs(hipStream_t st, const double *x, int64_t n, unsigned long long *slot);
+// the maxima of nslots slots (ncopies copies each) and one extra value into
+// out[0..nslots] (pinned host memory): one small launch instead of a copy of
+// every slot copy to pageable memory
+hipError_t launch_pack_slots(hipStream_t st, const unsigned long long *slots, int nslots, int ncopies,
+                             const double *extra, double *out);
+constexpr int kPinnedDoubles = 512;   // per thread and device (pinned_block)
+// kPinnedDoubles doubles of pinned host memory for this host thread and
+// device, allocated on first use and kept for the life of the process
+// (nullptr if the allocation fails; callers then copy to pageable memory)
+double *pinned_block(int device);
 
 // setup kernels (one axis at a time)
 // one copy of every host-planned table (block bounds, owners, n_s, interface

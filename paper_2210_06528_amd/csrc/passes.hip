@@ -133,6 +133,22 @@ __global__ void k_zero_slots(unsigned long long *s, int n, double *hist, int idx
   if (i < n) s[i] = 0ull;
 }
 
+// out[s] = the largest of slot s's ncopies copies, as the double its bit
+// pattern is (s < nslots), then out[nslots] = *extra (0 without one).  One
+// workgroup; out is pinned host memory the host reads after synchronising.
+__global__ void k_pack_slots(const unsigned long long *__restrict__ slots, int nslots, int ncopies,
+                             const double *__restrict__ extra, double *out) {
+  for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
+    unsigned long long m = 0ull;
+    for (int c = 0; c < ncopies; ++c) {
+      const unsigned long long v = slots[(size_t)s * ncopies + c];
+      m = v > m ? v : m;
+    }
+    out[s] = __longlong_as_double((long long)m);
+  }
+  if (threadIdx.x == 0) out[nslots] = extra ? *extra : 0.0;
+}
+
 __global__ void __launch_bounds__(256) k_maxabs(const double *x, int64_t n, unsigned long long *slot) {
   double v = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -229,6 +245,12 @@ hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n, d
                              const unsigned long long *from) {
   static_assert(kSlotMaxDP == 0 && kSlotCopies == 64, "one wavefront reads the max-correction slot");
   k_zero_slots<<<nblk(n, 64), 64, 0, st>>>(slots, n, hist, idx, from ? from : slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_slots(hipStream_t st, const unsigned long long *slots, int nslots, int ncopies,
+                             const double *extra, double *out) {
+  k_pack_slots<<<1, 64, 0, st>>>(slots, nslots, ncopies, extra, out);
   return hipGetLastError();
 }
 
