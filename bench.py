@@ -553,10 +553,10 @@ def main():
         lat.append((time.perf_counter() - ts) * 1e3)
         phases.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
         sweeps_total += st["sweep"]
-        for k in _lib.KERNEL_CLASSES:
-            ms_k, n_k = enc.kernel_time(k)
-            a, b = ktimes.get(k, (0.0, 0))
-            ktimes[k] = (a + ms_k, b + n_k)
+        # only the residual stencil is timed in these steps
+        ms_k, n_k = enc.kernel_time("resid")
+        a, b = ktimes.get("resid", (0.0, 0))
+        ktimes["resid"] = (a + ms_k, b + n_k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms = wall * 1e3 / args.steps
