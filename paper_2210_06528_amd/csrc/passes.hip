@@ -133,20 +133,23 @@ __global__ void k_zero_slots(unsigned long long *s, int n, double *hist, int idx
   if (i < n) s[i] = 0ull;
 }
 
-// out[s] = the largest of slot s's ncopies copies, as the double its bit
-// pattern is (s < nslots), then out[nslots] = *extra (0 without one).  One
-// workgroup; out is pinned host memory the host reads after synchronising.
-__global__ void k_pack_slots(const unsigned long long *__restrict__ slots, int nslots, int ncopies,
-                             const double *__restrict__ extra, double *out) {
-  for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
-    unsigned long long m = 0ull;
-    for (int c = 0; c < ncopies; ++c) {
-      const unsigned long long v = slots[(size_t)s * ncopies + c];
-      m = v > m ? v : m;
-    }
-    out[s] = __longlong_as_double((long long)m);
+// out[s] = the largest of slot s's ncopies (<= 64) copies, as the double its
+// bit pattern is, then out[nslots] = *extra (0 without one).  One wavefront
+// per slot (workgroup s); out is pinned host memory the host reads after
+// synchronising.
+__global__ void __launch_bounds__(64) k_pack_slots(const unsigned long long *__restrict__ slots,
+                                                   int nslots, int ncopies,
+                                                   const double *__restrict__ extra, double *out) {
+  const int s = blockIdx.x, c = threadIdx.x;
+  unsigned long long m = c < ncopies ? slots[(size_t)s * ncopies + c] : 0ull;
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
   }
-  if (threadIdx.x == 0) out[nslots] = extra ? *extra : 0.0;
+  if (c == 0) {
+    out[s] = __longlong_as_double((long long)m);
+    if (s == 0) out[nslots] = extra ? *extra : 0.0;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_maxabs(const double *x, int64_t n, unsigned long long *slot) {
@@ -250,7 +253,8 @@ hipError_t launch_zero_slots(hipStream_t st, unsigned long long *slots, int n, d
 
 hipError_t launch_pack_slots(hipStream_t st, const unsigned long long *slots, int nslots, int ncopies,
                              const double *extra, double *out) {
-  k_pack_slots<<<1, 64, 0, st>>>(slots, nslots, ncopies, extra, out);
+  if (nslots < 1 || ncopies < 1 || ncopies > 64) return hipErrorInvalidValue;
+  k_pack_slots<<<nslots, 64, 0, st>>>(slots, nslots, ncopies, extra, out);
   return hipGetLastError();
 }
 
