@@ -110,6 +110,8 @@ __global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, do
   // registers while the current one is contracted; the loads use clamped
   // in-bounds indices and carry no branches (rows past the group and columns
   // past W are never stored or read).
+  // NTR zeros after the last staged row (the row stores never reach them)
+  for (int e = tid; e < NTR; e += BS) rows[RI * W + e] = (TQ)0;
   TQ pre[RI][NCW];
   auto fetch = [&](int64_t g) {
     const int nr = (int)min((int64_t)RI, r_hi - g);
@@ -131,25 +133,40 @@ __global__ void __launch_bounds__(256) k_proj_inner(const TQ *__restrict__ Q, do
         if (rr < nr && tid + cw * BS < W) rows[rr * W + tid + cw * BS] = pre[rr][cw];
     __syncthreads();
     fetch(min(g + RI, r_hi - 1));
-    for (int rr = 0; rr < nr; ++rr) {
-      const int64_t i1 = g + rr;
-      double v = 0.0;
-      const TQ *row = rows + rr * W + off;
+    // axis 2 for RB rows at a time as independent chains (rows past nr are
+    // stale and never used; RI is a multiple of RB).  Taps past len have
+    // zero weights and read the next values of the staged rows, or the
+    // zeroed pad after the last row, so every term is exact and in bounds.
+    constexpr int RB = NTR <= 12 ? 4 : (NTR <= 24 ? 2 : 1);
+    static_assert(RI % RB == 0, "row batches tile the group");
+    for (int r0 = 0; r0 < nr; r0 += RB) {
+      double vb[RB];
 #pragma unroll
-      for (int t = 0; t < NTR; ++t)
-        if (t < len) v += tv[t] * (double)row[t];
-      const int s = ss[i1 - r_lo];
-      if (s != cur) {   // s == cur + 1: row cur-p is complete
-        const int k1 = cur - P;
-        if (act && k1 >= K1a && k1 < K1b) dst[(int64_t)k1 * n2] = acc[0];
+      for (int b = 0; b < RB; ++b) {
+        const TQ *row = rows + (r0 + b) * W + off;
+        double v = 0.0;
 #pragma unroll
-        for (int q = 0; q < P; ++q) acc[q] = acc[q + 1];
-        acc[P] = 0.0;
-        cur = s;
+        for (int t = 0; t < NTR; ++t) v += tv[t] * (double)row[t];
+        vb[b] = v;
       }
-      const double *w = sw + (i1 - r_lo) * (P + 1);
 #pragma unroll
-      for (int q = 0; q <= P; ++q) acc[q] += w[q] * v;
+      for (int b = 0; b < RB; ++b) {
+        if (r0 + b >= nr) break;
+        const int64_t i1 = g + r0 + b;
+        const double v = vb[b];
+        const int s = ss[i1 - r_lo];
+        if (s != cur) {   // s == cur + 1: row cur-p is complete
+          const int k1 = cur - P;
+          if (act && k1 >= K1a && k1 < K1b) dst[(int64_t)k1 * n2] = acc[0];
+#pragma unroll
+          for (int q = 0; q < P; ++q) acc[q] = acc[q + 1];
+          acc[P] = 0.0;
+          cur = s;
+        }
+        const double *w = sw + (i1 - r_lo) * (P + 1);
+#pragma unroll
+        for (int q = 0; q <= P; ++q) acc[q] += w[q] * v;
+      }
     }
   }
 #pragma unroll
@@ -582,6 +599,7 @@ Rows rows_of(const Axis &X, int r) {
 }
 
 constexpr int kProjRI = 8;
+constexpr int kProjPad = 48;   // the largest N_2^T row length the projection takes
 constexpr int kDecRI = 8;
 
 int pick_chunk(int64_t parallel, int n, int lo) {
@@ -625,8 +643,10 @@ hipError_t project_p(Handle &h, const void *q, bool f32) {
   int maxrows1 = 0;
   for (int c = 0; c < nk1c; ++c)
     maxrows1 = (int)std::max<int64_t>(maxrows1, rows_of_chunk(m1, n1, c * K1C, std::min(n1, c * K1C + K1C)));
+  // staged rows plus a pad of the largest N_2^T row length (zeros the
+  // kernel's contraction may read past the last row)
   const size_t lds = (size_t)maxrows1 * (P + 1) * sizeof(double) + ((maxrows1 + 3) & ~3) * sizeof(int) +
-                     (size_t)kProjRI * W * esz;
+                     ((size_t)kProjRI * W + kProjPad) * esz;
   if (lds > 64 * 1024) return hipErrorNotSupported;
   const bool outer = X0.active;
   if (outer && h.s1n < m0 * n1 * (int64_t)n2) return hipErrorNotSupported;
