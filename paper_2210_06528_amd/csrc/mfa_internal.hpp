@@ -277,7 +277,8 @@ hipError_t launch_decode_grid(Handle &h, void *out, bool f32, const int r[3],
 bool mfma_fits(int npad);
 hipError_t setup_mfma_axes(Handle *h, hipStream_t st);
 // axes 2 and 1 of the split-BF16 correction in one pass (3-D problems)
-int fuse21_ldw(const Handle &h);
+// (and, in *maxnc when given, the most 32-column K chunks of one M_2 tile)
+int fuse21_ldw(const Handle &h, int *maxnc = nullptr);
 bool mfma_fused21_ok(const Handle &h);
 hipError_t launch_mfma_fused21(Handle &h, const float *in, float *out);
 hipError_t launch_mfma_correct(Handle &h, int axis, const float *in, float *out, bool add);

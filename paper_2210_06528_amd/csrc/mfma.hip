@@ -502,44 +502,46 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
   // Two chunks of lines in flight: the loads of chunk l0 + 64 are issued
   // after chunk l0 is staged, so a chunk's data has the products of the
   // chunk before it to arrive.  Every load is issued (indices clamped in
-  // bounds, values past the plane zeroed after the load) so that the waits,
-  // which count loads in issue order, never cover the later chunk.
+  // bounds) and holds the raw value; the values past the plane are zeroed
+  // where the chunk is staged, so that no wait for a chunk's loads comes
+  // before its staging (the waits count loads in issue order, and a select
+  // right after the load would wait for the later chunk's loads too).
   auto fetch = [&](int l0, float(&v)[2][8]) {
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
       const int bi = threadIdx.x + 256 * hh;
       const int li = bi / nbw, j0 = jlo + 8 * (bi - li * nbw);
-      const bool ok = bi < nblk32 && l0 + li < n1;
       const float *row = plane + (int64_t)min(l0 + li, n1 - 1) * n2;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         if (VEC) {
           const int jj = j0 + 4 * u;   // a multiple of 4, as is n2
           const float4 f = *reinterpret_cast<const float4 *>(row + min(jj, n2 - 4));
-          const bool okk = ok && jj < n2;
-          v[hh][4 * u] = okk ? f.x : 0.f;
-          v[hh][4 * u + 1] = okk ? f.y : 0.f;
-          v[hh][4 * u + 2] = okk ? f.z : 0.f;
-          v[hh][4 * u + 3] = okk ? f.w : 0.f;
+          v[hh][4 * u] = f.x;
+          v[hh][4 * u + 1] = f.y;
+          v[hh][4 * u + 2] = f.z;
+          v[hh][4 * u + 3] = f.w;
         } else {
 #pragma unroll
-          for (int q = 4 * u; q < 4 * u + 4; ++q) {
-            const float f = row[min(j0 + q, n2 - 1)];
-            v[hh][q] = (ok && j0 + q < n2) ? f : 0.f;
-          }
+          for (int q = 4 * u; q < 4 * u + 4; ++q) v[hh][q] = row[min(j0 + q, n2 - 1)];
         }
       }
     }
   };
-  auto stage = [&](const float(&v)[2][8]) {
+  auto stage = [&](int l0, const float(&v)[2][8]) {
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
       const int bi = threadIdx.x + 256 * hh;
       if (bi < nblk32) {
-        const int li = bi / nbw, bj = bi - li * nbw;
+        const int li = bi / nbw, bj = bi - li * nbw, j0 = jlo + 8 * bj;
+        const bool ok = l0 + li < n1;
         __hip_bfloat16 hb[8], lb[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) split_bf16(v[hh][q], hb[q], lb[q]);
+        for (int q = 0; q < 8; ++q) {
+          // VEC reads 4 values at a time: jj = j0 + 4 (q / 4) < n2 covers them
+          const bool okq = ok && (VEC ? j0 + 4 * (q / 4) < n2 : j0 + q < n2);
+          split_bf16(okq ? v[hh][q] : 0.f, hb[q], lb[q]);
+        }
         bf16x8 hv, lv;
         __builtin_memcpy(&hv, hb, sizeof(hv));
         __builtin_memcpy(&lv, lb, sizeof(lv));
@@ -559,11 +561,8 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
         acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), bhi[c], blo[c], acc);
       }
     }
-    for (int c = kPre; c < nc2; ++c) {
-      const int j0 = lo2 + 32 * c;
-      acc = mfma3(load8(Lhi + aoff + j0), load8(Llo + aoff + j0), load8(M2hi + moff + j0),
-                  load8(M2lo + moff + j0), acc);
-    }
+    // nc2 <= kPre (checked on the host): every K chunk's M_2 fragments are
+    // the ones loaded at the start
     const int ii = 16 * (w & 1) + r16;   // output k2 - K2a
     const int j1 = l0 + 16 * lbk + 4 * kq;
     if (j1 + 3 < n1) {   // four consecutive rows: one 8-byte write per half
@@ -587,13 +586,13 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
   fetch(32, vb);
   for (int l0 = 0; l0 < n1; l0 += 64) {
     __syncthreads();   // the previous chunk's staging is consumed
-    stage(va);
+    stage(l0, va);
     __syncthreads();
     fetch(l0 + 64, va);
     apply(l0);
     if (l0 + 32 >= n1) break;
     __syncthreads();
-    stage(vb);
+    stage(l0 + 32, vb);
     __syncthreads();
     fetch(l0 + 96, vb);
     apply(l0 + 32);
@@ -700,9 +699,10 @@ hipError_t setup_mfma_axes(Handle *h, hipStream_t st) {
 // outputs along axis 2 (two 16-row tiles of M_2), plus 8 of padding: the
 // host copy of the tile ranges k_tab_ktiles builds on the device (row k of
 // M spans the free sets of the blocks holding k: blo..bhi, or its owner).
-int fuse21_ldw(const Handle &h) {
+int fuse21_ldw(const Handle &h, int *maxnc) {
   const Axis &X = h.ax[2];
   const int n = X.n, ntiles = (n + 15) / 16;
+  if (maxnc) *maxnc = 0;
   std::vector<int> lo(ntiles), hi(ntiles);
   for (int t = 0; t < ntiles; ++t) {
     int l = 1 << 30, u = 0;
@@ -715,6 +715,7 @@ int fuse21_ldw(const Handle &h) {
     l &= ~7;
     lo[t] = l;
     hi[t] = l + 32 * ((u - l + 31) / 32);
+    if (maxnc) *maxnc = std::max(*maxnc, (u - l + 31) / 32);
   }
   int w = 0;
   for (int t = 0; t < ntiles; t += kIT / 16) {
@@ -735,8 +736,11 @@ static size_t fused21_lds(const Axis &X1, int ldw) {
 }
 
 bool mfma_fused21_ok(const Handle &h) {
-  const int ldw = fuse21_ldw(h);
-  return h.ax[1].active && h.ax[2].active && h.ax[2].n >= 16 && ldw > 0 &&
+  // phase 1 holds every 32-column K chunk of a tile's M_2 rows in registers:
+  // at most kPre of them
+  int maxnc = 0;
+  const int ldw = fuse21_ldw(h, &maxnc);
+  return h.ax[1].active && h.ax[2].active && h.ax[2].n >= 16 && ldw > 0 && maxnc <= kPre &&
          32 * ((ldw - 8) / 8) <= 512 && fused21_lds(h.ax[1], ldw) <= 64 * 1024 &&
          (int64_t)h.ax[0].n * nblk(h.ax[2].n, kIT) < (1ll << 31);
 }
