@@ -443,7 +443,11 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
 // chunks of lines are in flight in registers while the current one is
 // multiplied.  At most 168 registers per lane (three waves per SIMD, as many workgroups per CU
 // as the LDS holds).
-template <bool VEC>
+// NCH > 0: the plane has exactly NCH chunks of 32 lines (n1 <= 32 NCH) and
+// the chunk loop is unrolled, so the compiler counts the outstanding loads
+// of each chunk exactly; NCH = 0 loops over the chunks at run time (the
+// waits at the loop head then also cover the later chunk's loads).
+template <bool VEC, int NCH>
 __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict__ in, float *__restrict__ out,
                                                       int n1, int n2, int npad1, int npad2,
                                                       const __hip_bfloat16 *__restrict__ M1hi,
@@ -584,6 +588,23 @@ __global__ void __launch_bounds__(256, 3) k_mfma_fused21(const float *__restrict
   float va[2][8], vb[2][8];
   fetch(0, va);
   fetch(32, vb);
+  if constexpr (NCH > 0) {
+#pragma unroll
+    for (int c = 0; c < NCH; c += 2) {
+      __syncthreads();   // the previous chunk's staging is consumed
+      stage(32 * c, va);
+      __syncthreads();
+      if (c + 2 < NCH) fetch(32 * c + 64, va);
+      apply(32 * c);
+      if (c + 1 < NCH) {
+        __syncthreads();
+        stage(32 * c + 32, vb);
+        __syncthreads();
+        if (c + 3 < NCH) fetch(32 * c + 96, vb);
+        apply(32 * c + 32);
+      }
+    }
+  } else
   for (int l0 = 0; l0 < n1; l0 += 64) {
     __syncthreads();   // the previous chunk's staging is consumed
     stage(l0, va);
@@ -754,15 +775,28 @@ hipError_t launch_mfma_fused21(Handle &h, const float *in, float *out) {
   const __hip_bfloat16 *M2lo = M2hi + (int64_t)nr2 * X2.npad;
   const int ldw = fuse21_ldw(h);
   const unsigned nb2 = nblk(X2.n, kIT);
+  const int nch = (X1.n + 31) / 32;
+#define MFA_F21(V, N)                                                                               \
+  k_mfma_fused21<V, N><<<nb2 * (unsigned)h.ax[0].n, 256, fused21_lds(X1, ldw), h.stream>>>(         \
+      in, out, X1.n, X2.n, X1.npad, X2.npad, M1hi, M1lo, X1.d_klo, X1.d_knc, M2hi, M2lo, X2.d_klo, \
+      X2.d_knc, ldw, (int)nb2)
+#define MFA_F21N(V)                      \
+  switch (nch) {                         \
+    case 4: MFA_F21(V, 4); break;        \
+    case 6: MFA_F21(V, 6); break;        \
+    case 8: MFA_F21(V, 8); break;        \
+    case 12: MFA_F21(V, 12); break;      \
+    case 16: MFA_F21(V, 16); break;      \
+    default: MFA_F21(V, 0); break;       \
+  }
   // 16-byte row loads need rows (and the array) 16-byte aligned
-  if (X2.n % 4 == 0)
-    k_mfma_fused21<true><<<nb2 * (unsigned)h.ax[0].n, 256, fused21_lds(X1, ldw), h.stream>>>(
-        in, out, X1.n, X2.n, X1.npad, X2.npad, M1hi, M1lo, X1.d_klo, X1.d_knc, M2hi, M2lo, X2.d_klo,
-        X2.d_knc, ldw, (int)nb2);
-  else
-    k_mfma_fused21<false><<<nb2 * (unsigned)h.ax[0].n, 256, fused21_lds(X1, ldw), h.stream>>>(
-        in, out, X1.n, X2.n, X1.npad, X2.npad, M1hi, M1lo, X1.d_klo, X1.d_knc, M2hi, M2lo, X2.d_klo,
-        X2.d_knc, ldw, (int)nb2);
+  if (X2.n % 4 == 0) {
+    MFA_F21N(true)
+  } else {
+    MFA_F21N(false)
+  }
+#undef MFA_F21N
+#undef MFA_F21
   return hipGetLastError();
 }
 
