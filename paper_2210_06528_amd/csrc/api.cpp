@@ -751,6 +751,7 @@ mfa_status create_handle(const mfa_problem *prob, void *workspace, size_t bytes,
   if ((e = launch_zero_slots(h.stream, (unsigned long long *)h.flag, 2)) != hipSuccess)
     return bail(e, "zero flag");
   if ((e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0)) != hipSuccess) return bail(e, "fill P");
+  h.p_zero = true;
   // the plan image stays alive until the synchronisation at the end of setup
   std::vector<char> plan_img;
   if ((e = upload_plan(&h, plan_img)) != hipSuccess) return bail(e, "upload plan");
@@ -954,6 +955,7 @@ mfa_status mfa_schwarz_step(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype,
   if (mfa_status s0 = check_handle(H)) return s0;
   Handle &h = H->h;
   hipSetDevice(h.device);
+  h.p_zero = false;
   if (q_dev) {
     mfa_status s = load_q(h, q_dev, q_dtype);
     if (s != MFA_OK) return s;
@@ -982,6 +984,9 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
   if (max_sweeps < 1) return fail(MFA_EINVAL, "max_sweeps must be >= 1");
   Handle &h = H->h;
   hipSetDevice(h.device);
+  // a cold start needs P = 0, which a new handle already holds
+  const bool p_zero = h.p_zero;
+  h.p_zero = false;
   mfa_status s = load_q(h, q_dev, q_dtype);
   if (s != MFA_OK) return s;
   if (h.variant) {   // one-shot fit, no sweeps
@@ -989,7 +994,7 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
     return encode_variant(h, last);
   }
   h.sweep = 0;
-  if (!h.warm) {
+  if (!h.warm && !p_zero) {
     hipError_t e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0);
     if (e != hipSuccess) return hip_fail(e, "fill P");
   }
@@ -1143,6 +1148,7 @@ mfa_status mfa_set_ctrl(mfa_handle *H, const double *ctrl, int32_t on_device) {
     return MFA_OK;
   }
   const size_t bytes = sizeof(double) * (size_t)h.nctrl_total;
+  h.p_zero = false;
   HIP_CHECK(hipMemcpyAsync(h.P, ctrl, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            h.stream),
             "set_ctrl");

@@ -136,6 +136,7 @@ struct Handle {
   int q_dtype = 0;
   int g_type = 0;           // element type of g: 0 float64, 1 float32, 2 bfloat16
   bool warm = false;        // P was set by mfa_set_ctrl: the next encode starts there
+  bool p_zero = false;      // P still holds the zeros mfa_create wrote (nothing has written it since)
   bool serial = false;      // every launch on `stream` (no auxiliary streams or tuner events)
   uint64_t noalloc_gen = 0; // nonzero: the workspace is the device's no-allocation array,
                             // claimed by this handle as generation noalloc_gen
