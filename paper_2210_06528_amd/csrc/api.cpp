@@ -255,18 +255,25 @@ hipError_t choose_fused21(Handle &h, const float *gf, bool *fused) {
 //                                     subdomains at once)
 //   P += (M_0 x M_1 x M_2) g         (local solves with lagged ghosts and the
 //                                     1/n_s combine, Section 2.3.2)
-hipError_t sweep_normal(Handle &h, const SlotTurn &turn) {
-  const int n0 = h.ax[0].n, n1 = h.ax[1].n, n2 = h.ax[2].n;
+// The residual g = c - A P of a sweep: the stencil kernel, or, when P = 0
+// (p_zero: the first sweep of a cold start), g = c (the stencil of zeros is
+// zero), which needs no stencil and no bookkeeping turn (both slot sets are
+// clear and no correction history exists yet).  Only the stencil kernel's
+// launches are timed as the residual class.
+template <typename TG>
+static hipError_t residual(Handle &h, TG *g, const SlotTurn &turn, bool p_zero) {
+  if (p_zero) return launch_resid_zero<TG>(h.stream, h.c, g, h.nctrl_total, h.slots);
+  TimeScope ts(h, MFA_K_RESID);
+  return launch_resid<TG>(h.stream, h.p, h.P, h.c, g, h.ax[0].d_acoef, h.ax[1].d_acoef, h.ax[2].d_acoef,
+                          h.ax[0].n, h.ax[1].n, h.ax[2].n, h.slots, turn, !h.serial);
+}
+
+hipError_t sweep_normal(Handle &h, const SlotTurn &turn, bool p_zero) {
   if (h.precision == MFA_PREC_MIXED_BF16 && mfma_ok(h)) {
     // residual in float64, rounded to FP32; correction on the matrix cores
     h.g_type = 1;
     float *gf = reinterpret_cast<float *>(h.g);
-    hipError_t e;
-    {
-      TimeScope ts(h, MFA_K_RESID);
-      e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                              h.ax[2].d_acoef, n0, n1, n2, h.slots, turn, !h.serial);
-    }
+    hipError_t e = residual<float>(h, gf, turn, p_zero);
     if (e != hipSuccess) return e;
     bool fused = false;
     if ((e = choose_fused21(h, gf, &fused)) != hipSuccess) return e;
@@ -301,21 +308,11 @@ hipError_t sweep_normal(Handle &h, const SlotTurn &turn) {
     h.g_type = low ? 1 : 0;
     if (low) {
       float *gf = reinterpret_cast<float *>(h.g);
-      hipError_t e;
-      {
-        TimeScope ts(h, MFA_K_RESID);
-        e = launch_resid<float>(h.stream, h.p, h.P, h.c, gf, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                                h.ax[2].d_acoef, n0, n1, n2, h.slots, turn, !h.serial);
-      }
+      hipError_t e = residual<float>(h, gf, turn, p_zero);
       if (e != hipSuccess) return e;
       return correct_bsolve<float>(h, gf);
     }
-    hipError_t e;
-    {
-      TimeScope ts(h, MFA_K_RESID);
-      e = launch_resid<double>(h.stream, h.p, h.P, h.c, h.g, h.ax[0].d_acoef, h.ax[1].d_acoef,
-                               h.ax[2].d_acoef, n0, n1, n2, h.slots, turn, !h.serial);
-    }
+    hipError_t e = residual<double>(h, h.g, turn, p_zero);
     if (e != hipSuccess) return e;
     return correct_bsolve<double>(h, h.g);
   }
@@ -922,6 +919,9 @@ static mfa_status do_sweep(Handle &h, bool metrics) {
   const int hidx = (h.sweep - 1 + kHist) % kHist;
   SlotTurn turn;
   hipError_t e = hipSuccess;
+  // P = 0 is known only for the first sweep of a cold-start encode
+  const bool p_zero = h.p_known_zero && h.sweep == 0;
+  h.p_known_zero = false;
   if (sweep_uses_resid_kernel(h)) {
     // the first sweep also clears its own set (both sets start cleared)
     if (h.sweep == 0 && (e = launch_zero_slots(h.stream, h.slot_base, 2 * (int)nset)) != hipSuccess)
@@ -940,7 +940,7 @@ static mfa_status do_sweep(Handle &h, bool metrics) {
       if (e != hipSuccess) return hip_fail(e, "metrics");
     }
   } else {
-    e = sweep_normal(h, turn);
+    e = sweep_normal(h, turn, p_zero);
     if (e != hipSuccess) return hip_fail(e, "sweep");
     if (metrics) {
       e = sweep_metrics(h);
@@ -998,6 +998,7 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
     hipError_t e = launch_fill(h.stream, h.P, h.nctrl_total, 0.0);
     if (e != hipSuccess) return hip_fail(e, "fill P");
   }
+  h.p_known_zero = !h.warm;
   h.warm = false;
   mfa_step_stats st{};
   bool converged = false;

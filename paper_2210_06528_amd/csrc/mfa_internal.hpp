@@ -137,6 +137,7 @@ struct Handle {
   int g_type = 0;           // element type of g: 0 float64, 1 float32, 2 bfloat16
   bool warm = false;        // P was set by mfa_set_ctrl: the next encode starts there
   bool p_zero = false;      // P still holds the zeros mfa_create wrote (nothing has written it since)
+  bool p_known_zero = false;  // P = 0 for the next sweep (cold start of an encode)
   bool serial = false;      // every launch on `stream` (no auxiliary streams or tuner events)
   uint64_t noalloc_gen = 0; // nonzero: the workspace is the device's no-allocation array,
                             // claimed by this handle as generation noalloc_gen
@@ -254,6 +255,9 @@ hipError_t launch_resid(hipStream_t st, int p, const double *Pc, const double *c
                         const double *A0, const double *A1, const double *A2, int n0, int n1, int n2,
                         unsigned long long *slots, const SlotTurn &turn = SlotTurn{},
                         bool may_tune = true);
+// the residual at P = 0: g = c and max |g| into slot kSlotNres of `slots`
+template <typename TG>
+hipError_t launch_resid_zero(hipStream_t st, const double *c, TG *g, int64_t n, unsigned long long *slots);
 template <typename TI, typename TO, typename TC>
 hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int axis, int n0, int n1,
                          int n2, int p, const Axis &X, int combine, unsigned long long *slots);

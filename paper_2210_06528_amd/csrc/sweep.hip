@@ -576,6 +576,24 @@ __global__ void __launch_bounds__(MAXF >= 64 ? 256 : 1024) k_bsolve_seg(const TI
   if (MODE == 1) slot_max_c(slots, kSlotMaxDP, dmax);
 }
 
+// The residual at P = 0 (the first sweep of a cold start): the stencil of
+// zeros is zero, so g = c exactly, and max |g| goes to the residual slot as
+// k_resid would put it.  Two values per thread and trip.
+template <typename TG>
+__global__ void __launch_bounds__(256) k_resid_zero(const double *__restrict__ c, TG *__restrict__ g,
+                                                   int64_t n, unsigned long long *slots) {
+  double nres = 0.0;
+  const int64_t stride = 2 * (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i < n; i += stride) {
+    const double v0 = c[i];
+    const double v1 = i + 1 < n ? c[i + 1] : 0.0;
+    g[i] = from_d<TG>(v0);
+    if (i + 1 < n) g[i + 1] = from_d<TG>(v1);
+    nres = fmax(nres, fmax(fabs(v0), fabs(v1)));
+  }
+  slot_max_c(slots, kSlotNres, nres);
+}
+
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // x-chunk of the residual stencil for at most `target` workgroups: the
@@ -778,6 +796,18 @@ hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int 
   }
   return hipGetLastError();
 }
+
+template <typename TG>
+hipError_t launch_resid_zero(hipStream_t st, const double *c, TG *g, int64_t n, unsigned long long *slots) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>(nblk((n + 1) / 2, 256), 4096);
+  k_resid_zero<TG><<<grid, 256, 0, st>>>(c, g, n, slots);
+  return hipGetLastError();
+}
+template hipError_t launch_resid_zero<double>(hipStream_t, const double *, double *, int64_t,
+                                              unsigned long long *);
+template hipError_t launch_resid_zero<float>(hipStream_t, const double *, float *, int64_t,
+                                             unsigned long long *);
 
 template hipError_t launch_resid<double>(hipStream_t, int, const double *, const double *, double *,
                                          const double *, const double *, const double *, int, int, int,
