@@ -486,6 +486,9 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
   constexpr int NT = (LYY * LXX + 255) / 256;
   __shared__ double tile[LYY][LXX + 1];
   __shared__ double sd1[TY][PP][PP];   // axis-1 rows: sd1[k1 - k1a][r][q]
+  // axis-0 rows of the chunk's planes, sd0[idx - k0a][r][q] (K0C <= 32),
+  // staged once instead of loaded from global memory in every plane step
+  __shared__ double sd0[32][PP][PP];
   const int tx = threadIdx.x & 63;
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int k2a = blockIdx.x * TX, k1a = blockIdx.y * TY;
@@ -498,6 +501,15 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
     int rowoff = 0;
     for (int rr = 0; rr < r; ++rr) rowoff += n1 - rr;
     sd1[yl][r][q] = (act1 && q <= r && k1 <= n1 - 1 - r) ? d1.val[(int64_t)(rowoff + k1) * d1.L + q] : 0.0;
+  }
+  for (int e = threadIdx.x; e < K0C * PP * PP; e += 256) {
+    const int il = e / (PP * PP), r = (e / PP) % PP, q = e % PP;
+    const int idx = k0a + il;
+    int rowoff = 0;
+    for (int rr = 0; rr < r; ++rr) rowoff += n0 - rr;
+    sd0[il][r][q] = (act0 && idx < k0b && q <= r && idx <= n0 - 1 - r)
+                        ? d0.val[(int64_t)(rowoff + idx) * d0.L + q]
+                        : 0.0;
   }
   // this thread's axis-2 coefficient rows (fixed k2)
   double dv2[PP][PP];
@@ -543,21 +555,10 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
     for (int u = 0; u < NT; ++u) buf[u] = base[toff[u]];
   };
   auto step = [&](double (&buf)[NT], bool &bin, int k0) {
-    // axis-0 rows of the plane whose window completes here (uniform)
+    // the plane whose axis-0 window completes here (uniform); its rows come
+    // from sd0 (written before the first barrier below)
     const int idx = k0 - H;
     const bool do0 = act0 && idx >= k0a && idx < k0b;
-    double dv0[PP][PP];
-    {
-      int rowoff = 0;
-#pragma unroll
-      for (int r = 0; r < PP; ++r) {
-        const bool okr = do0 && idx <= n0 - 1 - r;
-        const double *dv = d0.val + (int64_t)(rowoff + (okr ? idx : 0)) * d0.L;
-#pragma unroll
-        for (int q = 0; q <= r; ++q) dv0[r][q] = okr ? dv[q] : 0.0;
-        rowoff += n0 - r;
-      }
-    }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
@@ -601,12 +602,13 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
         }
       }
       if (do0) {
+        const int il = idx - k0a;
 #pragma unroll
         for (int r = 0; r < PP; ++r) {
           if (idx <= n0 - 1 - r) {
             double sum = 0.0;
 #pragma unroll
-            for (int q = 0; q <= r; ++q) sum += dv0[r][q] * win[j][q];
+            for (int q = 0; q <= r; ++q) sum += sd0[il][r][q] * win[j][q];
             mx[0][r] = fmax(mx[0][r], fabs(sum));
           }
         }

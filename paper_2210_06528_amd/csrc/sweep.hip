@@ -578,18 +578,35 @@ __global__ void __launch_bounds__(MAXF >= 64 ? 256 : 1024) k_bsolve_seg(const TI
 
 // The residual at P = 0 (the first sweep of a cold start): the stencil of
 // zeros is zero, so g = c exactly, and max |g| goes to the residual slot as
-// k_resid would put it.  Two values per thread and trip.
+// k_resid would put it.  Four values per thread and trip, 16-byte accesses
+// (c and g start on 16-byte boundaries: workspace arrays).
+template <typename TG>
+__device__ __forceinline__ void store4(TG *g, double a, double b, double c, double d);
+template <>
+__device__ __forceinline__ void store4<float>(float *g, double a, double b, double c, double d) {
+  *reinterpret_cast<float4 *>(g) = float4{(float)a, (float)b, (float)c, (float)d};
+}
+template <>
+__device__ __forceinline__ void store4<double>(double *g, double a, double b, double c, double d) {
+  reinterpret_cast<double2 *>(g)[0] = double2{a, b};
+  reinterpret_cast<double2 *>(g)[1] = double2{c, d};
+}
 template <typename TG>
 __global__ void __launch_bounds__(256) k_resid_zero(const double *__restrict__ c, TG *__restrict__ g,
                                                    int64_t n, unsigned long long *slots) {
   double nres = 0.0;
-  const int64_t stride = 2 * (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i < n; i += stride) {
-    const double v0 = c[i];
-    const double v1 = i + 1 < n ? c[i + 1] : 0.0;
-    g[i] = from_d<TG>(v0);
-    if (i + 1 < n) g[i + 1] = from_d<TG>(v1);
-    nres = fmax(nres, fmax(fabs(v0), fabs(v1)));
+  const int64_t n4 = n / 4, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < n4; i += stride) {
+    const double2 a = reinterpret_cast<const double2 *>(c)[2 * i];
+    const double2 b = reinterpret_cast<const double2 *>(c)[2 * i + 1];
+    store4<TG>(g + 4 * i, a.x, a.y, b.x, b.y);
+    nres = fmax(nres, fmax(fmax(fabs(a.x), fabs(a.y)), fmax(fabs(b.x), fabs(b.y))));
+  }
+  for (int64_t i = 4 * n4 + t0; i < n; i += stride) {
+    const double v = c[i];
+    g[i] = from_d<TG>(v);
+    nres = fmax(nres, fabs(v));
   }
   slot_max_c(slots, kSlotNres, nres);
 }
@@ -800,7 +817,9 @@ hipError_t launch_bsolve(hipStream_t st, const TI *in, TO *out, double *pc, int 
 template <typename TG>
 hipError_t launch_resid_zero(hipStream_t st, const double *c, TG *g, int64_t n, unsigned long long *slots) {
   if (n <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)std::min<int64_t>(nblk((n + 1) / 2, 256), 4096);
+  // four workgroups per CU: every wavefront ends with one atomic max on the
+  // slot's copies, so more workgroups only queue more atomics at L2
+  const unsigned grid = (unsigned)std::min<int64_t>(nblk((n + 3) / 4, 256), 1024);
   k_resid_zero<TG><<<grid, 256, 0, st>>>(c, g, n, slots);
   return hipGetLastError();
 }
