@@ -48,6 +48,25 @@ __device__ __forceinline__ void slot_max_m(unsigned long long *slots, int slot, 
   }
 }
 
+// The workgroup's max of v, one atomic on one copy of the slot: wavefront
+// maxima through LDS, then thread 0.  Every thread of the workgroup must
+// call it (it has a barrier).  One atomic per workgroup instead of one per
+// wavefront: the atomics on a slot's copies queue at L2, and at the end of a
+// kernel whose workgroups all finish together that queue is the kernel's tail.
+__device__ __forceinline__ void block_slot_max_m(unsigned long long *slots, int slot, double v) {
+  __shared__ double red[16];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int i = 1; i < nw; ++i) m = fmax(m, red[i]);
+    const unsigned copy = (blockIdx.x * 7u + blockIdx.y * 131u + blockIdx.z * 1031u) % kSlotCopies;
+    atomicMax(slots + (size_t)slot * kSlotCopies + copy, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 // Operands are split into two BF16 terms, x = hi + lo with hi = bf16(x) and
 // lo = bf16(x - hi) (about 16 significant bits together), and every product
 // accumulates hi*hi + hi*lo + lo*hi in FP32 ("bf16x3"): plain BF16 rounding of
@@ -358,7 +377,7 @@ __global__ void __launch_bounds__(256) k_mfma_axis0_add(const float *__restrict_
       }
     }
   }
-  slot_max_m(slots, kSlotMaxDP, dmax);
+  block_slot_max_m(slots, kSlotMaxDP, dmax);
 }
 
 // Contiguous axis: the array is [nlines][n] (FP32); workgroup = 16*nw lines

@@ -32,6 +32,25 @@ __device__ __forceinline__ void slot_max_c(unsigned long long *slots, int slot, 
   }
 }
 
+// The workgroup's max of v, one atomic on one copy of the slot: wavefront
+// maxima through LDS, then thread 0.  Every thread of the workgroup must
+// call it (it has a barrier).  One atomic per workgroup instead of one per
+// wavefront: the atomics on a slot's copies queue at L2, and at the end of a
+// kernel whose workgroups all finish together that queue is the kernel's tail.
+__device__ __forceinline__ void block_slot_max_c(unsigned long long *slots, int slot, double v) {
+  __shared__ double red[16];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int i = 1; i < nw; ++i) m = fmax(m, red[i]);
+    const unsigned copy = (blockIdx.x * 7u + blockIdx.y * 131u + blockIdx.z * 1031u) % kSlotCopies;
+    atomicMax(slots + (size_t)slot * kSlotCopies + copy, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ double to_d(T v) {
   return (double)v;
@@ -296,7 +315,7 @@ __global__ void __launch_bounds__(kRT, (P <= 4 ? 4 : 1)) k_resid(const double *_
     __syncthreads();
     yx(1, xs + npl - 1 - P, a0v, cv);
   }
-  slot_max_c(slots, kSlotNres, nres);
+  block_slot_max_c(slots, kSlotNres, nres);
 }
 
 // Line geometry of an axis pass on an (n0, n1, n2) array: `nlines` lines of
@@ -608,7 +627,7 @@ __global__ void __launch_bounds__(256) k_resid_zero(const double *__restrict__ c
     g[i] = from_d<TG>(v);
     nres = fmax(nres, fabs(v));
   }
-  slot_max_c(slots, kSlotNres, nres);
+  block_slot_max_c(slots, kSlotNres, nres);
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
