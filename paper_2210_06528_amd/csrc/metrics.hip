@@ -27,6 +27,24 @@ __device__ __forceinline__ void slot_max_w(unsigned long long *slots, int slot, 
   }
 }
 
+// The workgroup's max of v, one atomic on one copy of the slot (wavefront
+// maxima through LDS, then thread 0); every thread must call it.  One atomic
+// per workgroup instead of one per wavefront: the atomics on a slot's copies
+// queue at L2, a tail for kernels whose workgroups all finish together.
+__device__ __forceinline__ void block_slot_max_w(unsigned long long *slots, int slot, double v) {
+  __shared__ double red[16];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int i = 1; i < nw; ++i) m = fmax(m, red[i]);
+    const unsigned copy = (blockIdx.x * 7u + blockIdx.y * 131u + blockIdx.z * 1031u) % kSlotCopies;
+    atomicMax(slots + (size_t)slot * kSlotCopies + copy, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 __device__ __forceinline__ double tod(double v) { return v; }
 __device__ __forceinline__ double tod(float v) { return (double)v; }
 __device__ __forceinline__ double tod(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
@@ -149,7 +167,7 @@ __global__ void __launch_bounds__(256) k_jump_expand(const double *__restrict__ 
   } else {
     for (int i = threadIdx.x; i < nib; i += blockDim.x) mx = fmax(mx, fabs(V[i]));
   }
-  slot_max_w(slots, slot_base + row % p, mx);
+  block_slot_max_w(slots, slot_base + row % p, mx);
 }
 
 // 1-D: the interface rows themselves
@@ -624,12 +642,28 @@ __global__ void __launch_bounds__(256) k_deriv_scale_tiles(const double *__restr
     step(bufA, inA, k0);
     step(bufB, inB, k0 + 1);
   }
-  const int act[3] = {act0, act1, act2};
+  // the workgroup's maxima: wavefront maxima through LDS, then one atomic
+  // per (axis, order) on one slot copy (not one per wavefront)
+  __shared__ double red[4][3 * PP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int r = 0; r < PP; ++r)
-      if (act[a]) slot_max_w(slots, kSlotS + a * kMaxP + r, mx[a][r]);
+    for (int r = 0; r < PP; ++r) {
+      double v = mx[a][r];
+      for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+      if (lane == 0) red[wv][a * PP + r] = v;
+    }
+  __syncthreads();
+  const int act[3] = {act0, act1, act2};
+  if (threadIdx.x < 3 * PP && act[threadIdx.x / PP]) {
+    const int a = threadIdx.x / PP, r = threadIdx.x % PP;
+    double m = red[0][threadIdx.x];
+    for (int i = 1; i < 4; ++i) m = fmax(m, red[i][threadIdx.x]);
+    const unsigned copy = (blockIdx.x * 7u + blockIdx.y * 131u + blockIdx.z * 1031u) % kSlotCopies;
+    atomicMax(slots + (size_t)(kSlotS + a * kMaxP + r) * kSlotCopies + copy,
+              (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
