@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(256) k_mfma_strided(const float *__restrict__ 
   __syncthreads();
   double dmax = 0.0;
   strided_apply<MODE>(Thi, Tlo, ld, out, pc, n, inner, npad, o, i0, Mhi, Mlo, klo, knc, dmax);
-  if (MODE == 1) slot_max_m(slots, kSlotMaxDP, dmax);
+  if (MODE == 1) block_slot_max_m(slots, kSlotMaxDP, dmax);
 }
 
 // Axis-0 pass that adds into the control points (outer = 1), for n <= 64 *
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(256) k_mfma_contig(const float *__restrict__ i
       }
     }
   }
-  if (MODE == 1) slot_max_m(slots, kSlotMaxDP, dmax);
+  if (MODE == 1) block_slot_max_m(slots, kSlotMaxDP, dmax);
 }
 
 // Axes 2 and 1 of the correction in one pass (mode 0): a workgroup takes one

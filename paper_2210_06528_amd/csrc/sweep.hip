@@ -592,7 +592,7 @@ __global__ void __launch_bounds__(MAXF >= 64 ? 256 : 1024) k_bsolve_seg(const TI
       }
     }
   }
-  if (MODE == 1) slot_max_c(slots, kSlotMaxDP, dmax);
+  if (MODE == 1) block_slot_max_c(slots, kSlotMaxDP, dmax);
 }
 
 // The residual at P = 0 (the first sweep of a cold start): the stencil of
