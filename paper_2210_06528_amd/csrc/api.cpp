@@ -1014,6 +1014,18 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
   // the tolerance after log(tol / J) / log(rate) more sweeps, the rate taken
   // from the corrections of sweeps k-2 .. k.  The first check comes at sweep
   // 6, after the transient.
+  //
+  // The count is rounded up, except for the prediction made at the first
+  // check when an axis has four or more subdomains: there the contraction
+  // is still speeding up at sweep 6 (a correction crosses one subdomain per
+  // sweep, so the slowest error components take longer to form), the rate
+  // from sweeps 4..6 is slower than the one that follows, and the count is
+  // rounded down.  With at most two subdomains per axis the rate is steady
+  // by then and the rounded-up count is the crossing itself.
+  int bmax = 1;
+  for (int a = 0; a < 3; ++a)
+    if (h.ax[a].active) bmax = std::max(bmax, h.ax[a].B);
+  bool first_prediction = true;
   int next_check = jump_tol > 0.0 ? (check_every > 0 ? check_every : 6) : max_sweeps;
   for (int k = 1; k <= max_sweeps; ++k) {
     const bool check = k == next_check || k == max_sweeps;
@@ -1045,9 +1057,11 @@ mfa_status mfa_encode(mfa_handle *H, const void *q_dev, mfa_dtype q_dtype, int32
         if (d2 > 0.0 && d0 > 0.0 && d0 < d2 && jm > 0.0) {
           const double rate = std::sqrt(d0 / d2);
           const double need = std::log(jump_tol / jm) / std::log(rate);
-          stride = (int)std::min(32.0, std::max(1.0, std::ceil(need)));
+          const double n = first_prediction && bmax >= 4 ? std::floor(need) : std::ceil(need);
+          stride = (int)std::min(32.0, std::max(1.0, n));
         }
       }
+      first_prediction = false;
       next_check = k + stride;
     }
   }

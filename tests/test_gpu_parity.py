@@ -280,6 +280,23 @@ def test_predicted_check_schedule_stops_at_or_just_after_the_crossing(precision,
     assert len(hist) <= st["sweep"] <= len(hist) + 3, (st["sweep"], len(hist))
 
 
+@pytest.mark.parametrize("blocks", [2, 5])
+def test_predicted_check_schedule_bounds_with_few_and_many_blocks(blocks):
+    """The first prediction is rounded up with at most two subdomains per
+    axis and rounded down from four on; either way the encode stops only
+    below the tolerance and within a few sweeps of the oracle's crossing."""
+    w = W.Workload(f"2d-spectral-{blocks}x{blocks}", (256, 256), 3, [W.even_sizes(32, blocks)] * 2, 2,
+                   jump_tol=1e-8, dtype="f64", seed=3)
+    w.extra["kmax"] = 6
+    S = _oracle(w)
+    Q = W.make_field(w)
+    _, hist = schwarz.encode(S, Q, 60, jump_tol=w.jump_tol)
+    enc = _enc(w)
+    st = enc.encode(torch.from_numpy(Q).cuda(), 60, w.jump_tol, 0)
+    assert st["converged"] and max(st["jump"]) < w.jump_tol
+    assert len(hist) <= st["sweep"] <= len(hist) + 3, (st["sweep"], len(hist))
+
+
 @pytest.mark.parametrize("name", ["1d", "2d", "3d", "3d-p4"])
 def test_decode_points_match_oracle(name):
     """Decode at arbitrary parameter points: random points, every knot exactly
