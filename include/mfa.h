@@ -207,8 +207,10 @@ mfa_status mfa_create_noalloc(const mfa_problem *prob, void *hip_stream, mfa_han
  * sweep 6; after a check at sweep k with largest jump J the next comes
  * ceil(log(jump_tol / J) / log(rho)) sweeps later (clamped to 1..32), rho =
  * sqrt(max|dP_k| / max|dP_{k-2}|) the decay of the corrections every sweep
- * records (4 sweeps later when no decay is seen); so the stop may come a few
- * sweeps after the first sweep that met the tolerance.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
+ * records (4 sweeps later when no decay is seen).  The count predicted at
+ * the first check is rounded down instead when an axis has four or more
+ * subdomains (the decay is still speeding up there at sweep 6).  The stop
+ * may come a few sweeps after the first sweep that met the tolerance.  jump_tol <= 0 runs exactly max_sweeps sweeps.  `last` (may be
  * NULL) receives the statistics of the last checked sweep.  Returns
  * MFA_ENOTCONV if the tolerance was not met (the control points are still
  * the last iterate) or a non-finite value appeared.                         */
